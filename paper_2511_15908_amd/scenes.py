@@ -1,0 +1,434 @@
+"""Seeded synthetic scenes for the SPH hot path.
+
+This module only builds inputs: particle positions and velocities on lattices,
+boundary samplings of tanks and bodies, soft-body spring tables and the pose
+trajectories that drive kinematic bodies.  It holds none of the method's
+arithmetic (no kernel, no density, no force, no neighbour search), so both the
+HIP library and the CPU oracle can consume the same arrays.
+
+Geometry follows the paper's scenario types (Sec. 3.2 unified particles, Sec.
+3.3 grabbed rigid body, Table 1 scenes): a static boundary tank, fluid filled
+on a lattice, a kinematic rigid body sampled as boundary particles, and a
+mass-spring soft cube (Sec. 3.2, Alg. 2 spring kernel).
+
+Randomness: SplitMix64 (Steele, Lea and Flood 2014; Vigna's reference
+constants), u = (z >> 11) * 2^-53, one stream per (scene seed, purpose).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+FLUID, SOFT, BOUNDARY = 0, 1, 2
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+# purpose ids for independent streams
+P_JITTER, P_PHASE, P_WALK, P_PERTURB, P_BATCH = 1, 2, 3, 4, 5
+
+
+class SplitMix64:
+    """Counter-based SplitMix64 stream: value k is mix(seed + (k+1)*gamma)."""
+
+    def __init__(self, seed: int, purpose: int = 0):
+        s = (int(seed) * 1000003 + int(purpose) * 7919 + 0x5EED) & 0xFFFFFFFFFFFFFFFF
+        self.state = np.uint64(s)
+        self.count = 0
+
+    def next_u64(self, n: int) -> np.ndarray:
+        k = np.arange(self.count + 1, self.count + 1 + n, dtype=np.uint64)
+        self.count += n
+        with np.errstate(over="ignore"):
+            z = self.state + k * _GAMMA
+            z = (z ^ (z >> np.uint64(30))) * _M1
+            z = (z ^ (z >> np.uint64(27))) * _M2
+            z = z ^ (z >> np.uint64(31))
+        return z
+
+    def uniform(self, n: int) -> np.ndarray:
+        return (self.next_u64(n) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+    def normal(self, n: int) -> np.ndarray:
+        u1 = self.uniform(n)
+        u2 = self.uniform(n)
+        return np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * math.pi * u2)
+
+
+@dataclass
+class Scene:
+    name: str
+    precision: str                 # "f32" | "f64"
+    params: dict                   # h, rho0, k_pressure, nu, gravity, dt, domain_lo/hi, flags, smoothing_window
+    x: np.ndarray                  # (n,3) float64
+    v: np.ndarray                  # (n,3) float64
+    mass: np.ndarray               # (n,) float64 (fluid/soft; ignored for boundary)
+    type: np.ndarray               # (n,) uint8
+    object: np.ndarray             # (n,) int32, -1 for fluid/soft
+    object_kinematic: np.ndarray   # (n_objects,) uint8
+    object_pose0: np.ndarray       # (n_objects,7) float64: c[3], q[4] (w,x,y,z)
+    spring_ij: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.uint32))
+    spring_L0: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    spring_k: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    spring_c: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    spacing: float = 0.0
+    info: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    def counts(self) -> dict:
+        return {
+            "fluid": int((self.type == FLUID).sum()),
+            "soft": int((self.type == SOFT).sum()),
+            "boundary": int((self.type == BOUNDARY).sum()),
+            "all": self.n,
+        }
+
+
+# --------------------------------------------------------------------------
+# lattice samplers
+# --------------------------------------------------------------------------
+
+def _grid(i0, i1, j0, j1, k0, k1):
+    i, j, k = np.meshgrid(np.arange(i0, i1 + 1), np.arange(j0, j1 + 1),
+                          np.arange(k0, k1 + 1), indexing="ij")
+    ijk = np.stack([i.ravel(), j.ravel(), k.ravel()], 1)
+    # lexicographic (k, j, i): k slowest
+    order = np.lexsort((ijk[:, 0], ijk[:, 1], ijk[:, 2]))
+    return ijk[order]
+
+
+def tank_sites(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Open-top single-layer tank on lattice sites: floor k=0 over
+    i in 0..nx, j in 0..ny; walls k in 1..nz on the perimeter."""
+    floor = _grid(0, nx, 0, ny, 0, 0)
+    walls = _grid(0, nx, 0, ny, 1, nz)
+    per = (walls[:, 0] == 0) | (walls[:, 0] == nx) | (walls[:, 1] == 0) | (walls[:, 1] == ny)
+    return np.concatenate([floor, walls[per]], 0)
+
+
+def block_surface_sites(i0, i1, j0, j1, k0, k1) -> np.ndarray:
+    g = _grid(i0, i1, j0, j1, k0, k1)
+    surf = ((g[:, 0] == i0) | (g[:, 0] == i1) | (g[:, 1] == j0) | (g[:, 1] == j1)
+            | (g[:, 2] == k0) | (g[:, 2] == k1))
+    return g[surf]
+
+
+def fibonacci_sphere(n: int, r: float, c) -> np.ndarray:
+    k = np.arange(n, dtype=np.float64)
+    z = 1.0 - (2.0 * k + 1.0) / n
+    rho = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = k * math.pi * (3.0 - math.sqrt(5.0))
+    return np.asarray(c, np.float64) + r * np.stack([rho * np.cos(phi), rho * np.sin(phi), z], 1)
+
+
+def fill_to_count(n_fluid, i_range, j_range, s, occupied: set, exclude_fn=None, k_start=1):
+    """Take tank-interior lattice sites in (k, j, i) order, skipping occupied
+    sites and sites for which exclude_fn(xyz) is true, until n_fluid are placed."""
+    out = []
+    need = n_fluid
+    k = k_start
+    ii, jj = np.meshgrid(np.arange(i_range[0], i_range[1] + 1),
+                         np.arange(j_range[0], j_range[1] + 1), indexing="xy")
+    layer_ij = np.stack([ii.ravel(), jj.ravel()], 1)      # j slowest, i fastest
+    while need > 0:
+        ijk = np.concatenate([layer_ij, np.full((layer_ij.shape[0], 1), k)], 1)
+        if occupied:
+            keep = np.array([tuple(t) not in occupied for t in ijk.tolist()], bool)
+            ijk = ijk[keep]
+        if exclude_fn is not None and ijk.shape[0]:
+            ijk = ijk[~exclude_fn(ijk.astype(np.float64) * s)]
+        take = ijk[:need]
+        out.append(take)
+        need -= take.shape[0]
+        k += 1
+        if k > 100000:
+            raise RuntimeError("fill_to_count did not converge")
+    return np.concatenate(out, 0)
+
+
+def soft_cube_springs(ijk: np.ndarray):
+    """Springs between lattice neighbours of a solid block: the 6 axis and 12
+    face-diagonal neighbours (each unordered pair once).  Returns (m,2) index
+    pairs into ijk."""
+    index = {tuple(t): n for n, t in enumerate(ijk.tolist())}
+    offs = []
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        offs.append(tuple(e))
+    for a in range(3):
+        for b in range(a + 1, 3):
+            for sb in (1, -1):
+                e = [0, 0, 0]
+                e[a] = 1
+                e[b] = sb
+                offs.append(tuple(e))
+    pairs = []
+    for n, t in enumerate(ijk.tolist()):
+        for o in offs:
+            m = index.get((t[0] + o[0], t[1] + o[1], t[2] + o[2]))
+            if m is not None:
+                pairs.append((n, m))
+    return np.asarray(pairs, np.int64).reshape(-1, 2)
+
+
+def _params(h, dt, lo, hi, precision, k_pressure=250.0, nu=1e-3, rho0=1000.0,
+            flags=0, smoothing_window=20):
+    return {
+        "h": float(h), "rho0": float(rho0), "k_pressure": float(k_pressure),
+        "nu": float(nu), "gravity": (0.0, 0.0, -9.81), "dt": float(dt),
+        "domain_lo": tuple(float(a) for a in lo), "domain_hi": tuple(float(a) for a in hi),
+        "flags": int(flags), "smoothing_window": int(smoothing_window),
+        "precision": precision,
+    }
+
+
+def _assemble(name, precision, params, s, parts, kin, poses, springs=None, info=None):
+    """parts: list of (xyz (m,3), type, object, mass)"""
+    xs, ts, os_, ms = [], [], [], []
+    for xyz, ty, ob, m in parts:
+        xs.append(np.asarray(xyz, np.float64))
+        ts.append(np.full(len(xyz), ty, np.uint8))
+        os_.append(np.full(len(xyz), ob, np.int32))
+        ms.append(np.full(len(xyz), m, np.float64))
+    x = np.concatenate(xs, 0)
+    sc = Scene(name=name, precision=precision, params=params, x=x,
+               v=np.zeros_like(x), mass=np.concatenate(ms), type=np.concatenate(ts),
+               object=np.concatenate(os_), object_kinematic=np.asarray(kin, np.uint8),
+               object_pose0=np.asarray(poses, np.float64).reshape(-1, 7), spacing=s,
+               info=dict(info or {}))
+    if springs is not None:
+        ij, L0, ks, cs = springs
+        sc.spring_ij = np.asarray(ij, np.uint32).reshape(-1, 2)
+        sc.spring_L0 = np.asarray(L0, np.float64)
+        sc.spring_k = np.asarray(ks, np.float64)
+        sc.spring_c = np.asarray(cs, np.float64)
+    return sc
+
+
+# --------------------------------------------------------------------------
+# the workloads
+# --------------------------------------------------------------------------
+
+def dam_break(seed: int = 1, precision: str = "f64") -> Scene:
+    """Dam break, 8,000 fluid particles (20^3 lattice, spacing 0.02 m, h = 2
+    spacing), an open tank and a fixed 0.1 m cube, 5,960 boundary particles,
+    dt = 1e-3 s, +-1e-4 m seeded jitter."""
+    s, h, dt = 0.02, 0.04, 1e-3
+    fl = _grid(1, 20, 1, 20, 1, 20).astype(np.float64) * s
+    rng = SplitMix64(seed, P_JITTER)
+    fl = fl + (2.0 * rng.uniform(fl.size).reshape(fl.shape) - 1.0) * 1e-4
+    tank = tank_sites(50, 21, 33).astype(np.float64) * s
+    cube = block_surface_sites(22, 27, 8, 13, 1, 6).astype(np.float64) * s
+    c_cube = np.array([24.5, 10.5, 3.5]) * s
+    m = 1000.0 * s ** 3
+    lo = (-0.5 * s, -0.5 * s, -0.5 * s)
+    hi = (50.5 * s, 21.5 * s, 40.5 * s)
+    params = _params(h, dt, lo, hi, precision)
+    poses = [[0, 0, 0, 1, 0, 0, 0], list(c_cube) + [1, 0, 0, 0]]
+    return _assemble("dam_break_8k", precision, params, s,
+                     [(fl, FLUID, -1, m), (tank, BOUNDARY, 0, 0.0), (cube, BOUNDARY, 1, 0.0)],
+                     kin=[0, 1], poses=poses, info={"steps": 100, "body": 1})
+
+
+def stirring_tank(seed: int = 2, n_fluid: int = 250_000, precision: str = "f32") -> Scene:
+    """Stirring tank: tank of about 1.01 x 0.51 x 0.6 m, a 4 x 25 x 40 paddle
+    (4,000 kinematic boundary particles) on a seeded 1 Hz, 0.1 m sinusoid,
+    n_fluid fluid particles filled layer by layer, dt = 5e-4 s."""
+    s, h, dt = 0.01, 0.02, 5e-4
+    tank = tank_sites(101, 51, 60).astype(np.float64) * s
+    pad_ijk = _grid(49, 52, 13, 37, 6, 45)
+    occ = set(map(tuple, pad_ijk.tolist()))
+    fl = fill_to_count(n_fluid, (1, 100), (1, 50), s, occ).astype(np.float64) * s
+    pad = pad_ijk.astype(np.float64) * s
+    c0 = pad.mean(0)
+    m = 1000.0 * s ** 3
+    phase = 2.0 * math.pi * float(SplitMix64(seed, P_PHASE).uniform(1)[0])
+    lo = (-0.5 * s, -0.5 * s, -0.5 * s)
+    hi = (101.5 * s, 51.5 * s, 70.5 * s)
+    params = _params(h, dt, lo, hi, precision)
+    poses = [[0, 0, 0, 1, 0, 0, 0], list(c0) + [1, 0, 0, 0]]
+    return _assemble(f"stirring_tank_{n_fluid}", precision, params, s,
+                     [(fl, FLUID, -1, m), (tank, BOUNDARY, 0, 0.0), (pad, BOUNDARY, 1, 0.0)],
+                     kin=[0, 1], poses=poses,
+                     info={"body": 1, "phase": phase, "amplitude": 0.1, "freq": 1.0, "c0": c0})
+
+
+def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") -> Scene:
+    """Coupled fluid + soft + rigid: tank 0.505 x 0.505 x 0.6 m, a 20^3 soft
+    cube (66,120 springs, k_s = 100 N/m), a grabbed sphere of radius 0.05 m as
+    three Fibonacci shells (3,079 particles), n_fluid fluid particles,
+    spacing 5 mm, h = 1 cm, dt = 2.5e-4 s."""
+    s, h, dt = 0.005, 0.01, 2.5e-4
+    tank = tank_sites(101, 101, 120).astype(np.float64) * s
+    soft_ijk = _grid(11, 30, 41, 60, 1, 20)
+    occ = set(map(tuple, soft_ijk.tolist()))
+    c0 = np.array([0.30, 0.25, 0.25])
+    R = 0.05
+    shells = [fibonacci_sphere(int(round(4 * math.pi * r * r / (s * s))), r, c0)
+              for r in (R, R - s, R - 2 * s)]
+    sph = np.concatenate(shells, 0)
+
+    def excl(xyz):
+        return np.linalg.norm(xyz - c0, axis=1) < R + 0.5 * s
+
+    fl = fill_to_count(n_fluid, (1, 100), (1, 100), s, occ, excl).astype(np.float64) * s
+    soft = soft_ijk.astype(np.float64) * s
+    m = 1000.0 * s ** 3
+    ij = soft_cube_springs(soft_ijk)
+    L0 = np.linalg.norm(soft[ij[:, 0]] - soft[ij[:, 1]], axis=1)
+    ks = 100.0
+    cs = 0.1 * 2.0 * math.sqrt(ks * m)
+    nf = fl.shape[0]
+    ij_glob = ij + nf                       # soft particles follow the fluid
+    lo = (-0.5 * s, -0.5 * s, -0.5 * s)
+    hi = (101.5 * s, 101.5 * s, 130.5 * s)
+    params = _params(h, dt, lo, hi, precision)
+    poses = [[0, 0, 0, 1, 0, 0, 0], list(c0) + [1, 0, 0, 0]]
+    return _assemble(f"coupled_{n_fluid}", precision, params, s,
+                     [(fl, FLUID, -1, m), (soft, SOFT, -1, m), (tank, BOUNDARY, 0, 0.0),
+                      (sph, BOUNDARY, 1, 0.0)],
+                     kin=[0, 1], poses=poses,
+                     springs=(ij_glob, L0, np.full(len(L0), ks), np.full(len(L0), cs)),
+                     info={"body": 1, "radius": R, "c0": c0})
+
+
+def small_scene(seed: int = 11, nf=(14, 9, 8), precision: str = "f32", with_soft=True,
+                with_body=True, perturb=True, n_tank=(24, 14, 16), spacing=0.02) -> Scene:
+    """A small coupled scene for parity tests: a tank, a fluid block of
+    nf[0] x nf[1] x nf[2] sites, optionally a 4^3 soft cube with springs and a
+    kinematic cube, with seeded velocity and position perturbations."""
+    s = spacing
+    h = 2 * s
+    nx, ny, nz = n_tank
+    tank = tank_sites(nx, ny, nz).astype(np.float64) * s
+    occ = set()
+    parts = []
+    soft_ijk = None
+    if with_soft:
+        soft_ijk = _grid(nx - 6, nx - 3, 2, 5, 1, 4)
+        occ |= set(map(tuple, soft_ijk.tolist()))
+    body_ijk = None
+    if with_body:
+        body_ijk = block_surface_sites(nx - 9, nx - 7, ny - 5, ny - 3, 2, 4)
+        occ |= set(map(tuple, _grid(nx - 9, nx - 7, ny - 5, ny - 3, 2, 4).tolist()))
+    fl_ijk = _grid(1, nf[0], 1, nf[1], 1, nf[2])
+    fl_ijk = np.asarray([t for t in fl_ijk.tolist() if tuple(t) not in occ], np.int64).reshape(-1, 3)
+    fl = fl_ijk.astype(np.float64) * s
+    m = 1000.0 * s ** 3
+    rng = SplitMix64(seed, P_PERTURB)
+    if perturb:
+        fl = fl + (2.0 * rng.uniform(fl.size).reshape(fl.shape) - 1.0) * 0.15 * s
+    parts.append((fl, FLUID, -1, m))
+    springs = None
+    nfl = fl.shape[0]
+    if with_soft:
+        soft = soft_ijk.astype(np.float64) * s
+        if perturb:
+            soft = soft + (2.0 * rng.uniform(soft.size).reshape(soft.shape) - 1.0) * 0.05 * s
+        parts.append((soft, SOFT, -1, m))
+        ij = soft_cube_springs(soft_ijk)
+        L0 = np.linalg.norm((soft_ijk[ij[:, 0]] - soft_ijk[ij[:, 1]]).astype(np.float64) * s, axis=1)
+        ks = 0.4 * 5e4 * s
+        springs = (ij + nfl, L0, np.full(len(L0), ks),
+                   np.full(len(L0), 0.1 * 2.0 * math.sqrt(ks * m)))
+    parts.append((tank, BOUNDARY, 0, 0.0))
+    kin = [0]
+    poses = [[0, 0, 0, 1, 0, 0, 0]]
+    if with_body:
+        body = body_ijk.astype(np.float64) * s
+        parts.append((body, BOUNDARY, 1, 0.0))
+        kin.append(1)
+        poses.append(list(body.mean(0)) + [1, 0, 0, 0])
+    lo = (-0.5 * s, -0.5 * s, -0.5 * s)
+    hi = ((nx + 0.5) * s, (ny + 0.5) * s, (nz + 6.5) * s)
+    params = _params(h, 1e-3 * (s / 0.02), lo, hi, precision)
+    sc = _assemble(f"small_{seed}", precision, params, s, parts, kin=kin, poses=poses,
+                   springs=springs, info={"body": 1 if with_body else None})
+    if perturb:
+        mov = sc.type != BOUNDARY
+        sc.v[mov] = (2.0 * rng.uniform(3 * int(mov.sum())).reshape(-1, 3) - 1.0) * 0.3
+    return sc
+
+
+# --------------------------------------------------------------------------
+# pose trajectories of kinematic bodies (inputs, not method arithmetic)
+# --------------------------------------------------------------------------
+
+def quat_normalize(q):
+    q = np.asarray(q, np.float64)
+    return q / np.linalg.norm(q)
+
+
+def quat_mul(a, b):
+    aw, ax, ay, az = a
+    bw, bx, by, bz = b
+    return np.array([aw * bw - ax * bx - ay * by - az * bz,
+                     aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw])
+
+
+def stirring_pose(scene: Scene, t: float):
+    """Paddle pose at time t: c = c0 + A[sin(2 pi f t + phi) - sin(phi)] e_x."""
+    A, f, ph = scene.info["amplitude"], scene.info["freq"], scene.info["phase"]
+    c0 = np.asarray(scene.info["c0"], np.float64)
+    c = c0 + np.array([A * (math.sin(2 * math.pi * f * t + ph) - math.sin(ph)), 0.0, 0.0])
+    v = np.array([A * 2 * math.pi * f * math.cos(2 * math.pi * f * t + ph), 0.0, 0.0])
+    return c, np.array([1.0, 0, 0, 0]), v, np.zeros(3)
+
+
+def random_walk(seed: int, n_ticks: int, c0, tick=1e-3, box_lo=(0.12, 0.12, 0.12),
+                box_hi=(0.43, 0.38, 0.40), sig_v=0.028, sig_w=0.141, decay=0.99):
+    """Ornstein-Uhlenbeck random walk of a body pose sampled every `tick`
+    seconds: v <- decay v + N(0, sig_v^2) per axis, w likewise; the centre is
+    reflected at the box.  Returns arrays c, q, v, w of shape (n_ticks, .)."""
+    rng = SplitMix64(seed, P_WALK)
+    c = np.asarray(c0, np.float64).copy()
+    q = np.array([1.0, 0, 0, 0])
+    v = np.zeros(3)
+    w = np.zeros(3)
+    lo, hi = np.asarray(box_lo), np.asarray(box_hi)
+    C, Q, V, W = (np.zeros((n_ticks, 3)), np.zeros((n_ticks, 4)),
+                  np.zeros((n_ticks, 3)), np.zeros((n_ticks, 3)))
+    for t in range(n_ticks):
+        C[t], Q[t], V[t], W[t] = c, q, v, w
+        nz = rng.normal(6)
+        v = decay * v + sig_v * nz[:3]
+        w = decay * w + sig_w * nz[3:]
+        c = c + tick * v
+        for a in range(3):
+            if c[a] < lo[a]:
+                c[a] = 2 * lo[a] - c[a]
+                v[a] = -v[a]
+            elif c[a] > hi[a]:
+                c[a] = 2 * hi[a] - c[a]
+                v[a] = -v[a]
+        q = quat_normalize(q + 0.5 * tick * quat_mul(np.array([0.0, *w]), q))
+    return C, Q, V, W
+
+
+def random_pose_velocity(seed: int, c0, vmax=0.3, wmax=2.0):
+    """A seeded rotation and rigid velocity for parity tests."""
+    rng = SplitMix64(seed, P_PERTURB + 100)
+    u = rng.uniform(10)
+    axis = u[0:3] - 0.5
+    axis = axis / np.linalg.norm(axis)
+    ang = (u[3] - 0.5) * 0.6
+    q = np.array([math.cos(ang / 2), *(math.sin(ang / 2) * axis)])
+    v = (2 * u[4:7] - 1) * vmax
+    w = (2 * u[7:10] - 1) * wmax
+    return np.asarray(c0, np.float64), q, v, w
+
+
+WORKLOADS = {
+    "dam_break": dam_break,
+    "stirring_tank": stirring_tank,
+    "coupled_1m": coupled_1m,
+}

@@ -1,0 +1,359 @@
+"""Pins of the CPU oracle against what the paper's definitions and plain
+mathematics fix (no GPU).
+
+Each test names the passage it pins.  Values under tests/golden/ are
+regression anchors written by tests/golden/make_pins.py from the oracle; the
+closed-form bounds next to them are the actual pins.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lattice_pins.json")))
+
+
+# ---------------------------------------------------------------- kernel (Eq. kernel)
+
+@pytest.mark.parametrize("h", [0.01, 0.04, 1.0])
+def test_kernel_partition_of_unity(orc, h):
+    """int W dV = 1 fixes alpha_3 = 3/(2 pi h^3) and both spline pieces."""
+    r = np.linspace(0.0, 2.0 * h, 200001)
+    w = np.array([orc.W(ri, h) for ri in r[::10]])
+    rr = r[::10]
+    integral = np.trapezoid(4 * math.pi * rr ** 2 * w, rr)
+    assert abs(integral - 1.0) < 1e-8
+
+
+def test_kernel_values_and_continuity(orc):
+    h = 0.04
+    assert abs(orc.W(0.0, h) * h ** 3 - 1.0 / math.pi) < 1e-15      # alpha_3 * 2/3
+    eps = 1e-12
+    assert abs(orc.W(h - eps, h) - orc.W(h + eps, h)) < 1e-6 * orc.W(h, h)
+    assert orc.W(2 * h, h) == 0.0 and orc.W(3 * h, h) == 0.0
+    assert orc.W(h, h) * h ** 3 == pytest.approx(1.0 / (4 * math.pi), rel=1e-14)  # alpha/6
+    assert orc.dWdr(0.0, h) == 0.0
+    assert orc.dWdr(2 * h, h) == 0.0
+
+
+def test_kernel_derivative_is_derivative(orc):
+    h = 0.04
+    for q in [0.1, 0.5, 0.9, 1.1, 1.5, 1.9]:
+        r = q * h
+        d = 1e-7 * h
+        fd = (orc.W(r + d, h) - orc.W(r - d, h)) / (2 * d)
+        assert orc.dWdr(r, h) == pytest.approx(fd, rel=1e-6)
+
+
+def test_kernel_gradient_moment(orc):
+    """int r dW/dr dV = -3 int W dV = -3 (integration by parts)."""
+    h = 0.5
+    r = np.linspace(0, 2 * h, 40001)
+    d = np.array([orc.dWdr(x, h) for x in r])
+    assert np.trapezoid(4 * math.pi * r ** 3 * d, r) == pytest.approx(-3.0, abs=1e-7)
+
+
+# ---------------------------------------------------------------- lattice sums
+
+def test_lattice_rest_density(orc):
+    """Interior density of a regular lattice with m = rho0 s^3 is rho0 up to
+    the kernel's aliasing error (Poisson summation): |rho/rho0 - 1| < 1e-4."""
+    v = GOLD["lattice_density_over_rho0"]["value"]
+    assert abs(v - 1.0) < 1e-4
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "mp", os.path.join(os.path.dirname(__file__), "golden", "make_pins.py"))
+    mp = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mp)
+    rho, cnt = mp.lattice_density()
+    assert rho == pytest.approx(v, rel=1e-13)
+    # 251 lattice points strictly inside the sphere of radius 4 (in units of s)
+    brute = sum(1 for i in range(-4, 5) for j in range(-4, 5) for k in range(-4, 5)
+                if i * i + j * j + k * k < 16)
+    assert cnt == brute == GOLD["lattice_neighbors_incl_self"]["value"]
+
+
+def _mp():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "mp", os.path.join(os.path.dirname(__file__), "golden", "make_pins.py"))
+    mp = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mp)
+    return mp
+
+
+def test_pressure_gradient_consistency(orc):
+    """Linear p on a lattice: pressure force = -G V grad p with G -> 1 in the
+    continuum (a wrong sign, a missing p_j term or a transposed gradient fails)."""
+    mp = _mp()
+    G = mp.gradient_factor()
+    assert abs(G - 1.0) < 1e-4
+    assert G == pytest.approx(GOLD["gradient_factor_G"]["value"], rel=1e-12)
+
+
+def test_uniform_pressure_zero_force(orc):
+    mp = _mp()
+    x, c = mp.lattice()
+    n = x.shape[0]
+    P = mp.params()
+    mass = np.full(n, 1000.0 * mp.S ** 3)
+    f = orc.forces(P, "f64", x, np.zeros_like(x), mass, np.zeros(n, np.uint8), np.zeros(n),
+                   np.full(n, 1000.0), np.full(n, 77.0), None, [c])
+    scale = mass[0] ** 2 * 2 * 77.0 / 1e6 * 251 / mp.H ** 4
+    assert np.abs(f).max() < 1e-13 * scale
+
+
+def test_viscosity_laplacian(orc):
+    """v = (x^2,0,0): Brookshaw form gives lap v_x -> 2 (eps biases it by 1 %)."""
+    mp = _mp()
+    B = mp.brookshaw_sum()
+    assert abs(B - 2.0) < 0.025
+    assert B == pytest.approx(GOLD["brookshaw_sum_B"]["value"], rel=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "linear"])
+def test_viscosity_zero_for_affine_velocity(orc, kind):
+    mp = _mp()
+    x, c = mp.lattice()
+    n = x.shape[0]
+    P = mp.params(nu=1.0)
+    mass = np.full(n, 1000.0 * mp.S ** 3)
+    v = np.zeros_like(x)
+    v[:] = [0.3, -0.2, 0.1]
+    if kind == "linear":
+        v[:, 0] += 0.7 * x[:, 1] - 0.4 * x[:, 2]
+    f = orc.forces(P, "f64", x, v, mass, np.zeros(n, np.uint8), np.zeros(n), np.full(n, 1000.0),
+                   np.zeros(n), None, [c])
+    if kind == "uniform":
+        assert np.all(f == 0.0)
+    else:
+        assert np.abs(f).max() < 1e-12 * mass[0] * 1.0 * 1.0 / mp.S ** 2
+
+
+def test_flat_wall_boundary_volume(orc):
+    """psi_b of a flat single-layer wall: the in-plane kernel sum approximates
+    (1/s^2) * 2 pi int W(r) r dr, so V_b ~ s^2 / (2 pi int W r dr)."""
+    mp = _mp()
+    vb = mp.flat_wall_volume()
+    h = mp.H
+    r = np.linspace(0, 2 * h, 20001)
+    w = np.array([orc.W(x, h) for x in r])
+    plane = 2 * math.pi * np.trapezoid(w * r, r)
+    approx = mp.S ** 2 / plane / mp.S ** 3
+    assert vb == pytest.approx(approx, rel=2e-3)
+    assert vb == pytest.approx(GOLD["flat_wall_Vb_over_s3"]["value"], rel=1e-12)
+
+
+# ---------------------------------------------------------------- grid and neighbours (Alg. 2)
+
+def test_morton_interleave(orc):
+    assert orc.morton3(1, 0, 0, 4) == 1
+    assert orc.morton3(0, 1, 0, 4) == 2
+    assert orc.morton3(0, 0, 1, 4) == 4
+    assert orc.morton3(2, 0, 0, 4) == 8
+    assert orc.morton3(3, 3, 3, 4) == 63
+    assert orc.morton3(15, 0, 0, 4) == 0b001001001001
+    assert orc.morton3(5, 6, 7, 3) == int("111110101", 2)
+
+
+def test_cell_keys_by_hand(orc):
+    P = {"h": 0.5, "rho0": 1000.0, "k_pressure": 1.0, "nu": 0.0, "gravity": (0, 0, 0), "dt": 1.0,
+         "domain_lo": (0.0, 0.0, 0.0), "domain_hi": (4.0, 4.0, 4.0), "flags": 0}
+    g = orc.grid_info(P, "f32")
+    assert g["dims"] == (4, 4, 4) and g["bits"] == 2          # cell 1*(1+2^-10)
+    x = np.array([[0.5, 0.5, 0.5], [1.5, 0.2, 0.2], [0.2, 2.5, 3.9], [-5.0, 9.0, 1.0],
+                  [1.0005, 0, 0], [1.0, 0, 0], [np.nan, 0.0, 0.0]])
+    k = orc.cell_keys(P, "f32", x)
+    want = [orc.morton3(0, 0, 0, 2), orc.morton3(1, 0, 0, 2), orc.morton3(0, 2, 3, 2),
+            orc.morton3(0, 3, 0, 2), orc.morton3(0, 0, 0, 2), orc.morton3(0, 0, 0, 2),
+            orc.morton3(0, 0, 0, 2)]
+    assert list(k) == want
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_neighbors_grid_equals_bruteforce(orc, prec):
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=5, nf=(7, 6, 5), n_tank=(14, 9, 9))
+    x = orc.round_to(sc.x, prec)
+    a = orc.neighbors(sc.params, prec, x, use_grid=False)
+    b = orc.neighbors(sc.params, prec, x, use_grid=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+    cnt, off, ids = b
+    for i in range(0, sc.n, 37):
+        lst = ids[off[i]:off[i] + cnt[i]]
+        assert i in lst                                     # self included
+        assert np.all(np.diff(lst) > 0)                     # ascending id
+    # symmetry of the predicate
+    pairs = set()
+    for i in range(sc.n):
+        for j in ids[off[i]:off[i] + cnt[i]]:
+            pairs.add((i, int(j)))
+    assert all((j, i) in pairs for (i, j) in pairs)
+
+
+def test_neighbors_exact_support_boundary(orc):
+    """A pair at exactly r = 2h is not a neighbour (strict <), one ulp inside is."""
+    h = 0.5
+    P = {"h": h, "rho0": 1000.0, "k_pressure": 1.0, "nu": 0.0, "gravity": (0, 0, 0), "dt": 1.0,
+         "domain_lo": (-2.0, -2.0, -2.0), "domain_hi": (2.0, 2.0, 2.0), "flags": 0}
+    x = np.array([[0.0, 0, 0], [1.0, 0, 0], [0, np.nextafter(1.0, 0.0), 0]])
+    cnt, off, ids = orc.neighbors(P, "f64", x, [0], use_grid=False)
+    assert list(ids) == [0, 2]
+    xf = np.array([[0.0, 0, 0], [1.0, 0, 0], [0, float(np.nextafter(np.float32(1.0), np.float32(0))), 0]])
+    cnt, off, ids = orc.neighbors(P, "f32", xf, [0], use_grid=False)
+    assert list(ids) == [0, 2]
+
+
+# ---------------------------------------------------------------- momentum balance
+
+def _all_forces(orc, sc, prec="f64", grav=False, springs=False):
+    P = dict(sc.params)
+    if not grav:
+        P["gravity"] = (0.0, 0.0, 0.0)
+    x = orc.round_to(sc.x, prec)
+    v = orc.round_to(sc.v, prec)
+    n = sc.n
+    psi = orc.boundary_psi(P, prec, x, sc.type, sc.object)
+    nb = orc.neighbors(P, prec, x)
+    mov = np.nonzero(sc.type != 2)[0]
+    rho, p = orc.density(P, prec, x, sc.mass, sc.type, psi, mov,
+                         (nb[0][mov], nb[1][mov], nb[2]))
+    rf, pf = np.zeros(n), np.zeros(n)
+    rf[mov], pf[mov] = rho, p
+    fs = orc.springs(n, x, v, sc.spring_ij, sc.spring_L0, sc.spring_k, sc.spring_c) if springs else None
+    f = orc.forces(P, prec, x, v, sc.mass, sc.type, psi, rf, pf, fs, np.arange(n), nb)
+    return f, nb, x, psi
+
+
+def test_zero_net_internal_force(orc):
+    """Symmetric pressure and viscosity terms conserve momentum: the forces on
+    all particles (boundary reactions included) sum to zero."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=7)
+    f, nb, x, psi = _all_forces(orc, sc)
+    scale = np.abs(f).sum()
+    assert np.abs(f.sum(0)).max() < 1e-13 * scale
+
+
+def test_springs_internal_and_closed_form(orc):
+    # two particles, stretched by 10 %, approaching at 0.5 m/s along the axis
+    x = np.array([[0.0, 0, 0], [0.11, 0, 0]])
+    v = np.array([[0.25, 0, 0], [-0.25, 0, 0]])
+    f = orc.springs(2, x, v, [[0, 1]], [0.1], [100.0], [0.2])
+    # x_01 = -0.11 e_x, e = -e_x, v_01 . e = -0.5 -> mag = 100*0.01 + 0.2*(-0.5) = 0.9
+    assert f[0] == pytest.approx([0.9, 0, 0], abs=1e-15)
+    assert f[1] == pytest.approx([-0.9, 0, 0], abs=1e-15)
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=3)
+    fs = orc.springs(sc.n, sc.x, sc.v, sc.spring_ij, sc.spring_L0, sc.spring_k, sc.spring_c)
+    assert np.abs(fs.sum(0)).max() < 1e-12 * np.abs(fs).sum()
+
+
+def test_fluid_body_newton_third_law(orc):
+    """The body's force equals minus the force its particles exert on the
+    fluid/soft particles: run with only fluid + body (no tank, no gravity)."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=9, with_soft=False)
+    keep = (sc.type != 2) | (sc.object == 1)
+    for name in ["x", "v", "mass", "type", "object"]:
+        setattr(sc, name, getattr(sc, name)[keep])
+    f, nb, x, psi = _all_forces(orc, sc)
+    body = sc.object == 1
+    F_body = f[body].sum(0)
+    assert np.linalg.norm(F_body) > 0
+    assert np.abs(F_body + f[~body].sum(0)).max() < 1e-12 * np.abs(f).sum()
+
+
+# ---------------------------------------------------------------- rigid body, wrench, integrator
+
+def test_quaternion_rotation(orc):
+    a = math.pi / 2
+    R = orc.quat_to_R([math.cos(a / 2), 0, 0, math.sin(a / 2)])
+    assert R @ np.array([1.0, 0, 0]) == pytest.approx([0, 1, 0], abs=1e-15)
+    q = np.array([0.3, -0.5, 0.7, 0.2])
+    q /= np.linalg.norm(q)
+    R = orc.quat_to_R(q)
+    assert R @ R.T == pytest.approx(np.eye(3), abs=1e-15)
+    assert np.linalg.det(R) == pytest.approx(1.0, abs=1e-14)
+
+
+def test_wrench_closed_form(orc):
+    obj = np.array([1, 1, 0], np.int32)
+    r_loc = np.array([[1.0, 0, 0], [0, 2.0, 0], [5, 5, 5]])
+    f = np.array([[0, 1.0, 0], [3.0, 0, 0], [9, 9, 9]])
+    a = math.pi / 2
+    q = [math.cos(a / 2), 0, 0, math.sin(a / 2)]          # r -> R r: (1,0,0)->(0,1,0), (0,2,0)->(-2,0,0)
+    F, T = orc.wrench(obj, 1, q, r_loc, f)
+    assert F == pytest.approx([3, 1, 0])
+    # (0,1,0)x(0,1,0) + (-2,0,0)x(3,0,0) = 0
+    assert T == pytest.approx([0, 0, 0], abs=1e-14)
+    F, T = orc.wrench(obj, 1, [1, 0, 0, 0], r_loc, f)
+    # (1,0,0)x(0,1,0) + (0,2,0)x(3,0,0) = (0,0,1) + (0,0,-6)
+    assert T == pytest.approx([0, 0, -5])
+
+
+def test_body_frame_roundtrip(orc):
+    from paper_2511_15908_amd import scenes
+    o = orc.Oracle(scenes.small_scene(seed=2), "f64")
+    x0 = o.x.copy()
+    o.place()
+    assert np.abs(o.x - x0).max() < 1e-15
+    assert np.all(o.v[o.type == 2] == 0.0)
+
+
+def test_free_fall_closed_form(orc):
+    """An isolated particle under gravity: symplectic Euler (Eq. euler) gives
+    v_n = v0 - n g dt and z_n = z0 + n dt v0 - g dt^2 n(n+1)/2 exactly."""
+    P = {"h": 0.01, "rho0": 1000.0, "k_pressure": 250.0, "nu": 1e-3, "gravity": (0, 0, -9.81),
+         "dt": 1e-3, "domain_lo": (-1.0, -1.0, -1.0), "domain_hi": (1.0, 1.0, 1.0), "flags": 0}
+    x = np.array([[0.1, 0.2, 0.3]])
+    v = np.array([[0.0, 0.0, 0.5]])
+    m = np.array([0.125])
+    n = 40
+    for _ in range(n):
+        rho, p = orc.density(P, "f64", x, m, [0], np.zeros(1), [0])
+        f = orc.forces(P, "f64", x, v, m, [0], np.zeros(1), rho, p, None, [0])
+        x, v = orc.integrate(P, "f64", [0], m, f, x, v)
+    g, dt = 9.81, 1e-3
+    assert v[0, 2] == pytest.approx(0.5 - n * g * dt, rel=1e-13)
+    assert x[0, 2] == pytest.approx(0.3 + n * dt * 0.5 - g * dt * dt * n * (n + 1) / 2, rel=1e-13)
+
+
+def test_pose_advance(orc):
+    c, q = orc.pose_advance([0, 0, 0], [1, 0, 0, 0], [1, 2, 3], [0, 0, 0], 0.5)
+    assert list(c) == [0.5, 1.0, 1.5] and list(q) == [1, 0, 0, 0]
+    qq = np.array([1.0, 0, 0, 0])
+    cc = np.zeros(3)
+    dt, w = 1e-4, 2.0
+    for _ in range(5000):                   # 1 rad about z
+        cc, qq = orc.pose_advance(cc, qq, [0, 0, 0], [0, 0, w], dt)
+    assert abs(np.linalg.norm(qq) - 1) < 1e-14
+    assert 2 * math.atan2(qq[3], qq[0]) == pytest.approx(1.0, abs=1e-3)
+
+
+def test_rolling_average(orc):
+    """Sec. 3.3: the haptic force is a rolling average over the last K cycles."""
+    from paper_2511_15908_amd import scenes
+    o = orc.Oracle(scenes.small_scene(seed=2), "f64")
+    o.K = 4
+    seq = [np.full(6, float(i)) for i in range(10)]
+    o.samples[1] = seq[:2]
+    assert o.smoothed_wrench(1) == pytest.approx(np.full(6, 0.5))
+    o.samples[1] = seq
+    assert o.smoothed_wrench(1) == pytest.approx(np.full(6, 7.5))
+
+
+def test_jittered_dam_break_density(orc):
+    """The dam-break interior sits at rest density: fluid particles with a full
+    neighbourhood read rho within 2e-3 of rho0 (jitter +-1e-4 m on 0.02 m),
+    with a mean at the lattice value."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.dam_break()
+    o = orc.Oracle(sc)
+    fl = np.nonzero(sc.type == 0)[0]
+    core = fl[np.all((sc.x[fl] > 0.1) & (sc.x[fl] < 0.32), axis=1)]
+    rho, _ = orc.density(sc.params, "f64", o.x, sc.mass, sc.type, o.psi, core)
+    assert np.abs(rho / 1000.0 - 1.0).max() < 2e-3
+    assert abs(rho.mean() / 1000.0 - GOLD["lattice_density_over_rho0"]["value"]) < 2e-4
