@@ -1,0 +1,156 @@
+"""Benchmark of the SPH hot path on one MI355X.
+
+Workload: the coupled fluid + soft + rigid scene at 1M fluid particles
+(1,000,000 fluid, 8,000 soft with 66,120 springs, a 3,079-particle grabbed
+sphere driven by a seeded 1 kHz random-walk pose, 58,884 tank particles;
+FP32, dt = 2.5e-4 s).  One step = one sph_step (placement, neighbour search,
+springs, density, forces, FP64 body wrench, integration); the sphere's pose
+is set every 4 steps (1 kHz).  Inputs are resident in HBM before timing.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10]
+
+Prints one JSON line.  value = (fluid + soft) particle updates per second.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+
+# Algorithmic FLOPs per neighbour pair of the method's pair expressions
+# (density: r^2, r, the cubic spline and the weighted sum; force: r^2, r,
+# dW/dr, the symmetric pressure term, the Brookshaw viscosity term and the
+# vector accumulation), counted as written in the oracle, FMA = 2.
+FLOP_DENSITY_PAIR = 17
+FLOP_FORCE_PAIR = 49
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="coupled_1m")
+    ap.add_argument("--n-fluid", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg, quiet=False):
+    if not quiet:
+        print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(scene):
+    """The oracle as it stands, one full step of the same scene on the host
+    cores (bounded sample: one step)."""
+    import oracle
+    oracle.build(force=False)
+    o = oracle.Oracle(scene, scene.precision)
+    t0 = time.perf_counter()
+    o.step()
+    dt = time.perf_counter() - t0
+    nmov = int((scene.type != 2).sum())
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": nmov / dt, "unit": "particle-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 full step of the {scene.n:,}-particle scene ({nmov:,} fluid+soft), "
+                      f"FP64, {dt:.1f} s wall"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (single-GPU build)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2511_15908_amd as P
+    from paper_2511_15908_amd import scenes
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    sc = scenes.coupled_1m(n_fluid=a.n_fluid)
+    log(f"scene {sc.name}: {sc.counts()} built in {time.perf_counter() - t0:.1f} s", a.quiet)
+    sim = P.Sim(sc, device=dev)
+    info = sim.info()
+    dt = sc.params["dt"]
+    body = 1
+    per_tick = 4                                     # 1 kHz pose updates at dt = 2.5e-4
+    n_ticks = (a.warmup + a.steps) // per_tick + 2
+    C_, Q_, V_, W_ = scenes.random_walk(3, n_ticks, sc.info["c0"])
+    nmov = info["n_fluid"] + info["n_soft"]
+
+    def run(k0, k):
+        for s in range(k0, k0 + k):
+            if s % per_tick == 0:
+                t = s // per_tick
+                sim.set_body_pose(body, C_[t], Q_[t], V_[t], W_[t])
+            sim.step(1)
+
+    run(0, a.warmup)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    s0 = sim.stats()
+    sim.profile_begin(a.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(a.warmup, a.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    phases = sim.profile_read()
+    s1 = sim.stats()
+    F, T = sim.wrench(body)                          # also reports instability
+    ms_step = 1e3 * el / a.steps
+    value = nmov * a.steps / el
+    # roofline of the dominant kernel
+    pairs_d = (s1["pairs_density"] - s0["pairs_density"]) / a.steps
+    pairs_f = (s1["pairs_force"] - s0["pairs_force"]) / a.steps
+    cand = (s1["candidates"] - s0["candidates"]) / a.steps
+    ms = {k: v[0] / max(v[1], 1) for k, v in phases.items()}
+    dom = "forces" if ms["forces"] >= ms["density"] else "density"
+    flops = pairs_f * FLOP_FORCE_PAIR if dom == "forces" else pairs_d * FLOP_DENSITY_PAIR
+    achieved = flops / (ms[dom] * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": f"k_{dom}", "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": None, "avg_launch_ms": round(ms[dom], 4),
+            "algorithmic_flops_per_launch": int(flops)}
+    out = {
+        "metric": "SPH particle-updates/s @1M + haptic wrench Hz: surrogate vs plain, <=5% err",
+        "value": value, "unit": "particle-updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"coupled fluid+soft+rigid, {info['n_fluid']:,} fluid + {info['n_soft']:,} soft "
+                               f"+ {info['n_body_particles']:,} grabbed sphere + tank, {info['n']:,} particles, "
+                               f"h=0.01 m, dt=2.5e-4 s, 1 kHz pose",
+                   "n_particles": info["n"], "precision": "fp32 particles, fp64 wrench",
+                   "parallelism": "single GPU"},
+        "wrench_hz_plain": a.steps / el,
+        "realtime_factor": a.steps * dt / el,
+        "pairs_per_step": {"density": pairs_d, "force": pairs_f, "candidates_tested": cand},
+        "phase_ms": {k: round(v, 4) for k, v in ms.items()},
+        "roofline": roof,
+    }
+    log(json.dumps(out, indent=1), a.quiet)
+    if not a.no_cpu_baseline:
+        log("timing the CPU oracle on one step of the same scene ...", a.quiet)
+        out["cpu_baseline"] = cpu_baseline(sc)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

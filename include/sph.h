@@ -1,0 +1,211 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) SPH hot path.
+ *
+ * One simulation step follows the paper's simulation loop (arXiv 2511.15908,
+ * Alg. 2 and Sec. 3.2): rigid-body particles are re-placed from their parent
+ * transform, a uniform-grid spatial hash orders the particles (here a Morton
+ * cell-key radix sort with reorder and cell-start tables), soft-body spring
+ * forces are applied, then the SPH density/pressure pass and the force pass of
+ * Alg. 1 run over the neighbours, the point forces on each grabbed body are
+ * reduced into a force and torque (Sec. 3.2, Sec. 3.3), and fluid and soft
+ * particles are integrated with the semi-implicit Euler scheme (Eq. euler).
+ * The body wrench is the haptic output of Fig. 1 / Sec. 3.3; the device pose
+ * enters through sph_set_body_pose.
+ *
+ * Conventions for every call:
+ *  - All functions return sph_status and never abort or throw.  Argument
+ *    errors are reported before any device work is enqueued.  A HIP runtime
+ *    failure returns SPH_ERR_DEVICE and sph_last_error() holds its text; after
+ *    it the context only accepts sph_destroy (SPH_ERR_STATE otherwise).
+ *  - Host pointers are plain C arrays owned by the caller and only read or
+ *    written during the call.  The device workspace is one caller-allocated
+ *    block (e.g. a torch uint8 tensor) borrowed by the context until
+ *    sph_destroy; the library allocates no device memory of its own.
+ *  - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it; calls that return data to the host synchronise it.
+ *  - One context per host thread; different contexts are independent.
+ */
+#ifndef SPH_H_
+#define SPH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPH_ABI_VERSION 1u
+
+typedef struct sph_ctx sph_ctx;
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_ERR_ARG = 1,         /* invalid argument (null pointer, bad size, bad id, bad value) */
+    SPH_ERR_WORKSPACE = 2,   /* workspace missing, misaligned (256 B) or smaller than sph_workspace_size */
+    SPH_ERR_DEVICE = 3,      /* HIP runtime error; see sph_last_error */
+    SPH_ERR_STATE = 4,       /* call not valid in the context's state (after a device error) */
+    SPH_ERR_UNSTABLE = 5,    /* a particle velocity or position became non-finite or exceeded v_max */
+    SPH_ERR_UNSUPPORTED = 6, /* precision/flag/geometry the library does not implement */
+    SPH_ERR_CAPACITY = 7     /* a cell neighbourhood exceeded the candidate capacity (extreme compression) */
+} sph_status;
+
+typedef enum { SPH_FP32 = 0, SPH_FP64 = 1 } sph_precision;
+
+/* Particle types: each particle has a type (Sec. 3.2 unified framework). */
+enum { SPH_FLUID = 0, SPH_SOFT = 1, SPH_BOUNDARY = 2 };
+
+/* Alternative readings of points the paper leaves open (default 0). */
+enum {
+    SPH_FLAG_CLAMP_NEG_PRESSURE = 1u,   /* p = max(k (rho - rho0), 0) instead of Eq. pressure as printed */
+    SPH_FLAG_BOUNDARY_SINGLE_TERM = 2u, /* fluid-boundary pressure term p_i/rho_i^2 once, not mirrored */
+    SPH_FLAG_NO_BOUNDARY_VISCOSITY = 4u /* no viscosity between fluid/soft and boundary particles */
+};
+
+/* Fields readable with sph_read_field, all in original particle-id order. */
+enum {
+    SPH_FIELD_X = 0,        /* double[3n] positions after the last step (or init) */
+    SPH_FIELD_V = 1,        /* double[3n] velocities after the last step (or init) */
+    SPH_FIELD_RHO = 2,      /* double[n] density of the last step (fluid/soft; 0 for boundary) */
+    SPH_FIELD_PRESSURE = 3, /* double[n] pressure p = k (rho - rho0) of the last step */
+    SPH_FIELD_FORCE = 4,    /* double[3n] total force of the last step: pair forces + m g + springs
+                               (fluid/soft); reaction force of kinematic boundary particles; 0 static */
+    SPH_FIELD_PSI = 5,      /* double[n] boundary volume mass psi_b = rho0 V_b (0 for fluid/soft) */
+    SPH_FIELD_KEY = 6,      /* uint32[n] Morton cell key of the last neighbour search */
+    SPH_FIELD_SPRING = 7    /* double[3n] spring force of the last step (soft; 0 otherwise) */
+};
+
+typedef struct {
+    uint32_t abi_version;      /* must be SPH_ABI_VERSION */
+    int32_t precision;         /* sph_precision of particle arithmetic; the wrench is always FP64 */
+    uint32_t flags;            /* SPH_FLAG_* */
+    uint32_t smoothing_window; /* K >= 1 samples in the rolling average (Sec. 3.3, "tens" of cycles) */
+    double h;                  /* smoothing length; kernel support is 2h (Eq. kernel) [m] */
+    double rho0;               /* rest density (Eq. pressure) [kg/m^3] */
+    double k_pressure;         /* pressure constant k (Eq. pressure) [m^2/s^2] */
+    double nu;                 /* kinematic viscosity nu (Alg. 1) [m^2/s] */
+    double gravity[3];         /* external acceleration, F_ext = m g (Alg. 1) [m/s^2] */
+    double dt;                 /* time step (Eq. euler) [s] */
+    double domain_lo[3];       /* uniform grid bounds [m]; particles outside use the edge cells */
+    double domain_hi[3];
+    double v_max;              /* |v| above this flags SPH_ERR_UNSTABLE; 0 = only non-finite */
+    uint32_t reserved[8];      /* must be zero */
+} sph_params;
+
+typedef struct {               /* caller-owned host arrays, read only during sph_init */
+    uint32_t n;                /* number of particles (all types) */
+    const double *x;           /* [3n] initial positions (rounded to the run precision) */
+    const double *v;           /* [3n] initial velocities */
+    const double *mass;        /* [n] mass of fluid/soft particles; ignored for boundary particles */
+    const uint8_t *type;       /* [n] SPH_FLUID / SPH_SOFT / SPH_BOUNDARY */
+    const int32_t *object;     /* [n] object id of boundary particles (0..n_objects-1), -1 otherwise */
+    uint32_t n_objects;        /* boundary objects */
+    const uint8_t *object_kinematic; /* [n_objects] 1: pose-driven (grabbed) body, 0: static */
+    const double *object_pose0;      /* [7 n_objects] reference point c[3] and unit quaternion
+                                        q[4] = (w,x,y,z) of each object; body-frame offsets are
+                                        taken from x at this pose */
+    uint32_t n_springs;        /* soft-body springs (Sec. 3.2 mass-spring model) */
+    const uint32_t *spring_ij; /* [2 n_springs] particle ids of the two ends (soft particles) */
+    const double *spring_L0;   /* [n_springs] rest length [m] */
+    const double *spring_k;    /* [n_springs] stiffness [N/m] */
+    const double *spring_c;    /* [n_springs] damping along the spring [N s/m] */
+} sph_scene;
+
+typedef struct {               /* read-only facts about a context */
+    uint32_t n, n_fluid, n_soft, n_boundary, n_body_particles, n_kinematic;
+    uint32_t grid_dims[3], grid_bits;   /* cells per axis, Morton bits per axis */
+    uint32_t cell_slots;                /* 2^(3 grid_bits) */
+    uint32_t max_candidates;            /* per-cell neighbourhood capacity */
+    uint64_t steps;                     /* steps taken */
+    double cell_size;                   /* 2h (1 + 2^-10) */
+} sph_info;
+
+/* Bytes of device workspace sph_init needs for these params and scene. */
+sph_status sph_workspace_size(const sph_params *params, const sph_scene *scene, size_t *bytes);
+
+/*
+ * Create a context: validate, copy the scene into the workspace (async on
+ * hip_stream, the call synchronises before returning), compute boundary
+ * volumes psi_b from the initial configuration and sort the particles once.
+ * d_workspace: device pointer, 256-byte aligned, ws_bytes >= sph_workspace_size.
+ */
+sph_status sph_init(const sph_params *params, const sph_scene *scene, void *d_workspace,
+                    size_t ws_bytes, void *hip_stream, sph_ctx **out);
+
+/*
+ * Pose of a kinematic object from the haptic device (Sec. 3.3, Fig. 1):
+ * reference point c, orientation q (w,x,y,z; normalised by the library),
+ * linear velocity v and angular velocity w (world frame).  Enqueued on the
+ * context's last stream; takes effect at the next step.  Between calls the
+ * pose advances every step by c += v dt, q <- normalise(q + dt/2 (0,w) q).
+ * Errors: SPH_ERR_ARG for a static or unknown object or a zero/non-finite q.
+ */
+sph_status sph_set_body_pose(sph_ctx *ctx, uint32_t object, const double c[3], const double q[4],
+                             const double v[3], const double w[3]);
+
+/* Enqueue n_steps full steps on hip_stream (no host synchronisation). */
+sph_status sph_step(sph_ctx *ctx, uint32_t n_steps, void *hip_stream);
+
+/*
+ * Wrench exerted by the fluid and soft particles on a kinematic object
+ * (gravity excluded), about its reference point c, world frame, binary64:
+ * F [N], T [N m].  smoothed = 0: the last step's sample; 1: the mean of the
+ * last min(K, steps since init or reset) samples (Sec. 3.3 rolling average).
+ * Synchronises the stream; returns SPH_ERR_UNSTABLE / SPH_ERR_CAPACITY if a
+ * step since the last check raised that condition (the values are still
+ * written).
+ */
+sph_status sph_get_body_wrench(sph_ctx *ctx, uint32_t object, double F[3], double T[3], int smoothed);
+
+/* Restart the rolling average of a kinematic object (grab or release). */
+sph_status sph_reset_smoothing(sph_ctx *ctx, uint32_t object);
+
+/* Copy a field (SPH_FIELD_*) into host_dst; bytes must equal its size. Synchronises. */
+sph_status sph_read_field(sph_ctx *ctx, int field, void *host_dst, size_t bytes);
+
+/*
+ * Neighbour lists found by the last step's density pass, for checking (any N,
+ * but it copies O(N * candidates) bytes to the host).  counts[n] receives
+ * |N(i)| for fluid, soft and kinematic-boundary particles (0 for static
+ * boundary particles); ids receives the lists back to back in particle-id
+ * order, each ascending, self included.  *total receives the total; ids is
+ * only written when total <= cap.
+ */
+sph_status sph_debug_neighbors(sph_ctx *ctx, uint32_t *counts, uint32_t *ids, size_t cap,
+                               size_t *total);
+
+/*
+ * Work counters accumulated by the density pass since init, on the device:
+ * out[0] neighbour pairs of fluid/soft particles (self included), out[1]
+ * neighbour pairs of all particles that receive forces (fluid, soft and
+ * kinematic boundary), out[2] candidate pairs tested, out[3] wavefronts run.
+ * Synchronises the stream.
+ */
+sph_status sph_get_stats(sph_ctx *ctx, uint64_t out[4]);
+
+/* Facts about the context (sizes, grid). */
+sph_status sph_get_info(const sph_ctx *ctx, sph_info *info);
+
+/* Wait for the context's stream; report SPH_ERR_UNSTABLE / SPH_ERR_CAPACITY if raised. */
+sph_status sph_synchronize(sph_ctx *ctx);
+
+/*
+ * Per-phase GPU timing with HIP events recorded on the step's stream.
+ * sph_profile_begin(ctx, max_steps) arms it for the next max_steps steps;
+ * sph_profile_read synchronises and writes, for each phase id 0..n_phases-1
+ * (see sph_profile_phase_name), the summed milliseconds and launch count.
+ */
+sph_status sph_profile_begin(sph_ctx *ctx, uint32_t max_steps);
+sph_status sph_profile_read(sph_ctx *ctx, double *ms, uint32_t *launches, uint32_t n_phases);
+const char *sph_profile_phase_name(uint32_t phase);
+
+/* Release the context (not the caller's workspace).  NULL is accepted. */
+sph_status sph_destroy(sph_ctx *ctx);
+
+const char *sph_status_string(sph_status s);
+const char *sph_last_error(const sph_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_H_ */

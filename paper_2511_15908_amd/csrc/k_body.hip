@@ -1,0 +1,259 @@
+// Rigid and soft bodies and the integrator of one SPH step (arXiv 2511.15908):
+//  - kinematic (grabbed) bodies: particles keep constant offsets from the
+//    parent transform (Sec. 3.2); the pose comes from the haptic device
+//    (Sec. 3.3, Fig. 1);
+//  - body wrench: the particles' point forces summed into the parent's force
+//    and torque (Sec. 3.2, Alg. 2 "resolve new rigid forces"), reduced in
+//    binary64 with a fixed wavefront-shuffle tree (deterministic), pushed into
+//    the rolling-average ring of Sec. 3.3;
+//  - soft bodies: mass-spring forces through a spring lookup table (Sec. 3.2,
+//    Alg. 2 "apply soft body forces from springs");
+//  - semi-implicit Euler (Eq. euler) for fluid and soft particles.
+#include "sph_internal.h"
+
+namespace sphk {
+
+__device__ __forceinline__ void quat_R(const double *q, double R[9])
+{
+#pragma clang fp contract(off)
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// ------------------------------------------------------------------ placement
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_place(BodyArgs b, const uint32_t *__restrict__ inv_perm, State<T> st)
+{
+#pragma clang fp contract(off)
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= b.nb) return;
+    const double *pose = b.poses + 16u * b.slot_obj[s];
+    double R[9];
+    quat_R(pose + 3, R);
+    const double r0 = b.r_loc[3 * s], r1 = b.r_loc[3 * s + 1], r2 = b.r_loc[3 * s + 2];
+    double rw[3];
+    for (int a = 0; a < 3; ++a) rw[a] = R[3 * a] * r0 + R[3 * a + 1] * r1 + R[3 * a + 2] * r2;
+    const double *w = pose + 10;
+    const double vx = pose[7] + (w[1] * rw[2] - w[2] * rw[1]);
+    const double vy = pose[8] + (w[2] * rw[0] - w[0] * rw[2]);
+    const double vz = pose[9] + (w[0] * rw[1] - w[1] * rw[0]);
+    const uint32_t p = inv_perm[b.slot_id[s]];
+    V4<T> x = st.pos[p];
+    x.x = (T)(pose[0] + rw[0]);
+    x.y = (T)(pose[1] + rw[1]);
+    x.z = (T)(pose[2] + rw[2]);
+    st.pos[p] = x;
+    st.vel[p] = V4<T>{(T)vx, (T)vy, (T)vz, (T)0};
+}
+
+template <typename T>
+void launch_place(hipStream_t s, const BodyArgs &b, const uint32_t *inv_perm, State<T> st)
+{
+    if (!b.nb) return;
+    hipLaunchKernelGGL(k_place<T>, dim3((b.nb + 255) / 256), dim3(256), 0, s, b, inv_perm, st);
+}
+template void launch_place<float>(hipStream_t, const BodyArgs &, const uint32_t *, State<float>);
+template void launch_place<double>(hipStream_t, const BodyArgs &, const uint32_t *, State<double>);
+
+// ------------------------------------------------------------------ wrench
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Pass 1: each block reduces up to 256 body particles of one object.
+__global__ __launch_bounds__(256) void k_wrench_partial(BodyArgs b)
+{
+    __shared__ double red[4][6];
+    const uint32_t blk = blockIdx.x, t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+    const uint32_t o = b.blk_obj[blk];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (t < b.blk_count[blk]) {
+        const uint32_t s = b.blk_first[blk] + t;
+        double R[9];
+        quat_R(b.poses + 16u * o + 3, R);
+        const double r0 = b.r_loc[3 * s], r1 = b.r_loc[3 * s + 1], r2 = b.r_loc[3 * s + 2];
+        double rw[3];
+        for (int a = 0; a < 3; ++a) rw[a] = R[3 * a] * r0 + R[3 * a + 1] * r1 + R[3 * a + 2] * r2;
+        const double fx = b.fbody[3 * s], fy = b.fbody[3 * s + 1], fz = b.fbody[3 * s + 2];
+        v[0] = fx;
+        v[1] = fy;
+        v[2] = fz;
+        v[3] = rw[1] * fz - rw[2] * fy;
+        v[4] = rw[2] * fx - rw[0] * fz;
+        v[5] = rw[0] * fy - rw[1] * fx;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k) red[wv][k] = v[k];
+    __syncthreads();
+    if (t < 6) b.partials[6u * blk + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+}
+
+// Pass 2: one wave per kinematic object sums its partials in a fixed order,
+// pushes the sample into the ring and advances the pose by one step.
+__global__ __launch_bounds__(64) void k_wrench_final(BodyArgs b)
+{
+#pragma clang fp contract(off)
+    const uint32_t o = blockIdx.x, lane = threadIdx.x;
+    const uint32_t b0 = b.obj_blk0[o], b1 = b.obj_blk0[o + 1];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t k = b0 + lane; k < b1; k += 64u)
+        for (int c = 0; c < 6; ++c) v[c] += b.partials[6u * k + c];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = wave_sum(v[c]);
+    if (lane == 0) {
+        const uint32_t cnt = b.ring_count[o];
+        double *slot = b.ring + ((size_t)o * b.K + (cnt % b.K)) * 6u;
+        for (int c = 0; c < 6; ++c) slot[c] = v[c];
+        b.ring_count[o] = cnt + 1u;
+        // pose advance: c += v dt, q <- normalise(q + dt/2 (0, w) q)
+        double *pz = b.poses + 16u * o;
+        const double dt = b.dt;
+        for (int a = 0; a < 3; ++a) pz[a] = pz[a] + pz[7 + a] * dt;
+        const double qw = pz[3], qx = pz[4], qy = pz[5], qz = pz[6];
+        const double wx = pz[10], wy = pz[11], wz = pz[12];
+        const double d0 = -wx * qx - wy * qy - wz * qz;
+        const double d1 = wx * qw + wy * qz - wz * qy;
+        const double d2 = wy * qw + wz * qx - wx * qz;
+        const double d3 = wz * qw + wx * qy - wy * qx;
+        const double n0 = qw + 0.5 * dt * d0, n1 = qx + 0.5 * dt * d1;
+        const double n2 = qy + 0.5 * dt * d2, n3 = qz + 0.5 * dt * d3;
+        const double s = sqrt(n0 * n0 + n1 * n1 + n2 * n2 + n3 * n3);
+        pz[3] = n0 / s;
+        pz[4] = n1 / s;
+        pz[5] = n2 / s;
+        pz[6] = n3 / s;
+    }
+}
+
+void launch_wrench(hipStream_t s, const BodyArgs &b)
+{
+    if (!b.nk || !b.nblk) return;
+    hipLaunchKernelGGL(k_wrench_partial, dim3(b.nblk), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_wrench_final, dim3(b.nk), dim3(64), 0, s, b);
+}
+
+struct PoseArg {
+    double v[13];
+};
+
+__global__ void k_set_pose(double *__restrict__ slot, PoseArg a)
+{
+    const uint32_t t = threadIdx.x;
+    if (t < 13) slot[t] = a.v[t];
+}
+
+void launch_set_pose(hipStream_t s, double *pose_slot, const double c[3], const double q[4], const double v[3],
+                     const double w[3])
+{
+    PoseArg a;
+    for (int k = 0; k < 3; ++k) a.v[k] = c[k];
+    for (int k = 0; k < 4; ++k) a.v[3 + k] = q[k];
+    for (int k = 0; k < 3; ++k) a.v[7 + k] = v[k];
+    for (int k = 0; k < 3; ++k) a.v[10 + k] = w[k];
+    hipLaunchKernelGGL(k_set_pose, dim3(1), dim3(64), 0, s, pose_slot, a);
+}
+
+__global__ void k_reset_ring(uint32_t *__restrict__ cnt)
+{
+    if (threadIdx.x == 0) cnt[0] = 0u;
+}
+
+void launch_reset_ring(hipStream_t s, uint32_t *ring_count_slot)
+{
+    hipLaunchKernelGGL(k_reset_ring, dim3(1), dim3(64), 0, s, ring_count_slot);
+}
+
+// ------------------------------------------------------------------ springs
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_springs(SpringArgs a, const uint32_t *__restrict__ inv_perm, State<T> st,
+                                                 V4<T> *__restrict__ fspring)
+{
+    const uint32_t r = blockIdx.x * 256u + threadIdx.x;
+    if (r >= a.rows) return;
+    const uint32_t i = inv_perm[a.row_id[r]];
+    const V4<T> xi = st.pos[i], vi = st.vel[i];
+    double f[3] = {0.0, 0.0, 0.0};
+    for (uint32_t e = a.row_ptr[r]; e < a.row_ptr[r + 1]; ++e) {
+        const uint32_t j = inv_perm[a.partner[e]];
+        const V4<T> xj = st.pos[j], vj = st.vel[j];
+        const double d0 = (double)xi.x - (double)xj.x;
+        const double d1 = (double)xi.y - (double)xj.y;
+        const double d2 = (double)xi.z - (double)xj.z;
+        const double len = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double e0 = d0 / len, e1 = d1 / len, e2 = d2 / len;
+        const double vr = ((double)vi.x - (double)vj.x) * e0 + ((double)vi.y - (double)vj.y) * e1 +
+                          ((double)vi.z - (double)vj.z) * e2;
+        const double *pr = a.prm + 3u * e;
+        const double mag = pr[1] * (len - pr[0]) + pr[2] * vr;
+        f[0] -= mag * e0;
+        f[1] -= mag * e1;
+        f[2] -= mag * e2;
+    }
+    fspring[r] = V4<T>{(T)f[0], (T)f[1], (T)f[2], (T)0};
+}
+
+template <typename T>
+void launch_springs(hipStream_t s, const SpringArgs &a, const uint32_t *inv_perm, State<T> st, V4<T> *fspring)
+{
+    if (!a.rows) return;
+    hipLaunchKernelGGL(k_springs<T>, dim3((a.rows + 255) / 256), dim3(256), 0, s, a, inv_perm, st, fspring);
+}
+template void launch_springs<float>(hipStream_t, const SpringArgs &, const uint32_t *, State<float>, V4<float> *);
+template void launch_springs<double>(hipStream_t, const SpringArgs &, const uint32_t *, State<double>,
+                                     V4<double> *);
+
+// ------------------------------------------------------------------ integrate
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_integrate(uint32_t n, State<T> st, const V4<T> *__restrict__ force,
+                                                   Phys<T> ph, uint32_t *__restrict__ err)
+{
+    const uint32_t p = blockIdx.x * 256u + threadIdx.x;
+    if (p >= n) return;
+    if (aux_type(st.aux[p]) == TY_BOUNDARY) return;
+    V4<T> x = st.pos[p];
+    V4<T> v = st.vel[p];
+    const V4<T> f = force[p];
+    const T m = x.w;
+    v.x = v.x + (f.x / m) * ph.dt;
+    v.y = v.y + (f.y / m) * ph.dt;
+    v.z = v.z + (f.z / m) * ph.dt;
+    x.x = x.x + v.x * ph.dt;
+    x.y = x.y + v.y * ph.dt;
+    x.z = x.z + v.z * ph.dt;
+    st.pos[p] = x;
+    st.vel[p] = v;
+    const T v2 = v.x * v.x + v.y * v.y + v.z * v.z;
+    const bool bad = !(v2 == v2) || !isfinite(v2) || !isfinite(x.x) || !isfinite(x.y) || !isfinite(x.z) ||
+                     (ph.vmax2 > (T)0 && v2 > ph.vmax2);
+    if (bad) atomicOr(err, ERR_UNSTABLE);
+}
+
+template <typename T>
+void launch_integrate(hipStream_t s, uint32_t n, State<T> st, const V4<T> *force, const Phys<T> &ph, uint32_t *err)
+{
+    if (!n) return;
+    hipLaunchKernelGGL(k_integrate<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, st, force, ph, err);
+}
+template void launch_integrate<float>(hipStream_t, uint32_t, State<float>, const V4<float> *, const Phys<float> &,
+                                      uint32_t *);
+template void launch_integrate<double>(hipStream_t, uint32_t, State<double>, const V4<double> *,
+                                       const Phys<double> &, uint32_t *);
+
+}  // namespace sphk

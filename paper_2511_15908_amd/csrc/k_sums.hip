@@ -1,0 +1,372 @@
+// SPH neighbour sums of one step (arXiv 2511.15908, Alg. 1): the density /
+// pressure pass (Eqs. density, pressure) and the force pass (pressure,
+// viscosity and external forces), with fluid/soft <-> boundary-particle
+// coupling (Sec. 3.2: every particle type interacts through SPH pressure; the
+// rigid particles receive the reaction point forces).
+//
+// Work decomposition (gfx950, wave64): one workgroup = one wavefront per
+// occupied grid cell (cell size 2h, so all neighbours of a particle lie in the
+// 27 cells around its own).  Each lane owns one particle of the home cell.
+// The 27 neighbour cells form one virtual candidate list; it is staged through
+// LDS 256 candidates at a time with coalesced loads of the sorted SoA arrays,
+// every lane tests every staged candidate (LDS broadcast reads), and the
+// per-lane hit masks (one bit per candidate) drive a compacted per-lane loop
+// that evaluates the kernel only for true neighbours.  The density pass writes
+// the masks to HBM; the force pass reuses them instead of testing again.
+// All sums accumulate FP32 terms in FP64 registers; no atomics, so results are
+// bitwise reproducible.
+#include "sph_internal.h"
+
+namespace sphk {
+
+struct Nbhd {
+    uint32_t start[32];   // first sorted index of each stencil cell
+    uint32_t pre[32];     // exclusive prefix of the cell counts; entries 27..31 = UINT32_MAX
+    uint32_t total;       // candidates in the 27 cells
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD runs of 64
+// consecutive Morton cells so that neighbouring cells share an L2.
+__device__ __forceinline__ uint32_t cell_of_block(uint32_t b, uint32_t nslots)
+{
+    if (nslots < 512u) return b;
+    const uint32_t grp = b / 512u, r = b % 512u;
+    return grp * 512u + (r & 7u) * 64u + (r >> 3);
+}
+
+__device__ __forceinline__ void load_nbhd(uint32_t cell, const Grid &g, const uint32_t *__restrict__ cs,
+                                          const uint32_t *__restrict__ ce, Nbhd &nb, uint32_t lane)
+{
+    const int cx = (int)compact3(cell), cy = (int)compact3(cell >> 1), cz = (int)compact3(cell >> 2);
+    uint32_t st = 0, cnt = 0;
+    if (lane < 27u) {
+        int ox, oy, oz;
+        stencil_offset((int)lane, ox, oy, oz);
+        const int nx = cx + ox, ny = cy + oy, nz = cz + oz;
+        if (nx >= 0 && ny >= 0 && nz >= 0 && nx < g.dims[0] && ny < g.dims[1] && nz < g.dims[2]) {
+            const uint32_t k = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
+            st = cs[k];
+            cnt = ce[k] - st;
+        }
+    }
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= (uint32_t)d) inc += t;
+    }
+    if (lane < 32u) {
+        nb.start[lane] = st;
+        nb.pre[lane] = lane < 27u ? inc - cnt : 0xffffffffu;
+    }
+    if (lane == 26u) nb.total = inc;
+    __syncthreads();
+}
+
+// Sorted index of virtual candidate v (0 <= v < total): the cell is the
+// largest k with pre[k] <= v (pre is non-decreasing, padded with UINT32_MAX).
+__device__ __forceinline__ uint32_t cand_index(const Nbhd &nb, uint32_t v)
+{
+    uint32_t k = 0;
+#pragma unroll
+    for (uint32_t step = 16; step >= 1; step >>= 1)
+        if (nb.pre[k + step] <= v) k += step;
+    return nb.start[k] + (v - nb.pre[k]);
+}
+
+// One 64-candidate word of hit bits for this lane's particle.
+template <typename T>
+__device__ __forceinline__ uint64_t hit_word(const V4<T> &me, const V4<T> *cand, T R2)
+{
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int b = 0; b < 32; ++b) lo |= (uint32_t)within_support<T>(me, cand[b], R2) << b;
+#pragma unroll
+    for (int b = 0; b < 32; ++b) hi |= (uint32_t)within_support<T>(me, cand[32 + b], R2) << b;
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Next set bit of this lane's staged masks (half-words in LDS); -1 when done.
+__device__ __forceinline__ int next_hit(uint32_t (*mlds)[kWave], uint32_t lane, int &hw, uint32_t &cur)
+{
+    while (cur == 0u && hw < 2 * kScWords - 1) {
+        ++hw;
+        cur = mlds[hw][lane];
+    }
+    if (cur == 0u) return -1;
+    const int b = __builtin_ctz(cur);
+    cur &= cur - 1u;
+    return hw * 32 + b;
+}
+
+// ------------------------------------------------------------------ density
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_density(uint32_t n, State<T> st, Grid g, Phys<T> ph,
+                                                const uint32_t *__restrict__ cstart,
+                                                const uint32_t *__restrict__ cend, V2<T> *__restrict__ dens,
+                                                uint64_t *__restrict__ masks, uint32_t *__restrict__ err,
+                                                unsigned long long *__restrict__ stats)
+{
+    __shared__ Nbhd nb;
+    __shared__ V4<T> cand[kSc];
+    __shared__ uint32_t mlds[2 * kScWords][kWave];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t cell = cell_of_block(blockIdx.x, g.nslots);
+    if (cell >= g.nslots) return;
+    const uint32_t s0 = cstart[cell], e0 = cend[cell];
+    if (s0 >= e0) return;
+    load_nbhd(cell, g, cstart, cend, nb, lane);
+    const uint32_t L = nb.total;
+    if (L > (uint32_t)(kMaxWords * kWave)) {
+        if (lane == 0) atomicOr(err, ERR_CAPACITY);
+        return;
+    }
+    const T R2 = grid_R2<T>(g);
+    for (uint32_t t0 = s0; t0 < e0; t0 += kWave) {
+        const uint32_t p = t0 + lane;
+        const bool act = p < e0;
+        const uint32_t pc = act ? p : s0;
+        V4<T> me = st.pos[pc];
+        const uint32_t aux = act ? st.aux[pc] : 0u;
+        {
+            const T inf = __builtin_huge_val();
+            me.x = act ? me.x : inf;
+            me.y = act ? me.y : inf;
+            me.z = act ? me.z : inf;
+        }
+        const bool fs = act && aux_type(aux) != TY_BOUNDARY;
+        const bool want = act && (fs || aux_kin(aux));
+        if (__ballot(want) == 0ull) continue;
+        double acc = 0.0;
+        uint32_t npair = 0;
+        for (uint32_t sc = 0; sc < L; sc += kSc) {
+#pragma unroll
+            for (int q = 0; q < kScWords; ++q) {
+                const uint32_t v = sc + q * kWave + lane;
+                const bool in = v < L;
+                const uint32_t j = in ? cand_index(nb, v) : s0;
+                V4<T> c = st.pos[j];
+                const T inf = __builtin_huge_val();
+                c.x = in ? c.x : inf;
+                c.y = in ? c.y : inf;
+                c.z = in ? c.z : inf;
+                cand[q * kWave + lane] = c;
+            }
+            __syncthreads();
+            const uint32_t nw = min((L - sc + kWave - 1) / kWave, (uint32_t)kScWords);
+#pragma unroll
+            for (int q = 0; q < kScWords; ++q) {
+                uint64_t m = 0;
+                if ((uint32_t)q < nw) {
+                    m = hit_word<T>(me, cand + q * kWave, R2);
+                    if (act) masks[(size_t)(sc / kWave + q) * n + p] = m;
+                    npair += want ? (uint32_t)__popcll(m) : 0u;
+                }
+                mlds[2 * q][lane] = fs ? (uint32_t)m : 0u;
+                mlds[2 * q + 1][lane] = fs ? (uint32_t)(m >> 32) : 0u;
+            }
+            // kernel sum over this lane's neighbours among the staged candidates
+            int hw = 0;
+            uint32_t cur = mlds[0][lane];
+            for (;;) {
+                const int k = next_hit(mlds, lane, hw, cur);
+                if (k < 0) break;
+                const V4<T> c = cand[k];
+                const T dx = c.x - me.x, dy = c.y - me.y, dz = c.z - me.z;
+                const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                const T q = fsqrt(r2) * ph.inv_h;
+                const T t2 = max((T)2 - q, (T)0);
+                const T t1 = max((T)1 - q, (T)0);
+                const T w = ph.alpha6 * (t2 * t2 * t2 - (T)4 * (t1 * t1 * t1));
+                acc += (double)(fabs(c.w) * w);
+            }
+            __syncthreads();
+        }
+        {
+            // step statistics: neighbour pairs of density targets, of force
+            // targets, candidate tests and target chunks
+            uint32_t nd = fs ? npair : 0u, nf = npair;
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) {
+                nd += __shfl_xor(nd, m, 64);
+                nf += __shfl_xor(nf, m, 64);
+            }
+            if (lane == 0) {
+                atomicAdd(stats + 0, (unsigned long long)nd);
+                atomicAdd(stats + 1, (unsigned long long)nf);
+                atomicAdd(stats + 2, (unsigned long long)L * kWave);
+                atomicAdd(stats + 3, 1ull);
+            }
+        }
+        if (act) {
+            V2<T> d{(T)0, (T)0};
+            if (fs) {
+                double pr = ph.kp * (acc - ph.rho0);
+                if ((ph.flags & 1u) && pr < 0.0) pr = 0.0;
+                d.x = (T)acc;
+                d.y = (T)(pr / (acc * acc));
+            }
+            dens[p] = d;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ forces
+
+// Pair force on particle a from particle c (both terms of Alg. 1's force
+// pass).  gradW_ac = g(r) x_ac with g = (dW/dr)/r.  A boundary particle takes
+// the pressure and density of its fluid/soft partner (pressure mirroring), its
+// mass is psi_b; two boundary particles exert nothing.  Every factor is
+// symmetric in (a, c) and the vector factors are antisymmetric, so the force
+// c computes on itself from a is the exact IEEE negation.
+template <typename T>
+__device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T rho_a, T P_a, bool isBa, T ma,
+                                           const V4<T> &c, const V4<T> &cv, const V2<T> &cd, const Phys<T> &ph,
+                                           double &fx, double &fy, double &fz)
+{
+    const T dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
+    const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const T q = fsqrt(r2) * ph.inv_h;
+    const T t2 = max((T)2 - q, (T)0);
+    const T g = (q < (T)1) ? ph.gc * ((T)3 * q - (T)4) : -(ph.gc * (t2 * t2)) * frcp(q);
+    const bool isBc = c.w < (T)0;
+    const T mc = fabs(c.w);
+    T Pa = isBa ? cd.y : P_a;
+    T Pc = isBc ? P_a : cd.y;
+    const T ra = isBa ? cd.x : rho_a;
+    const T rc = isBc ? rho_a : cd.x;
+    if (ph.flags & 2u) {   // single boundary pressure term
+        Pa = isBa ? (T)0 : Pa;
+        Pc = isBc ? (T)0 : Pc;
+    }
+    const T mm = ma * mc;
+    T sp = -(mm * (Pa + Pc)) * g;
+    T sv = ((ph.two_nu * mm) * ((T)2 * frcp(ra + rc))) * (g * (r2 * frcp(r2 + ph.eps)));
+    const bool bb = isBa && isBc;
+    const bool novisc = bb || ((ph.flags & 4u) && (isBa || isBc));
+    sp = bb ? (T)0 : sp;
+    sv = novisc ? (T)0 : sv;
+    const T dvx = mv.x - cv.x, dvy = mv.y - cv.y, dvz = mv.z - cv.z;
+    fx += (double)(sp * dx + sv * dvx);
+    fy += (double)(sp * dy + sv * dvy);
+    fz += (double)(sp * dz + sv * dvz);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, Phys<T> ph,
+                                               const uint32_t *__restrict__ cstart,
+                                               const uint32_t *__restrict__ cend, const V2<T> *__restrict__ dens,
+                                               const uint64_t *__restrict__ masks,
+                                               const V4<T> *__restrict__ fspring, V4<T> *__restrict__ force,
+                                               double *__restrict__ fbody)
+{
+    __shared__ Nbhd nb;
+    __shared__ V4<T> cp[kSc];
+    __shared__ V4<T> cvel[kSc];
+    __shared__ V2<T> cden[kSc];
+    __shared__ uint32_t mlds[2 * kScWords][kWave];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t cell = cell_of_block(blockIdx.x, g.nslots);
+    if (cell >= g.nslots) return;
+    const uint32_t s0 = cstart[cell], e0 = cend[cell];
+    if (s0 >= e0) return;
+    load_nbhd(cell, g, cstart, cend, nb, lane);
+    const uint32_t L = nb.total;
+    if (L > (uint32_t)(kMaxWords * kWave)) return;   // flagged by the density pass
+    for (uint32_t t0 = s0; t0 < e0; t0 += kWave) {
+        const uint32_t p = t0 + lane;
+        const bool act = p < e0;
+        const uint32_t pc = act ? p : s0;
+        const V4<T> me = st.pos[pc];
+        const V4<T> mv = st.vel[pc];
+        const V2<T> md = dens[pc];
+        const uint32_t aux = act ? st.aux[pc] : 0u;
+        const bool fs = act && aux_type(aux) != TY_BOUNDARY;
+        const bool kin = act && aux_kin(aux);
+        const bool tgt = fs || kin;
+        if (__ballot(tgt) == 0ull) continue;
+        const T ma = fabs(me.w);
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (uint32_t sc = 0; sc < L; sc += kSc) {
+#pragma unroll
+            for (int q = 0; q < kScWords; ++q) {
+                // out-of-range slots are never hit (their mask bits are 0)
+                const uint32_t v = sc + q * kWave + lane;
+                const uint32_t j = v < L ? cand_index(nb, v) : s0;
+                cp[q * kWave + lane] = st.pos[j];
+                cvel[q * kWave + lane] = st.vel[j];
+                cden[q * kWave + lane] = dens[j];
+            }
+            const uint32_t nw = min((L - sc + kWave - 1) / kWave, (uint32_t)kScWords);
+#pragma unroll
+            for (int q = 0; q < kScWords; ++q) {
+                uint64_t m = 0;
+                if ((uint32_t)q < nw && tgt) m = masks[(size_t)(sc / kWave + q) * n + p];
+                mlds[2 * q][lane] = (uint32_t)m;
+                mlds[2 * q + 1][lane] = (uint32_t)(m >> 32);
+            }
+            __syncthreads();
+            int hw = 0;
+            uint32_t cur = mlds[0][lane];
+            for (;;) {
+                const int k = next_hit(mlds, lane, hw, cur);
+                if (k < 0) break;
+                pair_force<T>(me, mv, md.x, md.y, kin, ma, cp[k], cvel[k], cden[k], ph, fx, fy, fz);
+            }
+            __syncthreads();
+        }
+        if (fs) {
+            double ex = ma * ph.gx, ey = ma * ph.gy, ez = ma * ph.gz;
+            if (aux_type(aux) == TY_SOFT) {
+                const V4<T> s = fspring[aux_index(aux)];
+                ex += s.x;
+                ey += s.y;
+                ez += s.z;
+            }
+            force[p] = V4<T>{(T)(fx + ex), (T)(fy + ey), (T)(fz + ez), (T)0};
+        } else if (kin) {
+            force[p] = V4<T>{(T)fx, (T)fy, (T)fz, (T)0};
+            double *fb = fbody + 3u * aux_index(aux);
+            fb[0] = fx;
+            fb[1] = fy;
+            fb[2] = fz;
+        }
+    }
+}
+
+template <typename T>
+void launch_density(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
+                    const uint32_t *cstart, const uint32_t *cend, V2<T> *dens, uint64_t *masks, uint32_t *err,
+                    unsigned long long *stats)
+{
+    if (!n) return;
+    hipLaunchKernelGGL(k_density<T>, dim3(g.nslots), dim3(64), 0, s, n, st, g, ph, cstart, cend, dens, masks,
+                       err, stats);
+}
+
+template <typename T>
+void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
+                   const uint32_t *cstart, const uint32_t *cend, const V2<T> *dens, const uint64_t *masks,
+                   const V4<T> *fspring, V4<T> *force, double *fbody, uint32_t *err)
+{
+    (void)err;
+    if (!n) return;
+    hipLaunchKernelGGL(k_forces<T>, dim3(g.nslots), dim3(64), 0, s, n, st, g, ph, cstart, cend, dens, masks,
+                       fspring, force, fbody);
+}
+
+template void launch_density<float>(hipStream_t, uint32_t, State<float>, const Grid &, const Phys<float> &,
+                                    const uint32_t *, const uint32_t *, V2<float> *, uint64_t *, uint32_t *,
+                                    unsigned long long *);
+template void launch_density<double>(hipStream_t, uint32_t, State<double>, const Grid &, const Phys<double> &,
+                                     const uint32_t *, const uint32_t *, V2<double> *, uint64_t *, uint32_t *,
+                                     unsigned long long *);
+template void launch_forces<float>(hipStream_t, uint32_t, State<float>, const Grid &, const Phys<float> &,
+                                   const uint32_t *, const uint32_t *, const V2<float> *, const uint64_t *,
+                                   const V4<float> *, V4<float> *, double *, uint32_t *);
+template void launch_forces<double>(hipStream_t, uint32_t, State<double>, const Grid &, const Phys<double> &,
+                                    const uint32_t *, const uint32_t *, const V2<double> *, const uint64_t *,
+                                    const V4<double> *, V4<double> *, double *, uint32_t *);
+
+}  // namespace sphk

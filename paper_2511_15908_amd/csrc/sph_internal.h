@@ -1,0 +1,246 @@
+// Internal declarations shared by the HIP translation units of libsph.
+// Nothing here is part of the C ABI (include/sph.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sphk {
+
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+    T x, y, z, w;
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) V2 {
+    T x, y;
+};
+
+// Per-particle state word: bits 0-1 type, bit 2 kinematic body particle,
+// bits 8-31 index (spring row of a soft particle, body slot of a kinematic
+// boundary particle, object id of a static boundary particle).
+enum : uint32_t { TY_FLUID = 0, TY_SOFT = 1, TY_BOUNDARY = 2 };
+__host__ __device__ inline uint32_t aux_type(uint32_t a) { return a & 3u; }
+__host__ __device__ inline bool aux_kin(uint32_t a) { return (a >> 2) & 1u; }
+__host__ __device__ inline uint32_t aux_index(uint32_t a) { return a >> 8; }
+__host__ __device__ inline uint32_t aux_make(uint32_t type, bool kin, uint32_t index)
+{
+    return (type & 3u) | (kin ? 4u : 0u) | (index << 8);
+}
+
+// error word bits
+enum : uint32_t { ERR_UNSTABLE = 1u, ERR_CAPACITY = 2u };
+
+constexpr int kWave = 64;
+constexpr int kScWords = 4;                 // 64-candidate mask words per staged super-chunk
+constexpr int kSc = kScWords * kWave;       // candidates staged in LDS at once
+constexpr int kMaxWords = 40;               // capacity: kMaxWords*64 candidates per neighbourhood
+
+// The 27 cells around a home cell: the home cell, then 13 pairs of opposite
+// cells, so that a staged super-chunk of candidates holds cells from both
+// sides of the home cell.
+__host__ __device__ inline void stencil_offset(int k, int &dx, int &dy, int &dz)
+{
+    const signed char tab[27][3] = {
+        {0, 0, 0},
+        {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},  {0, 0, 1},   {0, 0, -1},
+        {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0},  {1, 0, 1},   {-1, 0, -1},
+        {1, 0, -1},  {-1, 0, 1},  {0, 1, 1},   {0, -1, -1}, {0, 1, -1},  {0, -1, 1},
+        {1, 1, 1},   {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1},  {-1, 1, -1},
+        {-1, 1, 1},  {1, -1, -1}};
+    dx = tab[k][0];
+    dy = tab[k][1];
+    dz = tab[k][2];
+}
+
+__host__ __device__ inline uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__host__ __device__ inline uint32_t compact3(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v ^ (v >> 2)) & 0x030C30C3u;
+    v = (v ^ (v >> 4)) & 0x0300F00Fu;
+    v = (v ^ (v >> 8)) & 0xFF0000FFu;
+    v = (v ^ (v >> 16)) & 0x000003FFu;
+    return v;
+}
+__host__ __device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z)
+{
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// Uniform grid constants (by value into kernels).
+struct Grid {
+    float lo32[3];
+    float inv_cs32;
+    float R2_32;
+    int dims[3];
+    int bits;
+    uint32_t nslots;
+    double lo64[3];
+    double inv_cs64;
+    double R2_64;
+};
+
+// Physical constants in the run precision T.
+template <typename T>
+struct Phys {
+    T inv_h;
+    T alpha6;     // alpha_3 / 6
+    T gc;         // alpha_3 / (2 h^2)
+    T eps;        // 0.01 h^2
+    T two_nu;     // 2 nu
+    T gx, gy, gz;
+    T dt;
+    T vmax2;      // 0: no speed check
+    double rho0, kp;
+    double psi_scale; // rho0 (for psi init)
+    uint32_t flags;
+};
+
+// Device pointers of one state buffer (sorted order).
+template <typename T>
+struct State {
+    V4<T> *pos;    // x, y, z, w = mass (fluid/soft) or -psi (boundary)
+    V4<T> *vel;    // vx, vy, vz, unused
+    uint32_t *id;  // original particle id
+    uint32_t *aux; // aux word
+};
+
+struct Sort {
+    uint32_t *keys_a, *keys_b, *vals_a, *vals_b;
+    uint32_t *hist;
+    uint32_t nblk;
+};
+
+
+// ---- fast math for FP32 terms (1 ulp hardware sqrt / reciprocal); FP64 stays IEEE ----
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+
+// ---- canonical integer decisions shared by every kernel ----
+
+// Canonical cell coordinate: clamp(floor((x - lo) * inv_cs), 0, d - 1), the
+// subtraction and the product each rounded in the run precision.
+template <typename T>
+__device__ __forceinline__ int cell_coord(T x, T lo, T inv, int d)
+{
+    T t = (x - lo) * inv;
+    T f = floor(t);
+    if (!(f >= (T)0)) return 0;
+    if (f >= (T)d) return d - 1;
+    return (int)f;
+}
+
+template <typename T>
+__device__ __forceinline__ void grid_lo_inv(const Grid &g, T (&lo)[3], T &inv);
+template <>
+__device__ __forceinline__ void grid_lo_inv<float>(const Grid &g, float (&lo)[3], float &inv)
+{
+    lo[0] = g.lo32[0];
+    lo[1] = g.lo32[1];
+    lo[2] = g.lo32[2];
+    inv = g.inv_cs32;
+}
+template <>
+__device__ __forceinline__ void grid_lo_inv<double>(const Grid &g, double (&lo)[3], double &inv)
+{
+    lo[0] = g.lo64[0];
+    lo[1] = g.lo64[1];
+    lo[2] = g.lo64[2];
+    inv = g.inv_cs64;
+}
+
+template <typename T>
+__device__ __forceinline__ bool within_support(const V4<T> &a, const V4<T> &b, T R2)
+{
+#pragma clang fp contract(off)
+    const T dx = b.x - a.x;
+    const T dy = b.y - a.y;
+    const T dz = b.z - a.z;
+    const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    return r2 < R2;
+}
+
+template <typename T>
+__device__ __forceinline__ T grid_R2(const Grid &g);
+template <>
+__device__ __forceinline__ float grid_R2<float>(const Grid &g) { return g.R2_32; }
+template <>
+__device__ __forceinline__ double grid_R2<double>(const Grid &g) { return g.R2_64; }
+
+
+// --- launchers (k_grid.hip) ---
+template <typename T>
+void launch_keys(hipStream_t s, uint32_t n, const V4<T> *pos, const Grid &g, uint32_t *keys);
+void launch_radix_sort(hipStream_t s, uint32_t n, int key_bits, Sort &st, uint32_t **sorted_keys,
+                       uint32_t **sorted_vals);
+void launch_clear_u32(hipStream_t s, uint32_t *p, size_t count);
+template <typename T>
+void launch_reorder(hipStream_t s, uint32_t n, const uint32_t *perm, const uint32_t *keys,
+                    State<T> in, State<T> out, uint32_t *inv_perm, uint32_t *cstart, uint32_t *cend);
+template <typename T>
+void launch_psi_obj(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
+                    const uint32_t *cstart, const uint32_t *cend, const int32_t *obj_of_id);
+
+// --- launchers (k_sums.hip) ---
+template <typename T>
+void launch_density(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
+                    const uint32_t *cstart, const uint32_t *cend, V2<T> *dens, uint64_t *masks,
+                    uint32_t *err, unsigned long long *stats);
+template <typename T>
+void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
+                   const uint32_t *cstart, const uint32_t *cend, const V2<T> *dens,
+                   const uint64_t *masks, const V4<T> *fspring, V4<T> *force, double *fbody,
+                   uint32_t *err);
+
+// --- launchers (k_body.hip) ---
+struct BodyArgs {
+    uint32_t nb;           // body particles (slots)
+    const uint32_t *slot_id;   // slot -> particle id
+    const uint32_t *slot_obj;  // slot -> kinematic object index (0..nk-1)
+    const double *r_loc;       // [3 nb] body-frame offsets
+    double *poses;             // [16 nk]: c[3], q[4], v[3], w[3], pad
+    double *fbody;             // [3 nb]
+    double *partials;          // [6 nblk]
+    const uint32_t *blk_obj;   // [nblk] object of each reduction block
+    const uint32_t *blk_first; // [nblk] first slot of each reduction block
+    const uint32_t *blk_count; // [nblk]
+    const uint32_t *obj_blk0;  // [nk+1] first reduction block of each object
+    uint32_t nblk, nk;
+    double *ring;              // [nk][K][6]
+    uint32_t *ring_count;      // [nk] samples pushed (monotone; reset by sph_reset_smoothing)
+    uint32_t K;
+    double dt;
+};
+template <typename T>
+void launch_place(hipStream_t s, const BodyArgs &b, const uint32_t *inv_perm, State<T> st);
+void launch_wrench(hipStream_t s, const BodyArgs &b);
+void launch_set_pose(hipStream_t s, double *pose_slot, const double c[3], const double q[4],
+                     const double v[3], const double w[3]);
+void launch_reset_ring(hipStream_t s, uint32_t *ring_count_slot);
+
+struct SpringArgs {
+    uint32_t rows;
+    const uint32_t *row_id;   // soft row -> particle id
+    const uint32_t *row_ptr;  // [rows+1]
+    const uint32_t *partner;  // [2 ns] partner particle id
+    const double *prm;        // [3 * 2 ns] L0, k, c per CSR entry
+};
+template <typename T>
+void launch_springs(hipStream_t s, const SpringArgs &a, const uint32_t *inv_perm, State<T> st,
+                    V4<T> *fspring);
+template <typename T>
+void launch_integrate(hipStream_t s, uint32_t n, State<T> st, const V4<T> *force, const Phys<T> &ph,
+                      uint32_t *err);
+
+}  // namespace sphk
