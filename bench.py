@@ -139,7 +139,9 @@ def main():
                    "parallelism": "single GPU"},
         "wrench_hz_plain": a.steps / el,
         "realtime_factor": a.steps * dt / el,
-        "pairs_per_step": {"density": pairs_d, "force": pairs_f, "candidates_tested": cand},
+        "pairs_per_step": {"density": pairs_d, "force": pairs_f, "candidates_tested": cand,
+                           "lane_efficiency_density": pairs_d / max(64 * (s1["iter_density"] - s0["iter_density"]) / a.steps, 1),
+                           "lane_efficiency_force": pairs_f / max(64 * (s1["iter_force"] - s0["iter_force"]) / a.steps, 1)},
         "phase_ms": {k: round(v, 4) for k, v in ms.items()},
         "roofline": roof,
     }

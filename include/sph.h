@@ -175,13 +175,15 @@ sph_status sph_debug_neighbors(sph_ctx *ctx, uint32_t *counts, uint32_t *ids, si
                                size_t *total);
 
 /*
- * Work counters accumulated by the density pass since init, on the device:
- * out[0] neighbour pairs of fluid/soft particles (self included), out[1]
- * neighbour pairs of all particles that receive forces (fluid, soft and
- * kinematic boundary), out[2] candidate pairs tested, out[3] wavefronts run.
+ * Work counters accumulated on the device since init: out[0] neighbour pairs
+ * of fluid/soft particles (self included), out[1] neighbour pairs of all
+ * particles that receive forces (fluid, soft and kinematic boundary), out[2]
+ * candidate pairs tested (64 lanes x candidates per wavefront), out[3]
+ * wavefronts of the density pass, out[4] / out[5] wavefront iterations of the
+ * density / force neighbour loops (each iteration serves up to 64 pairs).
  * Synchronises the stream.
  */
-sph_status sph_get_stats(sph_ctx *ctx, uint64_t out[4]);
+sph_status sph_get_stats(sph_ctx *ctx, uint64_t out[6]);
 
 /* Facts about the context (sizes, grid). */
 sph_status sph_get_info(const sph_ctx *ctx, sph_info *info);

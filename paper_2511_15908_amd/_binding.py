@@ -273,9 +273,10 @@ class Sim:
 
     def stats(self) -> dict:
         """Cumulative device work counters of the density pass."""
-        v = (C.c_uint64 * 4)()
+        v = (C.c_uint64 * 6)()
         self._check(self.L.sph_get_stats(self.ctx, v), "sph_get_stats")
-        return {"pairs_density": v[0], "pairs_force": v[1], "candidates": v[2], "waves": v[3]}
+        return {"pairs_density": v[0], "pairs_force": v[1], "candidates": v[2], "waves": v[3],
+                "iter_density": v[4], "iter_force": v[5]}
 
     def synchronize(self):
         self._check(self.L.sph_synchronize(self.ctx), "sph_synchronize")

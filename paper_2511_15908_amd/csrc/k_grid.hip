@@ -37,8 +37,8 @@ template void launch_keys<double>(hipStream_t, uint32_t, const V4<double> *, con
 
 // ---------------------------------------------------------------- radix sort
 // Tile of 2048 keys per block (256 threads x 8 rounds).  hist is digit-major:
-// hist[d * nblk + b] = count of digit d in block b; after the scan it holds
-// the global output offset of (d, b).
+// hist[d * nblk + b] = count of digit d in block b; after the scans
+// dbase[d] + hist[d * nblk + b] is the global output offset of (d, b).
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_ROUNDS = 8;
@@ -62,53 +62,68 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t *__res
     hist[tid * nblk + blockIdx.x] = h[tid];
 }
 
-// Exclusive scan of hist[0 .. total) by one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t total)
+// Per digit d (one block each): exclusive scan of hist[d][0 .. nblk) in place,
+// digit total into tot[d].
+__global__ __launch_bounds__(256) void k_radix_scan_digit(uint32_t *__restrict__ hist, uint32_t nblk,
+                                                          uint32_t *__restrict__ tot)
 {
-    __shared__ uint32_t wsum[16];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t per = (total + 1023u) / 1024u;
-    const uint32_t b = tid * per;
-    const uint32_t e = min(b + per, total);
-    uint32_t s = 0;
-    for (uint32_t i = b; i < e; ++i) s += hist[i];
-    // inclusive scan of s over the block
-    const uint32_t lane = tid & 63u, wv = tid >> 6;
-    uint32_t inc = s;
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t carry;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    uint32_t *row = hist + (size_t)blockIdx.x * nblk;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < nblk; b0 += 256) {
+        const uint32_t i = b0 + tid;
+        const uint32_t v = i < nblk ? row[i] : 0u;
+        uint32_t inc = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d, 64);
+            if (lane >= (uint32_t)d) inc += t;
+        }
+        if (lane == 63u) wsum[wv] = inc;
+        __syncthreads();
+        uint32_t before = carry;
+        for (uint32_t w = 0; w < wv; ++w) before += wsum[w];
+        if (i < nblk) row[i] = before + inc - v;
+        __syncthreads();
+        if (tid == 255u) carry = before + inc;
+        __syncthreads();
+    }
+    if (tid == 0) tot[blockIdx.x] = carry;
+}
+
+// Exclusive scan of the 256 digit totals (one block).
+__global__ __launch_bounds__(256) void k_radix_scan_tot(uint32_t *__restrict__ tot)
+{
+    __shared__ uint32_t wsum[4];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t v = tot[tid];
+    uint32_t inc = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(inc, d, 64);
+        const uint32_t t = __shfl_up(inc, d, 64);
         if (lane >= (uint32_t)d) inc += t;
     }
     if (lane == 63u) wsum[wv] = inc;
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int w = 0; w < 16; ++w) {
-            uint32_t t = wsum[w];
-            wsum[w] = run;
-            run += t;
-        }
-    }
-    __syncthreads();
-    uint32_t run = wsum[wv] + inc - s;
-    for (uint32_t i = b; i < e; ++i) {
-        uint32_t t = hist[i];
-        hist[i] = run;
-        run += t;
-    }
+    uint32_t before = 0;
+    for (uint32_t w = 0; w < wv; ++w) before += wsum[w];
+    tot[tid] = before + inc - v;
 }
 
 // Stable scatter: elements are ranked in index order (round, wave, lane).
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, uint32_t n, uint32_t shift, const uint32_t *__restrict__ hist, uint32_t nblk)
+    uint32_t *__restrict__ vout, uint32_t n, uint32_t shift, const uint32_t *__restrict__ hist, uint32_t nblk,
+    const uint32_t *__restrict__ dbase)
 {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[RS_THREADS / 64][256];
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, wv = tid >> 6;
-    base[tid] = hist[tid * nblk + blockIdx.x];
+    base[tid] = dbase[tid] + hist[tid * nblk + blockIdx.x];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
     const uint32_t tile = blockIdx.x * RS_TILE;
     for (int r = 0; r < RS_ROUNDS; ++r) {
@@ -162,9 +177,10 @@ void launch_radix_sort(hipStream_t s, uint32_t n, int key_bits, Sort &st, uint32
     for (int p = 0; p < passes; ++p) {
         const uint32_t shift = 8u * (uint32_t)p;
         hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(RS_THREADS), 0, s, kin, n, shift, st.hist, nblk);
-        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, st.hist, 256u * nblk);
+        hipLaunchKernelGGL(k_radix_scan_digit, dim3(256), dim3(256), 0, s, st.hist, nblk, st.dbase);
+        hipLaunchKernelGGL(k_radix_scan_tot, dim3(1), dim3(256), 0, s, st.dbase);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(RS_THREADS), 0, s, kin, vin, kout, vout, n,
-                           shift, st.hist, nblk);
+                           shift, st.hist, nblk, st.dbase);
         // next pass reads what this one wrote
         uint32_t *nk = (kout == st.keys_b) ? st.keys_a : st.keys_b;
         uint32_t *nv = (vout == st.vals_b) ? st.vals_a : st.vals_b;

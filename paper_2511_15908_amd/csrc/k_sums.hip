@@ -7,22 +7,37 @@
 // Work decomposition (gfx950, wave64): one workgroup = one wavefront per
 // occupied grid cell (cell size 2h, so all neighbours of a particle lie in the
 // 27 cells around its own).  Each lane owns one particle of the home cell.
-// The 27 neighbour cells form one virtual candidate list; it is staged through
-// LDS 256 candidates at a time with coalesced loads of the sorted SoA arrays,
-// every lane tests every staged candidate (LDS broadcast reads), and the
-// per-lane hit masks (one bit per candidate) drive a compacted per-lane loop
-// that evaluates the kernel only for true neighbours.  The density pass writes
-// the masks to HBM; the force pass reuses them instead of testing again.
+// The candidates (particles of the 27 cells) are visited in S super-chunks of
+// at most kScWords*64: super-chunk s holds every S-th particle of every cell
+// (in-cell index = s mod S).  Each super-chunk is staged through LDS with
+// coalesced loads of the sorted SoA arrays and spreads each lane's neighbours
+// evenly, so the per-lane hit counts of a super-chunk are close to their mean
+// and the compacted per-lane loop below keeps most lanes busy.
+//  - Density pass: every lane tests every staged candidate (LDS broadcast
+//    reads) and keeps one 64-bit hit mask per word; the kernel sum runs over
+//    the set bits only.  The masks go to HBM.
+//  - Force pass: restages the same super-chunks (position, velocity,
+//    density) and walks the stored masks, so no pair is tested twice.
 // All sums accumulate FP32 terms in FP64 registers; no atomics, so results are
 // bitwise reproducible.
 #include "sph_internal.h"
 
 namespace sphk {
 
+#ifdef SPH_DENSITY_MIN_WAVES
+#define SPH_DENSITY_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SPH_DENSITY_MIN_WAVES)))
+#else
+#define SPH_DENSITY_OCCUPANCY
+#endif
+
 struct Nbhd {
-    uint32_t start[32];   // first sorted index of each stencil cell
-    uint32_t pre[32];     // exclusive prefix of the cell counts; entries 27..31 = UINT32_MAX
-    uint32_t total;       // candidates in the 27 cells
+    uint32_t start[27];   // first sorted index of each stencil cell
+    uint32_t cnt[27];     // particles in each stencil cell
+    uint32_t stride;      // S: number of super-chunks
+    uint32_t nw;          // candidate words of the neighbourhood
+    uint32_t wbase[kMaxWords + 1];  // first word of each super-chunk (S <= kMaxWords)
+    uint32_t pre[32];     // current super-chunk: exclusive prefix of per-cell counts, padded
+    uint32_t size;        // current super-chunk: candidates
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD runs of 64
@@ -34,7 +49,23 @@ __device__ __forceinline__ uint32_t cell_of_block(uint32_t b, uint32_t nslots)
     return grp * 512u + (r & 7u) * 64u + (r >> 3);
 }
 
-__device__ __forceinline__ void load_nbhd(uint32_t cell, const Grid &g, const uint32_t *__restrict__ cs,
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Particles of cell k (count c) in super-chunk s of S.
+__device__ __forceinline__ uint32_t share(uint32_t c, uint32_t s, uint32_t S)
+{
+    return c > s ? (c - s + S - 1u) / S : 0u;
+}
+
+// Load the 27 cells around `cell`, choose S so every super-chunk fits
+// kScWords words, and lay the super-chunks out in words.  Returns false
+// (uniformly) when the neighbourhood exceeds kMaxWords words.
+__device__ __forceinline__ bool load_nbhd(uint32_t cell, const Grid &g, const uint32_t *__restrict__ cs,
                                           const uint32_t *__restrict__ ce, Nbhd &nb, uint32_t lane)
 {
     const int cx = (int)compact3(cell), cy = (int)compact3(cell >> 1), cz = (int)compact3(cell >> 2);
@@ -48,30 +79,61 @@ __device__ __forceinline__ void load_nbhd(uint32_t cell, const Grid &g, const ui
             st = cs[k];
             cnt = ce[k] - st;
         }
+        nb.start[lane] = st;
+        nb.cnt[lane] = cnt;
     }
-    uint32_t inc = cnt;
+    const uint32_t L = wave_sum_u32(cnt);
+    const uint32_t cap = (uint32_t)(kScWords * kWave - 27);
+    const uint32_t S = (L + cap - 1u) / cap;     // >= 1: the home cell is occupied
+    if (S > (uint32_t)kMaxWords) return false;
+    // words of each super-chunk: lane s < S computes its own size
+    uint32_t words = 0;
+    for (uint32_t k = 0; k < 27u; ++k) {
+        const uint32_t ck = __shfl(cnt, (int)k, 64);
+        words += (lane < S) ? share(ck, lane, S) : 0u;
+    }
+    words = (words + (uint32_t)kWave - 1u) / (uint32_t)kWave;
+    uint32_t inc = words;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= (uint32_t)d) inc += t;
+    }
+    if (lane < S) nb.wbase[lane] = inc - words;
+    const uint32_t NW = __shfl(inc, 63, 64);
+    if (lane == 0) {
+        nb.stride = S;
+        nb.nw = NW;
+        nb.wbase[S] = NW;
+    }
+    __syncthreads();
+    return NW <= (uint32_t)kMaxWords;
+}
+
+// Prefix of the per-cell shares of super-chunk s (all lanes participate).
+__device__ __forceinline__ void begin_chunk(Nbhd &nb, uint32_t s, uint32_t lane)
+{
+    const uint32_t c = (lane < 27u) ? share(nb.cnt[lane], s, nb.stride) : 0u;
+    uint32_t inc = c;
 #pragma unroll
     for (int d = 1; d < 32; d <<= 1) {
         const uint32_t t = __shfl_up(inc, d, 64);
         if (lane >= (uint32_t)d) inc += t;
     }
-    if (lane < 32u) {
-        nb.start[lane] = st;
-        nb.pre[lane] = lane < 27u ? inc - cnt : 0xffffffffu;
-    }
-    if (lane == 26u) nb.total = inc;
+    if (lane < 32u) nb.pre[lane] = lane < 27u ? inc - c : 0xffffffffu;
+    if (lane == 26u) nb.size = inc;
     __syncthreads();
 }
 
-// Sorted index of virtual candidate v (0 <= v < total): the cell is the
-// largest k with pre[k] <= v (pre is non-decreasing, padded with UINT32_MAX).
-__device__ __forceinline__ uint32_t cand_index(const Nbhd &nb, uint32_t v)
+// Sorted index of candidate v (< size) of super-chunk s: cell k = largest
+// with pre[k] <= v, in-cell index s + S (v - pre[k]).
+__device__ __forceinline__ uint32_t chunk_index(const Nbhd &nb, uint32_t s, uint32_t v)
 {
     uint32_t k = 0;
 #pragma unroll
     for (uint32_t step = 16; step >= 1; step >>= 1)
         if (nb.pre[k + step] <= v) k += step;
-    return nb.start[k] + (v - nb.pre[k]);
+    return nb.start[k] + s + nb.stride * (v - nb.pre[k]);
 }
 
 // One 64-candidate word of hit bits for this lane's particle.
@@ -79,17 +141,18 @@ template <typename T>
 __device__ __forceinline__ uint64_t hit_word(const V4<T> &me, const V4<T> *cand, T R2)
 {
     uint32_t lo = 0, hi = 0;
-#pragma unroll
+#pragma unroll 16
     for (int b = 0; b < 32; ++b) lo |= (uint32_t)within_support<T>(me, cand[b], R2) << b;
-#pragma unroll
+#pragma unroll 16
     for (int b = 0; b < 32; ++b) hi |= (uint32_t)within_support<T>(me, cand[32 + b], R2) << b;
     return ((uint64_t)hi << 32) | lo;
 }
 
 // Next set bit of this lane's staged masks (half-words in LDS); -1 when done.
+template <int W>
 __device__ __forceinline__ int next_hit(uint32_t (*mlds)[kWave], uint32_t lane, int &hw, uint32_t &cur)
 {
-    while (cur == 0u && hw < 2 * kScWords - 1) {
+    while (cur == 0u && hw < 2 * W - 1) {
         ++hw;
         cur = mlds[hw][lane];
     }
@@ -102,75 +165,81 @@ __device__ __forceinline__ int next_hit(uint32_t (*mlds)[kWave], uint32_t lane, 
 // ------------------------------------------------------------------ density
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_density(uint32_t n, State<T> st, Grid g, Phys<T> ph,
+__global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n, State<T> st, Grid g, Phys<T> ph,
                                                 const uint32_t *__restrict__ cstart,
                                                 const uint32_t *__restrict__ cend, V2<T> *__restrict__ dens,
                                                 uint64_t *__restrict__ masks, uint32_t *__restrict__ err,
                                                 unsigned long long *__restrict__ stats)
 {
     __shared__ Nbhd nb;
-    __shared__ V4<T> cand[kSc];
+    __shared__ V4<T> cand[kScWords * kWave];
     __shared__ uint32_t mlds[2 * kScWords][kWave];
     const uint32_t lane = threadIdx.x;
     const uint32_t cell = cell_of_block(blockIdx.x, g.nslots);
     if (cell >= g.nslots) return;
     const uint32_t s0 = cstart[cell], e0 = cend[cell];
     if (s0 >= e0) return;
-    load_nbhd(cell, g, cstart, cend, nb, lane);
-    const uint32_t L = nb.total;
-    if (L > (uint32_t)(kMaxWords * kWave)) {
+    if (!load_nbhd(cell, g, cstart, cend, nb, lane)) {
         if (lane == 0) atomicOr(err, ERR_CAPACITY);
         return;
     }
+    const uint32_t S = nb.stride, NW = nb.nw;
     const T R2 = grid_R2<T>(g);
+    const T inf = __builtin_huge_val();
     for (uint32_t t0 = s0; t0 < e0; t0 += kWave) {
         const uint32_t p = t0 + lane;
         const bool act = p < e0;
         const uint32_t pc = act ? p : s0;
         V4<T> me = st.pos[pc];
         const uint32_t aux = act ? st.aux[pc] : 0u;
-        {
-            const T inf = __builtin_huge_val();
-            me.x = act ? me.x : inf;
-            me.y = act ? me.y : inf;
-            me.z = act ? me.z : inf;
-        }
+        me.x = act ? me.x : inf;
+        me.y = act ? me.y : inf;
+        me.z = act ? me.z : inf;
         const bool fs = act && aux_type(aux) != TY_BOUNDARY;
         const bool want = act && (fs || aux_kin(aux));
         if (__ballot(want) == 0ull) continue;
         double acc = 0.0;
-        uint32_t npair = 0;
-        for (uint32_t sc = 0; sc < L; sc += kSc) {
+        uint32_t npair = 0, witer = 0;
+        for (uint32_t sc = 0; sc < S; ++sc) {
+            begin_chunk(nb, sc, lane);
+            const uint32_t size = nb.size;
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) {
-                const uint32_t v = sc + q * kWave + lane;
-                const bool in = v < L;
-                const uint32_t j = in ? cand_index(nb, v) : s0;
-                V4<T> c = st.pos[j];
-                const T inf = __builtin_huge_val();
+                const uint32_t v = q * kWave + lane;
+                const bool in = v < size;
+                V4<T> c = st.pos[in ? chunk_index(nb, sc, v) : s0];
                 c.x = in ? c.x : inf;
                 c.y = in ? c.y : inf;
                 c.z = in ? c.z : inf;
-                cand[q * kWave + lane] = c;
+                cand[v] = c;
             }
             __syncthreads();
-            const uint32_t nw = min((L - sc + kWave - 1) / kWave, (uint32_t)kScWords);
+            const uint32_t nws = nb.wbase[sc + 1] - nb.wbase[sc];
+            const uint32_t w0 = nb.wbase[sc];
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) {
                 uint64_t m = 0;
-                if ((uint32_t)q < nw) {
+                if ((uint32_t)q < nws) {
                     m = hit_word<T>(me, cand + q * kWave, R2);
-                    if (act) masks[(size_t)(sc / kWave + q) * n + p] = m;
+                    if (act) masks[(size_t)(w0 + q) * n + p] = m;
                     npair += want ? (uint32_t)__popcll(m) : 0u;
                 }
                 mlds[2 * q][lane] = fs ? (uint32_t)m : 0u;
                 mlds[2 * q + 1][lane] = fs ? (uint32_t)(m >> 32) : 0u;
             }
+            {
+                uint32_t mine = 0;
+#pragma unroll
+                for (int h = 0; h < 2 * kScWords; ++h) mine += __popc(mlds[h][lane]);
+#pragma unroll
+                for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
+                witer += mine;
+            }
             // kernel sum over this lane's neighbours among the staged candidates
             int hw = 0;
             uint32_t cur = mlds[0][lane];
             for (;;) {
-                const int k = next_hit(mlds, lane, hw, cur);
+                const int k = next_hit<kScWords>(mlds, lane, hw, cur);
                 if (k < 0) break;
                 const V4<T> c = cand[k];
                 const T dx = c.x - me.x, dy = c.y - me.y, dz = c.z - me.z;
@@ -185,18 +254,16 @@ __global__ __launch_bounds__(64) void k_density(uint32_t n, State<T> st, Grid g,
         }
         {
             // step statistics: neighbour pairs of density targets, of force
-            // targets, candidate tests and target chunks
+            // targets, candidate tests, wavefronts, loop iterations
             uint32_t nd = fs ? npair : 0u, nf = npair;
-#pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) {
-                nd += __shfl_xor(nd, m, 64);
-                nf += __shfl_xor(nf, m, 64);
-            }
+            nd = wave_sum_u32(nd);
+            nf = wave_sum_u32(nf);
             if (lane == 0) {
                 atomicAdd(stats + 0, (unsigned long long)nd);
                 atomicAdd(stats + 1, (unsigned long long)nf);
-                atomicAdd(stats + 2, (unsigned long long)L * kWave);
+                atomicAdd(stats + 2, (unsigned long long)NW * kWave * kWave);
                 atomicAdd(stats + 3, 1ull);
+                atomicAdd(stats + 4, (unsigned long long)witer);
             }
         }
         if (act) {
@@ -259,21 +326,20 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, 
                                                const uint32_t *__restrict__ cend, const V2<T> *__restrict__ dens,
                                                const uint64_t *__restrict__ masks,
                                                const V4<T> *__restrict__ fspring, V4<T> *__restrict__ force,
-                                               double *__restrict__ fbody)
+                                               double *__restrict__ fbody, unsigned long long *__restrict__ stats)
 {
     __shared__ Nbhd nb;
-    __shared__ V4<T> cp[kSc];
-    __shared__ V4<T> cvel[kSc];
-    __shared__ V2<T> cden[kSc];
+    __shared__ V4<T> cp[kScWords * kWave];
+    __shared__ V4<T> cvel[kScWords * kWave];
+    __shared__ V2<T> cden[kScWords * kWave];
     __shared__ uint32_t mlds[2 * kScWords][kWave];
     const uint32_t lane = threadIdx.x;
     const uint32_t cell = cell_of_block(blockIdx.x, g.nslots);
     if (cell >= g.nslots) return;
     const uint32_t s0 = cstart[cell], e0 = cend[cell];
     if (s0 >= e0) return;
-    load_nbhd(cell, g, cstart, cend, nb, lane);
-    const uint32_t L = nb.total;
-    if (L > (uint32_t)(kMaxWords * kWave)) return;   // flagged by the density pass
+    if (!load_nbhd(cell, g, cstart, cend, nb, lane)) return;   // flagged by the density pass
+    const uint32_t S = nb.stride;
     for (uint32_t t0 = s0; t0 < e0; t0 += kWave) {
         const uint32_t p = t0 + lane;
         const bool act = p < e0;
@@ -288,41 +354,54 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, 
         if (__ballot(tgt) == 0ull) continue;
         const T ma = fabs(me.w);
         double fx = 0.0, fy = 0.0, fz = 0.0;
-        for (uint32_t sc = 0; sc < L; sc += kSc) {
+        uint32_t witer = 0;
+        for (uint32_t sc = 0; sc < S; ++sc) {
+            begin_chunk(nb, sc, lane);
+            const uint32_t size = nb.size;
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) {
-                // out-of-range slots are never hit (their mask bits are 0)
-                const uint32_t v = sc + q * kWave + lane;
-                const uint32_t j = v < L ? cand_index(nb, v) : s0;
-                cp[q * kWave + lane] = st.pos[j];
-                cvel[q * kWave + lane] = st.vel[j];
-                cden[q * kWave + lane] = dens[j];
+                // slots past the chunk are never hit (their mask bits are 0)
+                const uint32_t v = q * kWave + lane;
+                const uint32_t j = v < size ? chunk_index(nb, sc, v) : s0;
+                cp[v] = st.pos[j];
+                cvel[v] = st.vel[j];
+                cden[v] = dens[j];
             }
-            const uint32_t nw = min((L - sc + kWave - 1) / kWave, (uint32_t)kScWords);
+            const uint32_t nws = nb.wbase[sc + 1] - nb.wbase[sc];
+            const uint32_t w0 = nb.wbase[sc];
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) {
                 uint64_t m = 0;
-                if ((uint32_t)q < nw && tgt) m = masks[(size_t)(sc / kWave + q) * n + p];
+                if ((uint32_t)q < nws && tgt) m = masks[(size_t)(w0 + q) * n + p];
                 mlds[2 * q][lane] = (uint32_t)m;
                 mlds[2 * q + 1][lane] = (uint32_t)(m >> 32);
             }
             __syncthreads();
+            {
+                uint32_t mine = 0;
+#pragma unroll
+                for (int h = 0; h < 2 * kScWords; ++h) mine += __popc(mlds[h][lane]);
+#pragma unroll
+                for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
+                witer += mine;
+            }
             int hw = 0;
             uint32_t cur = mlds[0][lane];
             for (;;) {
-                const int k = next_hit(mlds, lane, hw, cur);
+                const int k = next_hit<kScWords>(mlds, lane, hw, cur);
                 if (k < 0) break;
                 pair_force<T>(me, mv, md.x, md.y, kin, ma, cp[k], cvel[k], cden[k], ph, fx, fy, fz);
             }
             __syncthreads();
         }
+        if (lane == 0) atomicAdd(stats + 5, (unsigned long long)witer);
         if (fs) {
             double ex = ma * ph.gx, ey = ma * ph.gy, ez = ma * ph.gz;
             if (aux_type(aux) == TY_SOFT) {
-                const V4<T> s = fspring[aux_index(aux)];
-                ex += s.x;
-                ey += s.y;
-                ez += s.z;
+                const V4<T> sp = fspring[aux_index(aux)];
+                ex += sp.x;
+                ey += sp.y;
+                ez += sp.z;
             }
             force[p] = V4<T>{(T)(fx + ex), (T)(fy + ey), (T)(fz + ez), (T)0};
         } else if (kin) {
@@ -348,12 +427,12 @@ void launch_density(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const
 template <typename T>
 void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
                    const uint32_t *cstart, const uint32_t *cend, const V2<T> *dens, const uint64_t *masks,
-                   const V4<T> *fspring, V4<T> *force, double *fbody, uint32_t *err)
+                   const V4<T> *fspring, V4<T> *force, double *fbody, uint32_t *err, unsigned long long *stats)
 {
     (void)err;
     if (!n) return;
     hipLaunchKernelGGL(k_forces<T>, dim3(g.nslots), dim3(64), 0, s, n, st, g, ph, cstart, cend, dens, masks,
-                       fspring, force, fbody);
+                       fspring, force, fbody, stats);
 }
 
 template void launch_density<float>(hipStream_t, uint32_t, State<float>, const Grid &, const Phys<float> &,
@@ -364,9 +443,9 @@ template void launch_density<double>(hipStream_t, uint32_t, State<double>, const
                                      unsigned long long *);
 template void launch_forces<float>(hipStream_t, uint32_t, State<float>, const Grid &, const Phys<float> &,
                                    const uint32_t *, const uint32_t *, const V2<float> *, const uint64_t *,
-                                   const V4<float> *, V4<float> *, double *, uint32_t *);
+                                   const V4<float> *, V4<float> *, double *, uint32_t *, unsigned long long *);
 template void launch_forces<double>(hipStream_t, uint32_t, State<double>, const Grid &, const Phys<double> &,
                                     const uint32_t *, const uint32_t *, const V2<double> *, const uint64_t *,
-                                    const V4<double> *, V4<double> *, double *, uint32_t *);
+                                    const V4<double> *, V4<double> *, double *, uint32_t *, unsigned long long *);
 
 }  // namespace sphk

@@ -288,6 +288,7 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
     c->sort.vals_a = cv.take<uint32_t>(n * 4);
     c->sort.vals_b = cv.take<uint32_t>(n * 4);
     c->sort.hist = cv.take<uint32_t>((size_t)256 * std::max<uint32_t>(pl.nblk_sort, 1) * 4);
+    c->sort.dbase = cv.take<uint32_t>(256 * 4);
     c->sort.nblk = pl.nblk_sort;
     c->inv_perm = cv.take<uint32_t>(n * 4);
     c->cstart = cv.take<uint32_t>((size_t)pl.nslots * 4);
@@ -313,7 +314,7 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
     c->ring = cv.take<double>((size_t)pl.nk * pl.K * 6 * 8);
     c->ring_count = cv.take<uint32_t>((size_t)pl.nk * 4);
     c->err = cv.take<uint32_t>(16);
-    c->stats = cv.take<unsigned long long>(4 * 8);
+    c->stats = cv.take<unsigned long long>(8 * 8);
     c->obj_of_id = cv.take<int32_t>(n * 4);
     *total = cv.off + 256;
 }
@@ -403,7 +404,7 @@ void one_step(sph_ctx *c)
     prof_mark(c, 5, false);
     prof_mark(c, 6, true);
     launch_forces<T>(s, c->n, st, c->grid, phys<T>(c), c->cstart, c->cend, (const V2<T> *)c->dens, c->masks,
-                     (const V4<T> *)c->fspring, (V4<T> *)c->force, c->fbody, c->err);
+                     (const V4<T> *)c->fspring, (V4<T> *)c->force, c->fbody, c->err, c->stats);
     prof_mark(c, 6, false);
     prof_mark(c, 7, true);
     launch_wrench(s, ba);
@@ -562,7 +563,7 @@ sph_status upload(sph_ctx *c, const sph_scene *s)
     // zero what must start at zero (fill kernels, no memset nodes)
     launch_clear_u32(st, c->ring_count, c->nk);
     launch_clear_u32(st, c->err, 4);
-    launch_clear_u32(st, (uint32_t *)c->stats, 8);
+    launch_clear_u32(st, (uint32_t *)c->stats, 16);
     launch_clear_u32(st, (uint32_t *)c->dens, (size_t)n * 2 * sizeof(T) / 4);
     launch_clear_u32(st, (uint32_t *)c->force, (size_t)n * 4 * sizeof(T) / 4);
     launch_clear_u32(st, (uint32_t *)c->fspring, (size_t)c->rows * 4 * sizeof(T) / 4);
@@ -911,33 +912,57 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t *counts, uint32_t *ids_out, size_t 
         if (aux_type(a) == TY_BOUNDARY && !aux_kin(a)) continue;
         const uint32_t home = keys[p];
         const int cx = (int)compact3(home), cy = (int)compact3(home >> 1), cz = (int)compact3(home >> 2);
-        uint32_t start[27], pre[28];
-        pre[0] = 0;
+        uint32_t start[27], cnt[27], L = 0;
         for (int k = 0; k < 27; ++k) {
             int ox, oy, oz;
             stencil_offset(k, ox, oy, oz);
             const int nx = cx + ox, ny = cy + oy, nz = cz + oz;
-            uint32_t stt = 0, cnt = 0;
+            uint32_t stt = 0, ct = 0;
             if (nx >= 0 && ny >= 0 && nz >= 0 && nx < g.dims[0] && ny < g.dims[1] && nz < g.dims[2]) {
                 const uint32_t key = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
                 stt = cs[key];
-                cnt = ce[key] - stt;
+                ct = ce[key] - stt;
             }
             start[k] = stt;
-            pre[k + 1] = pre[k] + cnt;
+            cnt[k] = ct;
+            L += ct;
         }
-        const uint32_t L = pre[27];
-        if (L > (uint32_t)(kMaxWords * kWave)) continue;
+        // super-chunk layout of the density/force passes: S chunks, chunk s
+        // holds in-cell indices = s mod S of every cell, words laid out in order
+        const uint32_t cap = (uint32_t)(kScWords * kWave - 27);
+        const uint32_t S = (L + cap - 1) / cap;
         std::vector<uint32_t> &lst = lists[ids[p]];
-        for (uint32_t w = 0; w * 64 < L; ++w) {
-            const uint64_t m = masks[(size_t)w * n + p];
-            for (int b = 0; b < 64; ++b) {
-                if (!((m >> b) & 1ull)) continue;
-                const uint32_t v = w * 64 + (uint32_t)b;
-                int k = 0;
-                while (k < 26 && pre[k + 1] <= v) ++k;
-                lst.push_back(ids[start[k] + (v - pre[k])]);
+        uint32_t w0 = 0;
+        bool over = S > (uint32_t)kMaxWords;
+        std::vector<std::pair<uint32_t, uint32_t>> found;
+        for (uint32_t sc = 0; sc < S && !over; ++sc) {
+            uint32_t pre[28];
+            pre[0] = 0;
+            for (int k = 0; k < 27; ++k) {
+                const uint32_t c = cnt[k] > sc ? (cnt[k] - sc + S - 1) / S : 0u;
+                pre[k + 1] = pre[k] + c;
             }
+            const uint32_t size = pre[27];
+            const uint32_t nws = (size + kWave - 1) / kWave;
+            if (w0 + nws > (uint32_t)kMaxWords) {
+                over = true;
+                break;
+            }
+            for (uint32_t q = 0; q < nws; ++q) {
+                const uint64_t m = masks[(size_t)(w0 + q) * n + p];
+                for (int b = 0; b < 64; ++b) {
+                    if (!((m >> b) & 1ull)) continue;
+                    const uint32_t v = q * kWave + (uint32_t)b;
+                    int k = 0;
+                    while (k < 26 && pre[k + 1] <= v) ++k;
+                    lst.push_back(ids[start[k] + sc + S * (v - pre[k])]);
+                }
+            }
+            w0 += nws;
+        }
+        if (over) {
+            lst.clear();
+            continue;
         }
         std::sort(lst.begin(), lst.end());
     }
@@ -975,14 +1000,14 @@ sph_status sph_debug_neighbors(sph_ctx *ctx, uint32_t *counts, uint32_t *ids, si
                                  : debug_nbrs_t<float>(ctx, counts, ids, cap, total);
 }
 
-sph_status sph_get_stats(sph_ctx *ctx, uint64_t out[4])
+sph_status sph_get_stats(sph_ctx *ctx, uint64_t out[6])
 {
     if (!ctx || !out) return SPH_ERR_ARG;
     if (ctx->dead) return SPH_ERR_STATE;
-    unsigned long long v[4] = {0, 0, 0, 0};
+    unsigned long long v[6] = {0, 0, 0, 0, 0, 0};
     HIPCHK(ctx, hipMemcpyAsync(v, ctx->stats, sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    for (int k = 0; k < 4; ++k) out[k] = (uint64_t)v[k];
+    for (int k = 0; k < 6; ++k) out[k] = (uint64_t)v[k];
     return SPH_OK;
 }
 
@@ -999,7 +1024,7 @@ sph_status sph_get_info(const sph_ctx *ctx, sph_info *info)
     for (int a = 0; a < 3; ++a) f.grid_dims[a] = (uint32_t)ctx->grid.dims[a];
     f.grid_bits = (uint32_t)ctx->grid.bits;
     f.cell_slots = ctx->grid.nslots;
-    f.max_candidates = (uint32_t)(kMaxWords * kWave);
+    f.max_candidates = (uint32_t)(kMaxWords * kWave);   // in cell-aligned words
     f.steps = ctx->steps;
     f.cell_size = ctx->cell_size;
     *info = f;

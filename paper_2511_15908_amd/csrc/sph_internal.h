@@ -32,9 +32,12 @@ __host__ __device__ inline uint32_t aux_make(uint32_t type, bool kin, uint32_t i
 enum : uint32_t { ERR_UNSTABLE = 1u, ERR_CAPACITY = 2u };
 
 constexpr int kWave = 64;
-constexpr int kScWords = 4;                 // 64-candidate mask words per staged super-chunk
-constexpr int kSc = kScWords * kWave;       // candidates staged in LDS at once
-constexpr int kMaxWords = 40;               // capacity: kMaxWords*64 candidates per neighbourhood
+#ifndef SPH_SC_WORDS
+#define SPH_SC_WORDS 2
+#endif
+// 64-candidate mask words per super-chunk staged in LDS
+constexpr int kScWords = SPH_SC_WORDS;
+constexpr int kMaxWords = 64;               // capacity: candidate words per neighbourhood
 
 // The 27 cells around a home cell: the home cell, then 13 pairs of opposite
 // cells, so that a staged super-chunk of candidates holds cells from both
@@ -117,6 +120,7 @@ struct State {
 struct Sort {
     uint32_t *keys_a, *keys_b, *vals_a, *vals_b;
     uint32_t *hist;
+    uint32_t *dbase;   // 256 digit bases
     uint32_t nblk;
 };
 
@@ -201,7 +205,7 @@ template <typename T>
 void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
                    const uint32_t *cstart, const uint32_t *cend, const V2<T> *dens,
                    const uint64_t *masks, const V4<T> *fspring, V4<T> *force, double *fbody,
-                   uint32_t *err);
+                   uint32_t *err, unsigned long long *stats);
 
 // --- launchers (k_body.hip) ---
 struct BodyArgs {
