@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--n-fluid", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -81,6 +83,15 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.calibrate_copy:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}))
+        return
     t0 = time.perf_counter()
     sc = scenes.coupled_1m(n_fluid=a.n_fluid)
     log(f"scene {sc.name}: {sc.counts()} built in {time.perf_counter() - t0:.1f} s", a.quiet)
@@ -145,6 +156,13 @@ def main():
         "phase_ms": {k: round(v, 4) for k, v in ms.items()},
         "roofline": roof,
     }
+    # cell occupancy of the last step (targets beyond 64 need a second wavefront pass)
+    keys = sim.read("key")
+    cnt = np.bincount(keys)
+    cnt = cnt[cnt > 0]
+    out["cells"] = {"occupied": int(cnt.size), "mean": float(cnt.mean()), "max": int(cnt.max()),
+                    "over64": int((cnt > 64).sum()),
+                    "passes_per_target": float(np.ceil(cnt / 64).sum() * 64 / cnt.sum())}
     log(json.dumps(out, indent=1), a.quiet)
     if not a.no_cpu_baseline:
         log("timing the CPU oracle on one step of the same scene ...", a.quiet)

@@ -136,15 +136,23 @@ __device__ __forceinline__ uint32_t chunk_index(const Nbhd &nb, uint32_t s, uint
     return nb.start[k] + s + nb.stride * (v - nb.pre[k]);
 }
 
-// One 64-candidate word of hit bits for this lane's particle.
+// Hit bits of this lane's particle against nv (<= 32) staged candidates;
+// nv is uniform, so empty slots of a super-chunk are never tested.
 template <typename T>
-__device__ __forceinline__ uint64_t hit_word(const V4<T> &me, const V4<T> *cand, T R2)
+__device__ __forceinline__ uint32_t hit_bits(const V4<T> &me, const V4<T> *cand, uint32_t nv, T R2)
 {
-    uint32_t lo = 0, hi = 0;
-#pragma unroll 16
-    for (int b = 0; b < 32; ++b) lo |= (uint32_t)within_support<T>(me, cand[b], R2) << b;
-#pragma unroll 16
-    for (int b = 0; b < 32; ++b) hi |= (uint32_t)within_support<T>(me, cand[32 + b], R2) << b;
+    uint32_t bits = 0;
+#pragma unroll 8
+    for (uint32_t b = 0; b < nv; ++b) bits |= (uint32_t)within_support<T>(me, cand[b], R2) << b;
+    return bits;
+}
+
+// One 64-candidate word of hit bits (the first nv slots are candidates).
+template <typename T>
+__device__ __forceinline__ uint64_t hit_word(const V4<T> &me, const V4<T> *cand, uint32_t nv, T R2)
+{
+    const uint32_t lo = hit_bits<T>(me, cand, nv < 32u ? nv : 32u, R2);
+    const uint32_t hi = nv > 32u ? hit_bits<T>(me, cand + 32, nv - 32u, R2) : 0u;
     return ((uint64_t)hi << 32) | lo;
 }
 
@@ -199,10 +207,11 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         const bool want = act && (fs || aux_kin(aux));
         if (__ballot(want) == 0ull) continue;
         double acc = 0.0;
-        uint32_t npair = 0, witer = 0;
+        uint32_t npair = 0, witer = 0, ncand = 0;
         for (uint32_t sc = 0; sc < S; ++sc) {
             begin_chunk(nb, sc, lane);
             const uint32_t size = nb.size;
+            ncand += size;
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) {
                 const uint32_t v = q * kWave + lane;
@@ -220,7 +229,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
             for (int q = 0; q < kScWords; ++q) {
                 uint64_t m = 0;
                 if ((uint32_t)q < nws) {
-                    m = hit_word<T>(me, cand + q * kWave, R2);
+                    const uint32_t nv = min(size - (uint32_t)q * kWave, (uint32_t)kWave);
+                    m = hit_word<T>(me, cand + q * kWave, nv, R2);
                     if (act) masks[(size_t)(w0 + q) * n + p] = m;
                     npair += want ? (uint32_t)__popcll(m) : 0u;
                 }
@@ -236,6 +246,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                 witer += mine;
             }
             // kernel sum over this lane's neighbours among the staged candidates
+            // (~1/S of them: summed in T, then in FP64)
+            T part = (T)0;
             int hw = 0;
             uint32_t cur = mlds[0][lane];
             for (;;) {
@@ -248,8 +260,9 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                 const T t2 = max((T)2 - q, (T)0);
                 const T t1 = max((T)1 - q, (T)0);
                 const T w = ph.alpha6 * (t2 * t2 * t2 - (T)4 * (t1 * t1 * t1));
-                acc += (double)(fabs(c.w) * w);
+                part = fma(fabs(c.w), w, part);
             }
+            acc += (double)part;
             __syncthreads();
         }
         {
@@ -261,7 +274,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
             if (lane == 0) {
                 atomicAdd(stats + 0, (unsigned long long)nd);
                 atomicAdd(stats + 1, (unsigned long long)nf);
-                atomicAdd(stats + 2, (unsigned long long)NW * kWave * kWave);
+                atomicAdd(stats + 2, (unsigned long long)ncand * kWave);
                 atomicAdd(stats + 3, 1ull);
                 atomicAdd(stats + 4, (unsigned long long)witer);
             }
@@ -282,21 +295,26 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
 // ------------------------------------------------------------------ forces
 
 // Pair force on particle a from particle c (both terms of Alg. 1's force
-// pass).  gradW_ac = g(r) x_ac with g = (dW/dr)/r.  A boundary particle takes
-// the pressure and density of its fluid/soft partner (pressure mirroring), its
-// mass is psi_b; two boundary particles exert nothing.  Every factor is
-// symmetric in (a, c) and the vector factors are antisymmetric, so the force
-// c computes on itself from a is the exact IEEE negation.
+// pass), accumulated into f.  gradW_ac = g(r) x_ac with
+//   g = (dW/dr)/r = alpha/(2 h^2) (4 t1^2 - t2^2) / q,  t1 = (1-q)+, t2 = (2-q)+,
+// written as (2 t1 - t2)(2 t1 + t2) / q, which is finite and 0 at r = 0 (self
+// pair).  A boundary particle takes the pressure and density of its
+// fluid/soft partner (pressure mirroring), its mass is psi_b; two boundary
+// particles exert nothing.  Every factor is symmetric in (a, c) and the
+// vector factors are antisymmetric, so the force c computes on itself from a
+// is the exact IEEE negation.
 template <typename T>
 __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T rho_a, T P_a, bool isBa, T ma,
                                            const V4<T> &c, const V4<T> &cv, const V2<T> &cd, const Phys<T> &ph,
-                                           double &fx, double &fy, double &fz)
+                                           T &fx, T &fy, T &fz)
 {
     const T dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
     const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    const T q = fsqrt(r2) * ph.inv_h;
+    const T rs = frsqrt(max(r2, (T)1e-30));      // 1/r
+    const T q = (r2 * rs) * ph.inv_h;
+    const T t1 = max((T)1 - q, (T)0);
     const T t2 = max((T)2 - q, (T)0);
-    const T g = (q < (T)1) ? ph.gc * ((T)3 * q - (T)4) : -(ph.gc * (t2 * t2)) * frcp(q);
+    const T g = ((ph.gch * fma((T)2, t1, -t2)) * fma((T)2, t1, t2)) * rs;
     const bool isBc = c.w < (T)0;
     const T mc = fabs(c.w);
     T Pa = isBa ? cd.y : P_a;
@@ -309,15 +327,15 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
     }
     const T mm = ma * mc;
     T sp = -(mm * (Pa + Pc)) * g;
-    T sv = ((ph.two_nu * mm) * ((T)2 * frcp(ra + rc))) * (g * (r2 * frcp(r2 + ph.eps)));
+    // 2 nu m_a m_c [2/(rho_a+rho_c)] g r^2/(r^2+eps), one reciprocal
+    T sv = ((ph.two_nu * mm) * g) * (((T)2 * r2) * frcp((ra + rc) * (r2 + ph.eps)));
     const bool bb = isBa && isBc;
     const bool novisc = bb || ((ph.flags & 4u) && (isBa || isBc));
     sp = bb ? (T)0 : sp;
     sv = novisc ? (T)0 : sv;
-    const T dvx = mv.x - cv.x, dvy = mv.y - cv.y, dvz = mv.z - cv.z;
-    fx += (double)(sp * dx + sv * dvx);
-    fy += (double)(sp * dy + sv * dvy);
-    fz += (double)(sp * dz + sv * dvz);
+    fx = fma(sp, dx, fma(sv, mv.x - cv.x, fx));
+    fy = fma(sp, dy, fma(sv, mv.y - cv.y, fy));
+    fz = fma(sp, dz, fma(sv, mv.z - cv.z, fz));
 }
 
 template <typename T>
@@ -385,13 +403,18 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, 
                 for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
                 witer += mine;
             }
+            // a super-chunk holds ~1/S of the neighbours: sum it in T, then in FP64
+            T cx = (T)0, cy = (T)0, cz = (T)0;
             int hw = 0;
             uint32_t cur = mlds[0][lane];
             for (;;) {
                 const int k = next_hit<kScWords>(mlds, lane, hw, cur);
                 if (k < 0) break;
-                pair_force<T>(me, mv, md.x, md.y, kin, ma, cp[k], cvel[k], cden[k], ph, fx, fy, fz);
+                pair_force<T>(me, mv, md.x, md.y, kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
             }
+            fx += (double)cx;
+            fy += (double)cy;
+            fz += (double)cz;
             __syncthreads();
         }
         if (lane == 0) atomicAdd(stats + 5, (unsigned long long)witer);

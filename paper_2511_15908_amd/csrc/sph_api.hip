@@ -424,6 +424,7 @@ void fill_phys(Phys<T> &ph, const sph_params *p)
     ph.inv_h = (T)(1.0 / h);
     ph.alpha6 = (T)(alpha / 6.0);
     ph.gc = (T)(alpha / (2.0 * h * h));
+    ph.gch = (T)(alpha / (2.0 * h));
     ph.eps = (T)(0.01 * h * h);
     ph.two_nu = (T)(2.0 * p->nu);
     ph.gx = (T)p->gravity[0];

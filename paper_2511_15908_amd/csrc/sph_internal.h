@@ -98,6 +98,7 @@ struct Phys {
     T inv_h;
     T alpha6;     // alpha_3 / 6
     T gc;         // alpha_3 / (2 h^2)
+    T gch;        // alpha_3 / (2 h)
     T eps;        // 0.01 h^2
     T two_nu;     // 2 nu
     T gx, gy, gz;
@@ -130,6 +131,8 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float frsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double frsqrt(double x) { return 1.0 / sqrt(x); }
 
 // ---- canonical integer decisions shared by every kernel ----
 

@@ -288,7 +288,7 @@ def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") 
     nf = fl.shape[0]
     ij_glob = ij + nf                       # soft particles follow the fluid
     lo = (-0.5 * s, -0.5 * s, -0.5 * s)
-    hi = (101.5 * s, 101.5 * s, 130.5 * s)
+    hi = (101.5 * s, 101.5 * s, 125.0 * s)          # 32 cells of 2h (1 + 2^-10) per axis
     params = _params(h, dt, lo, hi, precision)
     poses = [[0, 0, 0, 1, 0, 0, 0], list(c0) + [1, 0, 0, 0]]
     return _assemble(f"coupled_{n_fluid}", precision, params, s,
