@@ -54,20 +54,42 @@ def log(msg, quiet=False):
         print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(scene):
-    """The oracle as it stands, one full step of the same scene on the host
-    cores (bounded sample: one step)."""
+def cpu_baseline(scene, min_seconds=10.0):
+    """The oracle as it stands, timed on the host cores: full steps of the
+    same scene (neighbour lists, density, forces, springs, wrench,
+    integration) until at least min_seconds have elapsed."""
     import oracle
     oracle.build(force=False)
     o = oracle.Oracle(scene, scene.precision)
-    t0 = time.perf_counter()
-    o.step()
-    dt = time.perf_counter() - t0
     nmov = int((scene.type != 2).sum())
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step()
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": nmov / dt, "unit": "particle-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 full step of the {scene.n:,}-particle scene ({nmov:,} fluid+soft), "
-                      f"FP64, {dt:.1f} s wall"}
+    return {"value": nmov * steps / dt, "unit": "particle-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} full FP64 oracle step(s) of the same {scene.n:,}-particle scene "
+                      f"({nmov:,} fluid+soft), {dt:.1f} s wall"}
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary,
+    only while the profiled kernel source is unchanged."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_sums_coupled_1m_traffic.json")
+    src = os.path.join(ROOT, "paper_2511_15908_amd", "csrc", "k_sums.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256_k_sums") != sha or kernel not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel]["bytes"]
 
 
 def main():
@@ -136,7 +158,7 @@ def main():
     achieved = flops / (ms[dom] * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": f"k_{dom}", "achieved": round(achieved, 3),
             "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": None, "avg_launch_ms": round(ms[dom], 4),
+            "traffic": profiled_traffic(f"k_{dom}"), "avg_launch_ms": round(ms[dom], 4),
             "algorithmic_flops_per_launch": int(flops)}
     out = {
         "metric": "SPH particle-updates/s @1M + haptic wrench Hz: surrogate vs plain, <=5% err",

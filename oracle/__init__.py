@@ -430,7 +430,10 @@ class Oracle:
         targets = np.ascontiguousarray(targets, np.int64)
         self.place()
         nb_t = neighbors(self.params, self.prec, self.x, targets)
-        union = np.unique(np.concatenate([targets, nb_t[2]]))
+        mark = np.zeros(self.n, bool)
+        mark[targets] = True
+        mark[nb_t[2]] = True
+        union = np.nonzero(mark)[0]
         union_mov = union[self.type[union] != BOUNDARY]
         nb_u = neighbors(self.params, self.prec, self.x, union_mov)
         rho_full = np.zeros(self.n)
