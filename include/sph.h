@@ -174,6 +174,10 @@ sph_status sph_read_field(sph_ctx *ctx, int field, void *host_dst, size_t bytes)
 sph_status sph_debug_neighbors(sph_ctx *ctx, uint32_t *counts, uint32_t *ids, size_t cap,
                                size_t *total);
 
+/* The same for the given particle ids only (counts[t] and lists in target order). */
+sph_status sph_debug_neighbors_of(sph_ctx *ctx, uint32_t n_targets, const uint32_t *targets,
+                                  uint32_t *counts, uint32_t *ids, size_t cap, size_t *total);
+
 /*
  * Work counters accumulated on the device since init: out[0] neighbour pairs
  * of fluid/soft particles (self included), out[1] neighbour pairs of all

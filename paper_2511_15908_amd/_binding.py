@@ -30,7 +30,8 @@ STATUS = {0: "SPH_OK", 1: "SPH_ERR_ARG", 2: "SPH_ERR_WORKSPACE", 3: "SPH_ERR_DEV
 N_PHASES = 9
 
 EXPORTED = ["sph_workspace_size", "sph_init", "sph_set_body_pose", "sph_step", "sph_get_body_wrench",
-            "sph_reset_smoothing", "sph_read_field", "sph_debug_neighbors", "sph_get_stats", "sph_get_info",
+            "sph_reset_smoothing", "sph_read_field", "sph_debug_neighbors", "sph_debug_neighbors_of",
+            "sph_get_stats", "sph_get_info",
             "sph_synchronize", "sph_profile_begin", "sph_profile_read", "sph_profile_phase_name",
             "sph_destroy", "sph_status_string", "sph_last_error"]
 
@@ -90,6 +91,8 @@ def load_library(path=None):
     L.sph_read_field.argtypes = [vp, C.c_int, vp, sz]
     L.sph_debug_neighbors.argtypes = [vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), sz,
                                       C.POINTER(sz)]
+    L.sph_debug_neighbors_of.argtypes = [vp, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                         C.POINTER(C.c_uint32), sz, C.POINTER(sz)]
     L.sph_get_info.argtypes = [vp, C.POINTER(SphInfo)]
     L.sph_get_stats.argtypes = [vp, C.POINTER(C.c_uint64)]
     L.sph_synchronize.argtypes = [vp]
@@ -263,6 +266,24 @@ class Sim:
         counts = counts[:self.n].astype(np.int64)
         offs = np.zeros(self.n, np.int64)
         if self.n:
+            offs[1:] = np.cumsum(counts)[:-1]
+        return counts, offs, ids[:tot.value].astype(np.int64)
+
+    def neighbors_of(self, targets):
+        """(counts, offsets, ids) of the given particle ids, in their order."""
+        t = np.ascontiguousarray(targets, np.uint32)
+        counts = np.zeros(max(t.size, 1), np.uint32)
+        tot = C.c_size_t(0)
+        P = C.POINTER(C.c_uint32)
+        self._check(self.L.sph_debug_neighbors_of(self.ctx, t.size, t.ctypes.data_as(P), counts.ctypes.data_as(P),
+                                                  None, 0, C.byref(tot)), "sph_debug_neighbors_of")
+        ids = np.zeros(max(tot.value, 1), np.uint32)
+        self._check(self.L.sph_debug_neighbors_of(self.ctx, t.size, t.ctypes.data_as(P), counts.ctypes.data_as(P),
+                                                  ids.ctypes.data_as(P), ids.size, C.byref(tot)),
+                    "sph_debug_neighbors_of")
+        counts = counts[:t.size].astype(np.int64)
+        offs = np.zeros(t.size, np.int64)
+        if t.size:
             offs[1:] = np.cumsum(counts)[:-1]
         return counts, offs, ids[:tot.value].astype(np.int64)
 

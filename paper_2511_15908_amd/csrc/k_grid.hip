@@ -278,12 +278,12 @@ __global__ __launch_bounds__(128) void k_psi(uint32_t n, State<T> st, Grid g, Ph
             if (obj_of_id[st.id[j]] != ob) continue;
             const V4<T> c = st.pos[j];
             if (!within_support<T>(me, c, R2)) continue;
-            const T dx = c.x - me.x, dy = c.y - me.y, dz = c.z - me.z;
-            const T r = fsqrt(dx * dx + dy * dy + dz * dz);
-            const T q = r * ph.inv_h;
-            const T t2 = max((T)2 - q, (T)0);
-            const T t1 = max((T)1 - q, (T)0);
-            acc += (double)(ph.alpha6 * (t2 * t2 * t2 - (T)4 * (t1 * t1 * t1)));
+            const double dx = (double)c.x - (double)me.x, dy = (double)c.y - (double)me.y;
+            const double dz = (double)c.z - (double)me.z;
+            const double q = sqrt(dx * dx + dy * dy + dz * dz) * ph.inv_h64;
+            const double t2 = fmax(2.0 - q, 0.0);
+            const double t1 = fmax(1.0 - q, 0.0);
+            acc += ph.alpha6_64 * (t2 * t2 * t2 - 4.0 * (t1 * t1 * t1));
         }
     }
     st.pos[p].w = (T)(-(ph.psi_scale / acc));

@@ -245,24 +245,29 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                 for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
                 witer += mine;
             }
-            // kernel sum over this lane's neighbours among the staged candidates
-            // (~1/S of them: summed in T, then in FP64)
-            T part = (T)0;
+            // kernel sum over this lane's neighbours among the staged candidates.
+            // The coordinate differences are exact in T; the kernel value and
+            // the sum are evaluated in FP64, because p = k (rho - rho0) turns a
+            // relative density error e into e rho / (rho - rho0) (~1e4 e near
+            // rest) in the pressure, whose pair terms nearly cancel.
             int hw = 0;
             uint32_t cur = mlds[0][lane];
             for (;;) {
                 const int k = next_hit<kScWords>(mlds, lane, hw, cur);
                 if (k < 0) break;
                 const V4<T> c = cand[k];
-                const T dx = c.x - me.x, dy = c.y - me.y, dz = c.z - me.z;
-                const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                const T q = fsqrt(r2) * ph.inv_h;
-                const T t2 = max((T)2 - q, (T)0);
-                const T t1 = max((T)1 - q, (T)0);
-                const T w = ph.alpha6 * (t2 * t2 * t2 - (T)4 * (t1 * t1 * t1));
-                part = fma(fabs(c.w), w, part);
+                const double dx = (double)(c.x - me.x), dy = (double)(c.y - me.y), dz = (double)(c.z - me.z);
+                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                // r from an FP32 rsqrt seed and one Newton step in FP64 (~1e-14)
+                const double y = (double)frsqrt((float)fmax(r2, 1e-30));
+                double r = r2 * y;
+                r = fma(0.5 * y, fma(-r, r, r2), r);
+                const double q = r * ph.inv_h64;
+                const double t2 = fmax(2.0 - q, 0.0);
+                const double t1 = fmax(1.0 - q, 0.0);
+                const double w = ph.alpha6_64 * (t2 * t2 * t2 - 4.0 * (t1 * t1 * t1));
+                acc = fma((double)fabs(c.w), w, acc);
             }
-            acc += (double)part;
             __syncthreads();
         }
         {

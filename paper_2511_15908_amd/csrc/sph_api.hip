@@ -435,6 +435,8 @@ void fill_phys(Phys<T> &ph, const sph_params *p)
     ph.rho0 = p->rho0;
     ph.kp = p->k_pressure;
     ph.psi_scale = p->rho0;
+    ph.inv_h64 = 1.0 / h;
+    ph.alpha6_64 = alpha / 6.0;
     ph.flags = p->flags;
 }
 
@@ -890,7 +892,8 @@ sph_status read_field_t(sph_ctx *c, int field, void *dst, size_t bytes)
 }
 
 template <typename T>
-sph_status debug_nbrs_t(sph_ctx *c, uint32_t *counts, uint32_t *ids_out, size_t cap, size_t *total)
+sph_status debug_nbrs_t(sph_ctx *c, uint32_t nt, const uint32_t *targets, uint32_t *counts, uint32_t *ids_out,
+                        size_t cap, size_t *total)
 {
     const uint32_t n = c->n;
     hipStream_t s = c->stream;
@@ -907,8 +910,12 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t *counts, uint32_t *ids_out, size_t 
     sph_status st = check_err(c);
     if (st == SPH_ERR_DEVICE) return st;
     std::vector<std::vector<uint32_t>> lists(n);
+    std::vector<uint8_t> want(n, targets ? 0 : 1);
+    if (targets)
+        for (uint32_t t = 0; t < nt; ++t) want[targets[t]] = 1;
     const Grid &g = c->grid;
     for (uint32_t p = 0; p < n; ++p) {
+        if (!want[ids[p]]) continue;
         const uint32_t a = aux[p];
         if (aux_type(a) == TY_BOUNDARY && !aux_kin(a)) continue;
         const uint32_t home = keys[p];
@@ -968,15 +975,17 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t *counts, uint32_t *ids_out, size_t 
         std::sort(lst.begin(), lst.end());
     }
     size_t tot = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        counts[i] = (uint32_t)lists[i].size();
+    const uint32_t m = targets ? nt : n;
+    for (uint32_t t = 0; t < m; ++t) {
+        const uint32_t i = targets ? targets[t] : t;
+        counts[t] = (uint32_t)lists[i].size();
         tot += lists[i].size();
     }
     if (total) *total = tot;
     if (ids_out && tot <= cap) {
         size_t o = 0;
-        for (uint32_t i = 0; i < n; ++i)
-            for (uint32_t j : lists[i]) ids_out[o++] = j;
+        for (uint32_t t = 0; t < m; ++t)
+            for (uint32_t j : lists[targets ? targets[t] : t]) ids_out[o++] = j;
     }
     return st;
 }
@@ -997,8 +1006,19 @@ sph_status sph_debug_neighbors(sph_ctx *ctx, uint32_t *counts, uint32_t *ids, si
 {
     if (!ctx || (!counts && ctx->n)) return SPH_ERR_ARG;
     if (ctx->dead) return SPH_ERR_STATE;
-    return ctx->prec == SPH_FP64 ? debug_nbrs_t<double>(ctx, counts, ids, cap, total)
-                                 : debug_nbrs_t<float>(ctx, counts, ids, cap, total);
+    return ctx->prec == SPH_FP64 ? debug_nbrs_t<double>(ctx, 0, nullptr, counts, ids, cap, total)
+                                 : debug_nbrs_t<float>(ctx, 0, nullptr, counts, ids, cap, total);
+}
+
+sph_status sph_debug_neighbors_of(sph_ctx *ctx, uint32_t n_targets, const uint32_t *targets, uint32_t *counts,
+                                  uint32_t *ids, size_t cap, size_t *total)
+{
+    if (!ctx || (n_targets && (!targets || !counts))) return SPH_ERR_ARG;
+    if (ctx->dead) return SPH_ERR_STATE;
+    for (uint32_t t = 0; t < n_targets; ++t)
+        if (targets[t] >= ctx->n) return SPH_ERR_ARG;
+    return ctx->prec == SPH_FP64 ? debug_nbrs_t<double>(ctx, n_targets, targets, counts, ids, cap, total)
+                                 : debug_nbrs_t<float>(ctx, n_targets, targets, counts, ids, cap, total);
 }
 
 sph_status sph_get_stats(sph_ctx *ctx, uint64_t out[6])

@@ -105,6 +105,7 @@ struct Phys {
     T dt;
     T vmax2;      // 0: no speed check
     double rho0, kp;
+    double inv_h64, alpha6_64;   // FP64 kernel constants of the density sum
     double psi_scale; // rho0 (for psi init)
     uint32_t flags;
 };

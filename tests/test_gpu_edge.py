@@ -1,0 +1,200 @@
+"""Edge cases of the HIP path through the C ABI: empty and tiny scenes,
+closed-form free fall, cells far above 64 particles, particles outside the
+grid, neighbourhood capacity overflow, the instability flag, the
+alternative-reading flags, a non-default stream, argument errors."""
+import numpy as np
+import pytest
+
+from tests import _cmp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2511_15908_amd as P
+    P.load_library()
+    return P
+
+
+def _scene(x, v=None, types=None, mass=1e-3, h=0.02, precision="f32", lo=(-0.2,) * 3, hi=(0.2,) * 3,
+           gravity=(0.0, 0.0, -9.81), objects=None):
+    from paper_2511_15908_amd import scenes
+    x = np.asarray(x, np.float64).reshape(-1, 3)
+    n = x.shape[0]
+    types = np.zeros(n, np.uint8) if types is None else np.asarray(types, np.uint8)
+    obj = np.full(n, -1, np.int32)
+    kin, poses = [], []
+    if objects is not None:
+        obj = np.asarray(objects, np.int32)
+        no = int(obj.max()) + 1 if n else 0
+        kin = [0] * no
+        poses = [[0, 0, 0, 1, 0, 0, 0]] * no
+    params = scenes._params(h, 1e-4, lo, hi, precision)
+    params["gravity"] = gravity
+    sc = scenes.Scene(name="edge", precision=precision, params=params, x=x,
+                      v=np.zeros_like(x) if v is None else np.asarray(v, np.float64),
+                      mass=np.full(n, mass), type=types, object=obj,
+                      object_kinematic=np.asarray(kin, np.uint8),
+                      object_pose0=np.asarray(poses, np.float64).reshape(-1, 7), spacing=h / 2)
+    return sc
+
+
+def _compare_one_step(gpu, orc, sc, prec, tol_rho, tol_f):
+    sim = gpu.Sim(sc, precision=prec)
+    sim.step(1)
+    o = orc.Oracle(sc, prec)
+    r = o.step(keep_neighbors=True)
+    fs = np.nonzero(sc.type != 2)[0]
+    assert np.array_equal(sim.read("key"), r["keys"])
+    cg, og, ig = sim.neighbors()
+    co, oo, io = r["nbr"]
+    for t in fs:
+        assert np.array_equal(ig[og[t]:og[t] + cg[t]], io[oo[t]:oo[t] + co[t]])
+    assert _cmp.rel_density(sim.read("rho")[fs], r["rho"][fs]) <= tol_rho
+    mref = float(np.median(sc.mass[fs]))
+    assert _cmp.rel_force(sim.read("f")[fs], r["f"][fs], mref * 9.81) <= tol_f
+    return sim
+
+
+def test_empty_scene(gpu):
+    sc = _scene(np.zeros((0, 3)))
+    sim = gpu.Sim(sc)
+    sim.step(3)
+    sim.synchronize()
+    assert sim.read("x").shape == (0, 3)
+    assert sim.info()["steps"] == 3
+
+
+def test_single_particle_free_fall_closed_form(gpu):
+    """One isolated fluid particle: only gravity acts (its self pair gives no
+    force), so symplectic Euler gives v_n = -n g dt and
+    z_n = z0 - g dt^2 n(n+1)/2 (Eq. euler)."""
+    sc = _scene([[0.01, 0.02, 0.05]], precision="f64")
+    sim = gpu.Sim(sc, precision="f64")
+    n = 50
+    sim.step(n)
+    dt, g = sc.params["dt"], 9.81
+    x = sim.read("x")[0]
+    v = sim.read("v")[0]
+    assert v[2] == pytest.approx(-n * g * dt, rel=1e-12)
+    assert x[2] == pytest.approx(0.05 - g * dt * dt * n * (n + 1) / 2, rel=1e-12)
+    assert x[0] == 0.01 and x[1] == 0.02
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_overfull_cell(gpu, orc, prec):
+    """200 particles inside one grid cell (4 target chunks of a wavefront,
+    many super-chunks), with random velocities."""
+    from paper_2511_15908_amd import scenes
+    rng = scenes.SplitMix64(5, 9)
+    x = (rng.uniform(600).reshape(200, 3) - 0.5) * 0.03 - 0.02     # inside the cell [-0.04, 0.0002)^3
+    v = (rng.uniform(600).reshape(200, 3) - 0.5) * 0.2
+    sc = _scene(x, v, precision=prec)
+    tol = (1e-5, 1e-4) if prec == "f32" else (1e-12, 1e-10)
+    _compare_one_step(gpu, orc, sc, prec, *tol)
+
+
+def test_particles_outside_grid(gpu, orc):
+    """Particles beyond the grid bounds use the edge cells; neighbour sets
+    and sums are unchanged."""
+    from paper_2511_15908_amd import scenes
+    rng = scenes.SplitMix64(6, 9)
+    inside = (rng.uniform(900).reshape(300, 3) - 0.5) * 0.3
+    outside = np.array([[0.25, 0.0, 0.0], [0.26, 0.005, 0.0], [-0.3, -0.3, 0.31], [-0.305, -0.3, 0.31],
+                        [0.0, 0.5, -0.4]])
+    sc = _scene(np.concatenate([inside, outside]), precision="f32")
+    _compare_one_step(gpu, orc, sc, "f32", 1e-5, 1e-4)
+
+
+def test_capacity_overflow_is_reported(gpu):
+    """5,000 particles in one cell exceed the 64-word neighbourhood capacity:
+    the step reports SPH_ERR_CAPACITY instead of computing garbage."""
+    from paper_2511_15908_amd import scenes
+    rng = scenes.SplitMix64(7, 9)
+    x = (rng.uniform(15000).reshape(5000, 3) - 0.5) * 0.03 - 0.02
+    sc = _scene(x)
+    sim = gpu.Sim(sc)
+    sim.step(1)
+    with pytest.raises(gpu.SphError) as e:
+        sim.synchronize()
+    assert e.value.status == 7
+    sim.synchronize()      # the condition was reported once and cleared
+
+
+def test_instability_flag(gpu):
+    sc = _scene([[0.0, 0.0, 0.0], [0.05, 0.0, 0.0]])
+    sim = gpu.Sim(sc, v_max=1e-3)
+    sim.step(1)            # |v| = g dt = 9.81e-4 <= 1e-3
+    sim.synchronize()
+    sim.step(1)            # 1.96e-3 > 1e-3
+    with pytest.raises(gpu.SphError) as e:
+        sim.synchronize()
+    assert e.value.status == 5
+
+
+@pytest.mark.parametrize("flag", [1, 2, 4, 7])
+def test_reading_flags(gpu, orc, flag):
+    """The alternative readings (clamped pressure, single boundary pressure
+    term, no boundary viscosity) match the oracle too."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=51, precision="f64")
+    sc.params["flags"] = flag
+    sim = gpu.Sim(sc, precision="f64")
+    pose = scenes.random_pose_velocity(51, sc.object_pose0[1, :3])
+    sim.set_body_pose(1, *pose)
+    sim.step(1)
+    o = orc.Oracle(sc, "f64")
+    o.set_pose(1, *pose)
+    r = o.step()
+    fs = np.nonzero(sc.type != 2)[0]
+    assert _cmp.rel_density(sim.read("rho")[fs], r["rho"][fs]) <= 1e-12
+    assert np.allclose(sim.read("p")[fs], r["p"][fs], rtol=1e-9, atol=1e-9)
+    mref = float(np.median(sc.mass[fs]))
+    assert _cmp.rel_force(sim.read("f")[fs], r["f"][fs], mref * 9.81) <= 1e-10
+    F, T = sim.wrench(1)
+    assert _cmp.rel_vec(F, r["wrench"][1][0], 1000 * 9.81 * 27 * sc.spacing ** 3) <= 1e-10
+
+
+def test_non_default_stream(gpu):
+    import torch
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=61)
+    a = gpu.Sim(sc)
+    a.step(3)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = gpu.Sim(sc)
+        b.step(3)
+    assert np.array_equal(a.read("x"), b.read("x"))
+    assert np.array_equal(a.read("f"), b.read("f"))
+
+
+def test_argument_errors(gpu):
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=71)
+    sim = gpu.Sim(sc)
+    with pytest.raises(gpu.SphError) as e:
+        sim.set_body_pose(0, [0, 0, 0], [1, 0, 0, 0])      # static tank
+    assert e.value.status == 1
+    with pytest.raises(gpu.SphError):
+        sim.set_body_pose(5, [0, 0, 0], [1, 0, 0, 0])      # no such object
+    with pytest.raises(gpu.SphError):
+        sim.set_body_pose(1, [0, 0, 0], [0, 0, 0, 0])      # zero quaternion
+    with pytest.raises(gpu.SphError):
+        sim.wrench(0)
+    sim.step(1)
+    sim.synchronize()
+
+
+def test_fluid_only_no_boundary(gpu, orc):
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=81, with_soft=False, with_body=False)
+    keep = sc.type != 2
+    for name in ["x", "v", "mass", "type", "object"]:
+        setattr(sc, name, getattr(sc, name)[keep])
+    sc.object_kinematic = np.zeros(0, np.uint8)
+    sc.object_pose0 = np.zeros((0, 7))
+    _compare_one_step(gpu, orc, sc, "f32", 1e-5, 1e-4)

@@ -1,0 +1,86 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (FP32, 1M coupled scene; 250k stirring tank): the HIP path runs the
+whole scene, the oracle recomputes sampled particles one by one (their
+neighbour lists, the densities of all their neighbours, their forces), and the
+grabbed body's wrench from all of its particles.  Cell keys are compared for
+every particle."""
+import numpy as np
+import pytest
+
+from tests import _cmp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2511_15908_amd as P
+    P.load_library()
+    return P
+
+
+def _sample(sc, seed, n_rand=300):
+    from paper_2511_15908_amd import scenes
+    rng = scenes.SplitMix64(seed, 77)
+    fl = np.nonzero(sc.type == 0)[0]
+    soft = np.nonzero(sc.type == 1)[0]
+    body = np.nonzero(sc.object == 1)[0]
+    pick = lambda a, k: a[(rng.uniform(k) * a.size).astype(np.int64)] if a.size else a[:0]   # noqa: E731
+    c = sc.x[body].mean(0)
+    near_body = fl[np.linalg.norm(sc.x[fl] - c, axis=1) < 0.09]
+    lo = sc.x[sc.type == 2].min(0)
+    near_wall = fl[np.min(np.abs(sc.x[fl] - lo), axis=1) < 2 * sc.spacing]
+    t = np.concatenate([pick(fl, n_rand), pick(soft, 60), pick(near_body, 120), pick(near_wall, 80),
+                        pick(body, 40)])
+    return np.unique(t)
+
+
+def _fullsize(gpu, orc, sc, pose, seed):
+    sim = gpu.Sim(sc)
+    sim.set_body_pose(1, *pose)
+    sim.step(1)
+    o = orc.Oracle(sc, "f32")
+    o.set_pose(1, *pose)
+    targets = _sample(sc, seed)
+    res = o.sampled(targets)
+    # keys of every particle (after placement)
+    assert np.array_equal(sim.read("key"), orc.cell_keys(sc.params, "f32", o.x))
+    # neighbour sets of the sample
+    cg, og, ig = sim.neighbors_of(targets)
+    co, oo, io = res["nbr"]
+    assert np.array_equal(cg, co)
+    assert np.array_equal(ig, io)
+    fs = sc.type[targets] != 2
+    e_rho = _cmp.rel_density(sim.read("rho")[targets[fs]], res["rho"][fs])
+    mref = float(np.median(sc.mass[sc.type != 2]))
+    e_f = _cmp.rel_force(sim.read("f")[targets], res["f"], mref * _cmp.G)
+    # wrench of the grabbed body from all its particles
+    body = np.nonzero(sc.object == 1)[0]
+    rb = o.sampled(body)
+    f_full = np.zeros((sc.n, 3))
+    f_full[body] = rb["f"]
+    F_o, T_o = orc.wrench(sc.object, 1, o.pose[1][1], o.r_loc, f_full)
+    F_g, T_g = sim.wrench(1)
+    V = body.size * sc.spacing ** 3
+    L = float(np.ptp(sc.x[body], axis=0).max())
+    eF = _cmp.rel_vec(F_g, F_o, 1000 * _cmp.G * V)
+    eT = _cmp.rel_vec(T_g, T_o, 1000 * _cmp.G * V * L)
+    print(f"{sc.name}: {targets.size} sampled, density {e_rho:.2e}, force {e_f:.2e}, wrench F {eF:.2e} T {eT:.2e}")
+    assert e_rho <= 1e-5
+    assert e_f <= 1e-4
+    assert eF <= 1e-4 and eT <= 1e-4
+
+
+def test_coupled_1m_sampled(gpu, orc):
+    from paper_2511_15908_amd import scenes
+    sc = scenes.coupled_1m()
+    C, Q, V, W = scenes.random_walk(3, 40, sc.info["c0"])
+    _fullsize(gpu, orc, sc, (C[37], Q[37], V[37], W[37]), 3)
+
+
+def test_stirring_250k_sampled(gpu, orc):
+    from paper_2511_15908_amd import scenes
+    sc = scenes.stirring_tank()
+    _fullsize(gpu, orc, sc, scenes.stirring_pose(sc, 0.3), 2)
