@@ -172,6 +172,48 @@ __device__ __forceinline__ int next_hit(uint32_t (*mlds)[kWave], uint32_t lane, 
 
 // ------------------------------------------------------------------ density
 
+// Kernel value W(|c - me|) evaluated in FP64 from the exact T-precision
+// coordinate differences: p = k (rho - rho0) turns a relative density error e
+// into e rho / (rho - rho0) (~1e4 e near rest) in the pressure, whose pair
+// terms nearly cancel, so the density sum carries FP64 terms.
+template <typename T>
+__device__ __forceinline__ double kernel_w64(const V4<T> &c, const V4<T> &me, const Phys<T> &ph)
+{
+    const double dx = (double)(c.x - me.x), dy = (double)(c.y - me.y), dz = (double)(c.z - me.z);
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    // r from an FP32 rsqrt seed and one Newton step in FP64 (~1e-14)
+    const double y = (double)frsqrt((float)fmax(r2, 1e-30));
+    double r = r2 * y;
+    r = fma(0.5 * y, fma(-r, r, r2), r);
+    const double q = r * ph.inv_h64;
+    const double t2 = fmax(2.0 - q, 0.0);
+    const double t1 = fmax(1.0 - q, 0.0);
+    return ph.alpha6_64 * (t2 * t2 * t2 - 4.0 * (t1 * t1 * t1));
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// A cell's particles are served 64 per wavefront pass ("lane mode": lane =
+// target).  When a cell holds a little more than a multiple of 64 (common at
+// rest: a 2h cell holds exactly 4^3 lattice sites, so slight compression
+// tips it over), the last few targets would cost a whole extra pass; they
+// are served instead inside the previous pass's super-chunk loop in
+// "transposed mode" (lane = candidate, one target at a time, ballot = the
+// target's hit word), which costs about 1/20 of a pass per target.
+#ifndef SPH_LEFT_DENSITY
+#define SPH_LEFT_DENSITY 24
+#endif
+#ifndef SPH_LEFT_FORCE
+#define SPH_LEFT_FORCE 12
+#endif
+constexpr uint32_t kLeftD = SPH_LEFT_DENSITY;   // most leftover targets of the density pass
+constexpr uint32_t kLeftF = SPH_LEFT_FORCE;     // of the force pass
+
 template <typename T>
 __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n, State<T> st, Grid g, Phys<T> ph,
                                                 const uint32_t *__restrict__ cstart,
@@ -182,6 +224,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
     __shared__ Nbhd nb;
     __shared__ V4<T> cand[kScWords * kWave];
     __shared__ uint32_t mlds[2 * kScWords][kWave];
+    __shared__ double accl[kLeftD > 0 ? kLeftD : 1];
     const uint32_t lane = threadIdx.x;
     const uint32_t cell = cell_of_block(blockIdx.x, g.nslots);
     if (cell >= g.nslots) return;
@@ -191,10 +234,17 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         if (lane == 0) atomicOr(err, ERR_CAPACITY);
         return;
     }
-    const uint32_t S = nb.stride, NW = nb.nw;
+    const uint32_t S = nb.stride;
     const T R2 = grid_R2<T>(g);
     const T inf = __builtin_huge_val();
-    for (uint32_t t0 = s0; t0 < e0; t0 += kWave) {
+    const uint32_t ncell = e0 - s0, rem = ncell % kWave;
+    const bool use_left = ncell > (uint32_t)kWave && rem != 0u && rem <= kLeftD;
+    const uint32_t nlane = use_left ? ncell / kWave : (ncell + kWave - 1) / kWave;
+    const uint32_t nleft = use_left ? rem : 0u;
+    const uint32_t left0 = s0 + kWave * nlane;
+    for (uint32_t ch = 0; ch < nlane; ++ch) {
+        const uint32_t t0 = s0 + kWave * ch;
+        const bool with_left = (ch + 1 == nlane) && nleft;
         const uint32_t p = t0 + lane;
         const bool act = p < e0;
         const uint32_t pc = act ? p : s0;
@@ -205,9 +255,11 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         me.z = act ? me.z : inf;
         const bool fs = act && aux_type(aux) != TY_BOUNDARY;
         const bool want = act && (fs || aux_kin(aux));
-        if (__ballot(want) == 0ull) continue;
+        const bool lanes_any = __ballot(want) != 0ull;
+        if (!lanes_any && !with_left) continue;
+        if (with_left && lane < nleft) accl[lane] = 0.0;
         double acc = 0.0;
-        uint32_t npair = 0, witer = 0, ncand = 0;
+        uint32_t npair = 0, witer = 0, ncand = 0, nleftpair_d = 0, nleftpair_f = 0;
         for (uint32_t sc = 0; sc < S; ++sc) {
             begin_chunk(nb, sc, lane);
             const uint32_t size = nb.size;
@@ -225,48 +277,62 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
             __syncthreads();
             const uint32_t nws = nb.wbase[sc + 1] - nb.wbase[sc];
             const uint32_t w0 = nb.wbase[sc];
+            if (lanes_any) {
 #pragma unroll
-            for (int q = 0; q < kScWords; ++q) {
-                uint64_t m = 0;
-                if ((uint32_t)q < nws) {
-                    const uint32_t nv = min(size - (uint32_t)q * kWave, (uint32_t)kWave);
-                    m = hit_word<T>(me, cand + q * kWave, nv, R2);
-                    if (act) masks[(size_t)(w0 + q) * n + p] = m;
-                    npair += want ? (uint32_t)__popcll(m) : 0u;
+                for (int q = 0; q < kScWords; ++q) {
+                    uint64_t m = 0;
+                    if ((uint32_t)q < nws) {
+                        const uint32_t nv = min(size - (uint32_t)q * kWave, (uint32_t)kWave);
+                        m = hit_word<T>(me, cand + q * kWave, nv, R2);
+                        if (act) masks[(size_t)(w0 + q) * n + p] = m;
+                        npair += want ? (uint32_t)__popcll(m) : 0u;
+                    }
+                    mlds[2 * q][lane] = fs ? (uint32_t)m : 0u;
+                    mlds[2 * q + 1][lane] = fs ? (uint32_t)(m >> 32) : 0u;
                 }
-                mlds[2 * q][lane] = fs ? (uint32_t)m : 0u;
-                mlds[2 * q + 1][lane] = fs ? (uint32_t)(m >> 32) : 0u;
-            }
-            {
-                uint32_t mine = 0;
+                {
+                    uint32_t mine = 0;
 #pragma unroll
-                for (int h = 0; h < 2 * kScWords; ++h) mine += __popc(mlds[h][lane]);
+                    for (int h = 0; h < 2 * kScWords; ++h) mine += __popc(mlds[h][lane]);
 #pragma unroll
-                for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
-                witer += mine;
+                    for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
+                    witer += mine;
+                }
+                // kernel sum over this lane's neighbours among the staged candidates
+                int hw = 0;
+                uint32_t cur = mlds[0][lane];
+                for (;;) {
+                    const int k = next_hit<kScWords>(mlds, lane, hw, cur);
+                    if (k < 0) break;
+                    const V4<T> c = cand[k];
+                    acc = fma((double)fabs(c.w), kernel_w64<T>(c, me, ph), acc);
+                }
             }
-            // kernel sum over this lane's neighbours among the staged candidates.
-            // The coordinate differences are exact in T; the kernel value and
-            // the sum are evaluated in FP64, because p = k (rho - rho0) turns a
-            // relative density error e into e rho / (rho - rho0) (~1e4 e near
-            // rest) in the pressure, whose pair terms nearly cancel.
-            int hw = 0;
-            uint32_t cur = mlds[0][lane];
-            for (;;) {
-                const int k = next_hit<kScWords>(mlds, lane, hw, cur);
-                if (k < 0) break;
-                const V4<T> c = cand[k];
-                const double dx = (double)(c.x - me.x), dy = (double)(c.y - me.y), dz = (double)(c.z - me.z);
-                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                // r from an FP32 rsqrt seed and one Newton step in FP64 (~1e-14)
-                const double y = (double)frsqrt((float)fmax(r2, 1e-30));
-                double r = r2 * y;
-                r = fma(0.5 * y, fma(-r, r, r2), r);
-                const double q = r * ph.inv_h64;
-                const double t2 = fmax(2.0 - q, 0.0);
-                const double t1 = fmax(1.0 - q, 0.0);
-                const double w = ph.alpha6_64 * (t2 * t2 * t2 - 4.0 * (t1 * t1 * t1));
-                acc = fma((double)fabs(c.w), w, acc);
+            if (with_left) {
+                // transposed mode: lane = staged candidate slot
+                for (uint32_t t = 0; t < nleft; ++t) {
+                    const uint32_t pt = left0 + t;
+                    const uint32_t at = st.aux[pt];
+                    const bool fs_t = aux_type(at) != TY_BOUNDARY;
+                    if (!fs_t && !aux_kin(at)) continue;    // uniform: static boundary
+                    const V4<T> mt = st.pos[pt];
+                    double part = 0.0;
+#pragma unroll
+                    for (int q = 0; q < kScWords; ++q) {
+                        if ((uint32_t)q < nws) {
+                            const V4<T> c = cand[q * kWave + lane];   // far past the chunk end
+                            const bool hit = within_support<T>(mt, c, R2);
+                            const uint64_t m = __ballot(hit);
+                            if (lane == 0) masks[(size_t)(w0 + q) * n + pt] = m;
+                            const uint32_t cnt = (uint32_t)__popcll(m);
+                            nleftpair_f += cnt;
+                            nleftpair_d += fs_t ? cnt : 0u;
+                            if (fs_t && hit) part = fma((double)fabs(c.w), kernel_w64<T>(c, mt, ph), part);
+                        }
+                    }
+                    part = wave_sum_f64(part);
+                    if (lane == 0) accl[t] += part;
+                }
             }
             __syncthreads();
         }
@@ -277,9 +343,9 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
             nd = wave_sum_u32(nd);
             nf = wave_sum_u32(nf);
             if (lane == 0) {
-                atomicAdd(stats + 0, (unsigned long long)nd);
-                atomicAdd(stats + 1, (unsigned long long)nf);
-                atomicAdd(stats + 2, (unsigned long long)ncand * kWave);
+                atomicAdd(stats + 0, (unsigned long long)(nd + nleftpair_d));
+                atomicAdd(stats + 1, (unsigned long long)(nf + nleftpair_f));
+                atomicAdd(stats + 2, (unsigned long long)ncand * (kWave + nleft));
                 atomicAdd(stats + 3, 1ull);
                 atomicAdd(stats + 4, (unsigned long long)witer);
             }
@@ -293,6 +359,19 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                 d.y = (T)(pr / (acc * acc));
             }
             dens[p] = d;
+        }
+        if (with_left && lane < nleft) {
+            const uint32_t pt = left0 + lane;
+            const bool fs_t = aux_type(st.aux[pt]) != TY_BOUNDARY;
+            V2<T> d{(T)0, (T)0};
+            if (fs_t) {
+                const double rho = accl[lane];
+                double pr = ph.kp * (rho - ph.rho0);
+                if ((ph.flags & 1u) && pr < 0.0) pr = 0.0;
+                d.x = (T)rho;
+                d.y = (T)(pr / (rho * rho));
+            }
+            dens[pt] = d;
         }
     }
 }
@@ -343,6 +422,32 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
     fz = fma(sp, dz, fma(sv, mv.z - cv.z, fz));
 }
 
+// Force on a lane-mode or transposed-mode target from its accumulated pair
+// sum: fluid/soft add gravity and springs; kinematic boundary particles keep
+// the reaction for the body wrench.
+template <typename T>
+__device__ __forceinline__ void store_force(uint32_t p, uint32_t aux, T ma, double fx, double fy, double fz,
+                                            const Phys<T> &ph, const V4<T> *__restrict__ fspring,
+                                            V4<T> *__restrict__ force, double *__restrict__ fbody)
+{
+    if (aux_type(aux) != TY_BOUNDARY) {
+        double ex = ma * ph.gx, ey = ma * ph.gy, ez = ma * ph.gz;
+        if (aux_type(aux) == TY_SOFT) {
+            const V4<T> sp = fspring[aux_index(aux)];
+            ex += sp.x;
+            ey += sp.y;
+            ez += sp.z;
+        }
+        force[p] = V4<T>{(T)(fx + ex), (T)(fy + ey), (T)(fz + ez), (T)0};
+    } else if (aux_kin(aux)) {
+        force[p] = V4<T>{(T)fx, (T)fy, (T)fz, (T)0};
+        double *fb = fbody + 3u * aux_index(aux);
+        fb[0] = fx;
+        fb[1] = fy;
+        fb[2] = fz;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, Phys<T> ph,
                                                const uint32_t *__restrict__ cstart,
@@ -356,6 +461,7 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, 
     __shared__ V4<T> cvel[kScWords * kWave];
     __shared__ V2<T> cden[kScWords * kWave];
     __shared__ uint32_t mlds[2 * kScWords][kWave];
+    __shared__ double accf[kLeftF > 0 ? kLeftF : 1][3];
     const uint32_t lane = threadIdx.x;
     const uint32_t cell = cell_of_block(blockIdx.x, g.nslots);
     if (cell >= g.nslots) return;
@@ -363,7 +469,14 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, 
     if (s0 >= e0) return;
     if (!load_nbhd(cell, g, cstart, cend, nb, lane)) return;   // flagged by the density pass
     const uint32_t S = nb.stride;
-    for (uint32_t t0 = s0; t0 < e0; t0 += kWave) {
+    const uint32_t ncell = e0 - s0, rem = ncell % kWave;
+    const bool use_left = ncell > (uint32_t)kWave && rem != 0u && rem <= kLeftF;
+    const uint32_t nlane = use_left ? ncell / kWave : (ncell + kWave - 1) / kWave;
+    const uint32_t nleft = use_left ? rem : 0u;
+    const uint32_t left0 = s0 + kWave * nlane;
+    for (uint32_t ch = 0; ch < nlane; ++ch) {
+        const uint32_t t0 = s0 + kWave * ch;
+        const bool with_left = (ch + 1 == nlane) && nleft;
         const uint32_t p = t0 + lane;
         const bool act = p < e0;
         const uint32_t pc = act ? p : s0;
@@ -374,7 +487,9 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, 
         const bool fs = act && aux_type(aux) != TY_BOUNDARY;
         const bool kin = act && aux_kin(aux);
         const bool tgt = fs || kin;
-        if (__ballot(tgt) == 0ull) continue;
+        const bool lanes_any = __ballot(tgt) != 0ull;
+        if (!lanes_any && !with_left) continue;
+        if (with_left && lane < 3u * nleft) accf[lane / 3u][lane % 3u] = 0.0;
         const T ma = fabs(me.w);
         double fx = 0.0, fy = 0.0, fz = 0.0;
         uint32_t witer = 0;
@@ -400,44 +515,72 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, 
                 mlds[2 * q + 1][lane] = (uint32_t)(m >> 32);
             }
             __syncthreads();
-            {
-                uint32_t mine = 0;
+            if (lanes_any) {
+                {
+                    uint32_t mine = 0;
 #pragma unroll
-                for (int h = 0; h < 2 * kScWords; ++h) mine += __popc(mlds[h][lane]);
+                    for (int h = 0; h < 2 * kScWords; ++h) mine += __popc(mlds[h][lane]);
 #pragma unroll
-                for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
-                witer += mine;
+                    for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
+                    witer += mine;
+                }
+                // a super-chunk holds ~1/S of the neighbours: sum it in T, then in FP64
+                T cx = (T)0, cy = (T)0, cz = (T)0;
+                int hw = 0;
+                uint32_t cur = mlds[0][lane];
+                for (;;) {
+                    const int k = next_hit<kScWords>(mlds, lane, hw, cur);
+                    if (k < 0) break;
+                    pair_force<T>(me, mv, md.x, md.y, kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
+                }
+                fx += (double)cx;
+                fy += (double)cy;
+                fz += (double)cz;
             }
-            // a super-chunk holds ~1/S of the neighbours: sum it in T, then in FP64
-            T cx = (T)0, cy = (T)0, cz = (T)0;
-            int hw = 0;
-            uint32_t cur = mlds[0][lane];
-            for (;;) {
-                const int k = next_hit<kScWords>(mlds, lane, hw, cur);
-                if (k < 0) break;
-                pair_force<T>(me, mv, md.x, md.y, kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
+            if (with_left) {
+                // transposed mode: lane = staged candidate slot
+                for (uint32_t t = 0; t < nleft; ++t) {
+                    const uint32_t pt = left0 + t;
+                    const uint32_t at = st.aux[pt];
+                    const bool kin_t = aux_kin(at);
+                    if (aux_type(at) == TY_BOUNDARY && !kin_t) continue;   // uniform: static boundary
+                    const V4<T> mt = st.pos[pt];
+                    const V4<T> mvt = st.vel[pt];
+                    const V2<T> mdt = dens[pt];
+                    T cx = (T)0, cy = (T)0, cz = (T)0;
+#pragma unroll
+                    for (int q = 0; q < kScWords; ++q) {
+                        if ((uint32_t)q < nws) {
+                            const uint64_t m = masks[(size_t)(w0 + q) * n + pt];
+                            const uint32_t v = q * kWave + lane;
+                            if ((m >> lane) & 1ull)
+                                pair_force<T>(mt, mvt, mdt.x, mdt.y, kin_t, fabs(mt.w), cp[v], cvel[v], cden[v], ph,
+                                              cx, cy, cz);
+                        }
+                    }
+#pragma unroll
+                    for (int m = 32; m >= 1; m >>= 1) {
+                        cx += __shfl_xor(cx, m, 64);
+                        cy += __shfl_xor(cy, m, 64);
+                        cz += __shfl_xor(cz, m, 64);
+                    }
+                    if (lane == 0) {
+                        accf[t][0] += (double)cx;
+                        accf[t][1] += (double)cy;
+                        accf[t][2] += (double)cz;
+                    }
+                }
             }
-            fx += (double)cx;
-            fy += (double)cy;
-            fz += (double)cz;
             __syncthreads();
         }
         if (lane == 0) atomicAdd(stats + 5, (unsigned long long)witer);
-        if (fs) {
-            double ex = ma * ph.gx, ey = ma * ph.gy, ez = ma * ph.gz;
-            if (aux_type(aux) == TY_SOFT) {
-                const V4<T> sp = fspring[aux_index(aux)];
-                ex += sp.x;
-                ey += sp.y;
-                ez += sp.z;
-            }
-            force[p] = V4<T>{(T)(fx + ex), (T)(fy + ey), (T)(fz + ez), (T)0};
-        } else if (kin) {
-            force[p] = V4<T>{(T)fx, (T)fy, (T)fz, (T)0};
-            double *fb = fbody + 3u * aux_index(aux);
-            fb[0] = fx;
-            fb[1] = fy;
-            fb[2] = fz;
+        if (tgt) store_force<T>(p, aux, ma, fx, fy, fz, ph, fspring, force, fbody);
+        if (with_left && lane < nleft) {
+            const uint32_t pt = left0 + lane;
+            const uint32_t at = st.aux[pt];
+            if (aux_type(at) != TY_BOUNDARY || aux_kin(at))
+                store_force<T>(pt, at, fabs(st.pos[pt].w), accf[lane][0], accf[lane][1], accf[lane][2], ph, fspring,
+                               force, fbody);
         }
     }
 }
