@@ -89,7 +89,8 @@ typedef struct {
     double domain_lo[3];       /* uniform grid bounds [m]; particles outside use the edge cells */
     double domain_hi[3];
     double v_max;              /* |v| above this flags SPH_ERR_UNSTABLE; 0 = only non-finite */
-    uint32_t reserved[8];      /* must be zero */
+    uint32_t max_probes;       /* capacity of density probe points (sph_set_probes), <= 2^20; 0 = none */
+    uint32_t reserved[7];      /* must be zero */
 } sph_params;
 
 typedef struct {               /* caller-owned host arrays, read only during sph_init */
@@ -204,6 +205,25 @@ sph_status sph_synchronize(sph_ctx *ctx);
 sph_status sph_profile_begin(sph_ctx *ctx, uint32_t max_steps);
 sph_status sph_profile_read(sph_ctx *ctx, double *ms, uint32_t *launches, uint32_t n_phases);
 const char *sph_profile_phase_name(uint32_t phase);
+
+/*
+ * Density probes: the density field of the fluid and soft particles at given
+ * points (Sec. 3.4: density at grid points from particle proximity and the
+ * smoothing kernel, reusing the uniform-grid hash),
+ *   rho(p) = sum_{j fluid/soft, predicate(p, x_j)} m_j W(|p - x_j|),
+ * evaluated every step on the state the force pass sees (after placement, before
+ * integration).  points: [3n] host array; frame: [n] object id of a kinematic
+ * body whose frame the point is given in (moves with the body), or -1 for world
+ * coordinates.  n <= max_probes.  Replaces the previous set (the host arrays are
+ * copied; the caller keeps ownership); the values read zero until the next
+ * step.  SPH_ERR_ARG for n > max_probes, a non-finite point or a frame that is
+ * not a kinematic object.  sph_read_probes copies the last step's values into
+ * the caller's [n] doubles, n equal to the count last set, and synchronises;
+ * it reports pending step errors like sph_synchronize.  The probe points are
+ * rounded to the run precision; the support test is the particle-pair one.
+ */
+sph_status sph_set_probes(sph_ctx *ctx, uint32_t n, const double *points, const int32_t *frame);
+sph_status sph_read_probes(sph_ctx *ctx, double *rho, uint32_t n);
 
 /* Release the context (not the caller's workspace).  NULL is accepted. */
 sph_status sph_destroy(sph_ctx *ctx);

@@ -82,6 +82,7 @@ def lib():
         L.orc_body_place.argtypes = [C.c_int64, i32, C.c_int32, d, d, d, d, d, d, d]
         L.orc_pose_advance.argtypes = [d, d, d, d, C.c_double]
         L.orc_density.argtypes = [P, C.c_int64, d, d, u8, d, C.c_int64, i64, i64, i64, i64, d, d]
+        L.orc_probe_density.argtypes = [P, C.c_int64, d, d, u8, C.c_int64, d, d]
         L.orc_springs.argtypes = [C.c_int64, d, d, C.c_int64, u32, d, d, d, d]
         L.orc_forces.argtypes = [P, C.c_int64, d, d, d, u8, d, d, d, d, C.c_int64, i64, i64, i64,
                                  i64, d]
@@ -164,6 +165,19 @@ def neighbors(params, precision, x, targets=None, use_grid=True):
     if nt:
         offs[1:] = np.cumsum(counts)[:-1]
     return counts, offs, ids[:total]
+
+
+def probe_density(params, precision, x, mass, type_, points):
+    """Density of fluid and soft particles at world points (Eq. density at a
+    free point), brute force over all particles."""
+    P = make_params(params, precision)
+    x, mass = _f64(x), _f64(mass)
+    t = np.ascontiguousarray(type_, np.uint8)
+    pts = _f64(points).reshape(-1, 3)
+    out = np.zeros(pts.shape[0])
+    lib().orc_probe_density(C.byref(P), x.shape[0], _p(x, C.c_double), _p(mass, C.c_double),
+                            _p(t, C.c_uint8), pts.shape[0], _p(pts, C.c_double), _p(out, C.c_double))
+    return out
 
 
 def quat_to_R(q):
@@ -375,12 +389,27 @@ class Oracle:
                          _p(F, C.c_double), _p(T, C.c_double))
         return F, T
 
-    def step(self, keep_neighbors=False):
+    def probe_points_world(self, points, frame):
+        """World coordinates of probe points given in world (frame -1) or in
+        the frame of kinematic object `frame` (c + R p), with the current
+        poses."""
+        pts = _f64(points).reshape(-1, 3).copy()
+        for t, o in enumerate(np.asarray(frame, np.int64)):
+            if o >= 0:
+                c, q = self.pose[int(o)][0], self.pose[int(o)][1]
+                pts[t] = c + quat_to_R(q).reshape(3, 3) @ pts[t]
+        return pts
+
+    def step(self, keep_neighbors=False, probes=None):
         """One step: placement, keys, neighbours, springs, density, forces,
         wrench, integration, pose advance.  Returns the quantities computed
-        from the pre-integration state and updates x, v, poses."""
+        from the pre-integration state and updates x, v, poses.  `probes` =
+        (points, frame) adds the probe densities of that state as "probe"."""
         self.place()
         out = {"x_pre": self.x.copy(), "v_pre": self.v.copy()}
+        if probes is not None:
+            w = self.probe_points_world(*probes)
+            out["probe"] = probe_density(self.params, self.prec, self.x, self.mass, self.type, w)
         out["keys"] = cell_keys(self.params, self.prec, self.x)
         nbr = neighbors(self.params, self.prec, self.x)
         if keep_neighbors:

@@ -467,6 +467,35 @@ void orc_density(const orc_params *p, int64_t n, const double *x, const double *
 }
 
 /* ------------------------------------------------------------------ */
+/* Density probes: the summation of Eq. density evaluated at a free point */
+/* (Sec. 3.4 reads the fluid density field of the tank), over fluid and   */
+/* soft particles only.  The point is first rounded to the run precision */
+/* (the precision particle positions are stored in), then every particle */
+/* is tested with the same support predicate as a particle pair.         */
+/* Brute force over all particles: no grid involved.                    */
+/* ------------------------------------------------------------------ */
+
+void orc_probe_density(const orc_params *p, int64_t n, const double *x, const double *mass,
+                       const uint8_t *type, int64_t np, const double *pts, double *out)
+{
+    orc_grid g;
+    orc_grid_setup(p, &g);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < np; ++t) {
+        double q[3];
+        for (int a = 0; a < 3; ++a) q[a] = p->precision == 0 ? (double)(float)pts[3 * t + a] : pts[3 * t + a];
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (type[j] == ORC_BOUNDARY) continue;
+            if (!is_nbr(p, &g, q, x + 3 * j)) continue;
+            double d[3];
+            s += mass[j] * orc_W(dist(q, x + 3 * j, d), p->h);
+        }
+        out[t] = s;
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Springs of the soft bodies (Sec. 3.2 mass-spring, Alg. 2).            */
 /* f_i += -[k (|x_ij| - L0) + c (v_ij . e_ij)] e_ij, e_ij = x_ij/|x_ij| */
 /* ------------------------------------------------------------------ */

@@ -27,12 +27,13 @@ FIELD_NAMES = {"x": SPH_FIELD_X, "v": SPH_FIELD_V, "rho": SPH_FIELD_RHO, "p": SP
                "fspring": SPH_FIELD_SPRING}
 STATUS = {0: "SPH_OK", 1: "SPH_ERR_ARG", 2: "SPH_ERR_WORKSPACE", 3: "SPH_ERR_DEVICE",
           4: "SPH_ERR_STATE", 5: "SPH_ERR_UNSTABLE", 6: "SPH_ERR_UNSUPPORTED", 7: "SPH_ERR_CAPACITY"}
-N_PHASES = 9
+N_PHASES = 10
 
 EXPORTED = ["sph_workspace_size", "sph_init", "sph_set_body_pose", "sph_step", "sph_get_body_wrench",
             "sph_reset_smoothing", "sph_read_field", "sph_debug_neighbors", "sph_debug_neighbors_of",
             "sph_get_stats", "sph_get_info",
             "sph_synchronize", "sph_profile_begin", "sph_profile_read", "sph_profile_phase_name",
+            "sph_set_probes", "sph_read_probes",
             "sph_destroy", "sph_status_string", "sph_last_error"]
 
 
@@ -47,7 +48,7 @@ class SphParams(C.Structure):
                 ("smoothing_window", C.c_uint32), ("h", C.c_double), ("rho0", C.c_double),
                 ("k_pressure", C.c_double), ("nu", C.c_double), ("gravity", C.c_double * 3),
                 ("dt", C.c_double), ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
-                ("v_max", C.c_double), ("reserved", C.c_uint32 * 8)]
+                ("v_max", C.c_double), ("max_probes", C.c_uint32), ("reserved", C.c_uint32 * 7)]
 
 
 class SphScene(C.Structure):
@@ -100,6 +101,8 @@ def load_library(path=None):
     L.sph_profile_read.argtypes = [vp, d3, C.POINTER(C.c_uint32), C.c_uint32]
     L.sph_profile_phase_name.argtypes = [C.c_uint32]
     L.sph_profile_phase_name.restype = C.c_char_p
+    L.sph_set_probes.argtypes = [vp, C.c_uint32, d3, C.POINTER(C.c_int32)]
+    L.sph_read_probes.argtypes = [vp, d3, C.c_uint32]
     L.sph_destroy.argtypes = [vp]
     L.sph_status_string.argtypes = [C.c_int]
     L.sph_status_string.restype = C.c_char_p
@@ -117,7 +120,7 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None and a.size else None
 
 
-def make_params(params: dict, precision: str, v_max: float = 0.0) -> SphParams:
+def make_params(params: dict, precision: str, v_max: float = 0.0, max_probes: int = 0) -> SphParams:
     P = SphParams()
     P.abi_version = SPH_ABI_VERSION
     P.precision = SPH_FP64 if precision == "f64" else SPH_FP32
@@ -129,6 +132,7 @@ def make_params(params: dict, precision: str, v_max: float = 0.0) -> SphParams:
     P.domain_lo[:] = list(params["domain_lo"])
     P.domain_hi[:] = list(params["domain_hi"])
     P.v_max = float(v_max)
+    P.max_probes = int(max_probes)
     return P
 
 
@@ -181,7 +185,7 @@ class Sim:
     device (or `stream`, a torch.cuda.Stream).
     """
 
-    def __init__(self, scene, precision=None, device="cuda", stream=None, v_max=0.0, params=None):
+    def __init__(self, scene, precision=None, device="cuda", stream=None, v_max=0.0, params=None, max_probes=0):
         import torch
         self.torch = torch
         self.L = load_library()
@@ -191,7 +195,7 @@ class Sim:
         pr = dict(scene.params)
         if params:
             pr.update(params)
-        self.P = make_params(pr, self.precision, v_max)
+        self.P = make_params(pr, self.precision, v_max, max_probes)
         A = _SceneArrays(scene)
         out = C.c_size_t(0)
         st = self.L.sph_workspace_size(C.byref(self.P), C.byref(A.struct), C.byref(out))
@@ -286,6 +290,21 @@ class Sim:
         if t.size:
             offs[1:] = np.cumsum(counts)[:-1]
         return counts, offs, ids[:tot.value].astype(np.int64)
+
+    def set_probes(self, points, frame=None):
+        """Density probe points ([n,3]); frame[i] = kinematic object id of the
+        body whose frame point i is given in, or -1 for world coordinates."""
+        pts = np.ascontiguousarray(points, np.float64).reshape(-1, 3)
+        fr = np.full(pts.shape[0], -1, np.int32) if frame is None else np.ascontiguousarray(frame, np.int32)
+        self._check(self.L.sph_set_probes(self.ctx, pts.shape[0], _dp(pts),
+                                          fr.ctypes.data_as(C.POINTER(C.c_int32)) if fr.size else None),
+                    "sph_set_probes")
+        self.n_probes = pts.shape[0]
+
+    def read_probes(self):
+        out = np.zeros(getattr(self, "n_probes", 0))
+        self._check(self.L.sph_read_probes(self.ctx, _dp(out), out.size), "sph_read_probes")
+        return out
 
     def info(self) -> dict:
         I = SphInfo()

@@ -178,6 +178,65 @@ void launch_reset_ring(hipStream_t s, uint32_t *ring_count_slot)
     hipLaunchKernelGGL(k_reset_ring, dim3(1), dim3(64), 0, s, ring_count_slot);
 }
 
+// ------------------------------------------------------------------ density probes
+
+// rho(p) = sum over fluid/soft j with predicate(p, x_j) of m_j W(|p - x_j|):
+// the density field of Sec. 3.4 at arbitrary points, through the cell table.
+template <typename T>
+__global__ __launch_bounds__(128) void k_probe(ProbeArgs a, State<T> st, Grid g, Phys<T> ph,
+                                               const uint32_t *__restrict__ cstart,
+                                               const uint32_t *__restrict__ cend)
+{
+#pragma clang fp contract(off)
+    const uint32_t i = blockIdx.x * 128u + threadIdx.x;
+    if (i >= a.n) return;
+    double p[3] = {a.pts[3 * i], a.pts[3 * i + 1], a.pts[3 * i + 2]};
+    const int32_t f = a.frame[i];
+    if (f >= 0) {
+        const double *pose = a.poses + 16 * f;
+        double R[9];
+        quat_R(pose + 3, R);
+        double w[3];
+        for (int k = 0; k < 3; ++k) w[k] = R[3 * k] * p[0] + R[3 * k + 1] * p[1] + R[3 * k + 2] * p[2];
+        for (int k = 0; k < 3; ++k) p[k] = pose[k] + w[k];
+    }
+    const V4<T> me{(T)p[0], (T)p[1], (T)p[2], (T)0};
+    T lo[3], inv;
+    grid_lo_inv<T>(g, lo, inv);
+    const T R2 = grid_R2<T>(g);
+    const int cx = cell_coord<T>(me.x, lo[0], inv, g.dims[0]);
+    const int cy = cell_coord<T>(me.y, lo[1], inv, g.dims[1]);
+    const int cz = cell_coord<T>(me.z, lo[2], inv, g.dims[2]);
+    double acc = 0.0;
+    for (int k = 0; k < 27; ++k) {
+        int ox, oy, oz;
+        stencil_offset(k, ox, oy, oz);
+        const int nx = cx + ox, ny = cy + oy, nz = cz + oz;
+        if (nx < 0 || ny < 0 || nz < 0 || nx >= g.dims[0] || ny >= g.dims[1] || nz >= g.dims[2]) continue;
+        const uint32_t key = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
+        const uint32_t e = cend[key];
+        for (uint32_t j = cstart[key]; j < e; ++j) {
+            const V4<T> c = st.pos[j];
+            if (c.w < (T)0 || aux_type(st.aux[j]) == TY_BOUNDARY) continue;
+            if (!within_support<T>(me, c, R2)) continue;
+            acc += (double)c.w * kernel_w64<T>(c, me, ph);
+        }
+    }
+    a.out[i] = acc;
+}
+
+template <typename T>
+void launch_probe(hipStream_t s, const ProbeArgs &a, State<T> st, const Grid &g, const Phys<T> &ph,
+                  const uint32_t *cstart, const uint32_t *cend)
+{
+    if (!a.n) return;
+    hipLaunchKernelGGL(k_probe<T>, dim3((a.n + 127) / 128), dim3(128), 0, s, a, st, g, ph, cstart, cend);
+}
+template void launch_probe<float>(hipStream_t, const ProbeArgs &, State<float>, const Grid &, const Phys<float> &,
+                                  const uint32_t *, const uint32_t *);
+template void launch_probe<double>(hipStream_t, const ProbeArgs &, State<double>, const Grid &,
+                                   const Phys<double> &, const uint32_t *, const uint32_t *);
+
 // ------------------------------------------------------------------ springs
 
 template <typename T>

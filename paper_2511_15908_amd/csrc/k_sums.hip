@@ -172,25 +172,6 @@ __device__ __forceinline__ int next_hit(uint32_t (*mlds)[kWave], uint32_t lane, 
 
 // ------------------------------------------------------------------ density
 
-// Kernel value W(|c - me|) evaluated in FP64 from the exact T-precision
-// coordinate differences: p = k (rho - rho0) turns a relative density error e
-// into e rho / (rho - rho0) (~1e4 e near rest) in the pressure, whose pair
-// terms nearly cancel, so the density sum carries FP64 terms.
-template <typename T>
-__device__ __forceinline__ double kernel_w64(const V4<T> &c, const V4<T> &me, const Phys<T> &ph)
-{
-    const double dx = (double)(c.x - me.x), dy = (double)(c.y - me.y), dz = (double)(c.z - me.z);
-    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    // r from an FP32 rsqrt seed and one Newton step in FP64 (~1e-14)
-    const double y = (double)frsqrt((float)fmax(r2, 1e-30));
-    double r = r2 * y;
-    r = fma(0.5 * y, fma(-r, r, r2), r);
-    const double q = r * ph.inv_h64;
-    const double t2 = fmax(2.0 - q, 0.0);
-    const double t1 = fmax(1.0 - q, 0.0);
-    return ph.alpha6_64 * (t2 * t2 * t2 - 4.0 * (t1 * t1 * t1));
-}
-
 __device__ __forceinline__ double wave_sum_f64(double v)
 {
 #pragma unroll

@@ -14,9 +14,9 @@ using namespace sphk;
 
 namespace {
 
-constexpr uint32_t kPhases = 9;
+constexpr uint32_t kPhases = 10;
 const char *kPhaseNames[kPhases] = {"place",   "keys",   "sort",   "reorder",  "springs",
-                                    "density", "forces", "wrench", "integrate"};
+                                    "density", "forces", "wrench", "integrate", "probes"};
 
 struct Carve {
     char *base;
@@ -65,6 +65,11 @@ struct sph_ctx {
     uint32_t *err = nullptr;
     unsigned long long *stats = nullptr;
     int32_t *obj_of_id = nullptr;
+    uint32_t max_probes = 0, n_probes = 0;
+    double *probe_pts = nullptr, *probe_out = nullptr;
+    int32_t *probe_frame = nullptr;
+    std::vector<double> probe_host_pts;
+    std::vector<int32_t> probe_host_frame;
     uint64_t steps = 0;
     bool dead = false;
     std::string last_error;
@@ -98,7 +103,7 @@ sph_status dev_fail(sph_ctx *c, hipError_t e, const char *what)
 bool finite3(const double *v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
 
 struct Plan {
-    uint32_t n, nb, nk, rows, nsp2, nblk_w, nslots, K, nblk_sort;
+    uint32_t n, nb, nk, rows, nsp2, nblk_w, nslots, K, nblk_sort, max_probes;
     int prec;
 };
 
@@ -119,6 +124,10 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
             why = "reserved fields must be zero";
             return SPH_ERR_ARG;
         }
+    if (p->max_probes > (1u << 20)) {
+        why = "max_probes must be <= 2^20";
+        return SPH_ERR_ARG;
+    }
     if (p->precision != SPH_FP32 && p->precision != SPH_FP64) {
         why = "precision must be SPH_FP32 or SPH_FP64";
         return SPH_ERR_ARG;
@@ -269,6 +278,7 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
     pl.K = p->smoothing_window;
     pl.nblk_sort = (n + 2047) / 2048;
     pl.prec = p->precision;
+    pl.max_probes = p->max_probes;
     return SPH_OK;
 }
 
@@ -316,6 +326,9 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
     c->err = cv.take<uint32_t>(16);
     c->stats = cv.take<unsigned long long>(8 * 8);
     c->obj_of_id = cv.take<int32_t>(n * 4);
+    c->probe_pts = cv.take<double>((size_t)pl.max_probes * 3 * 8);
+    c->probe_frame = cv.take<int32_t>((size_t)pl.max_probes * 4);
+    c->probe_out = cv.take<double>((size_t)pl.max_probes * 8);
     *total = cv.off + 256;
 }
 
@@ -406,6 +419,12 @@ void one_step(sph_ctx *c)
     launch_forces<T>(s, c->n, st, c->grid, phys<T>(c), c->cstart, c->cend, (const V2<T> *)c->dens, c->masks,
                      (const V4<T> *)c->fspring, (V4<T> *)c->force, c->fbody, c->err, c->stats);
     prof_mark(c, 6, false);
+    prof_mark(c, 9, true);
+    if (c->n_probes) {
+        ProbeArgs pa{c->n_probes, c->probe_pts, c->probe_frame, c->poses, c->probe_out};
+        launch_probe<T>(s, pa, st, c->grid, phys<T>(c), c->cstart, c->cend);
+    }
+    prof_mark(c, 9, false);
     prof_mark(c, 7, true);
     launch_wrench(s, ba);
     prof_mark(c, 7, false);
@@ -670,6 +689,7 @@ sph_status sph_init(const sph_params *params, const sph_scene *scene, void *d_wo
     c->nblk_w = pl.nblk_w;
     c->K = pl.K;
     c->n_objects = scene->n_objects;
+    c->max_probes = pl.max_probes;
     c->grid = g;
     c->cell_size = cs;
     c->stream = (hipStream_t)hip_stream;
@@ -773,6 +793,47 @@ sph_status sph_get_body_wrench(sph_ctx *ctx, uint32_t object, double F[3], doubl
         T[a] = out[3 + a];
     }
     return st;
+}
+
+sph_status sph_set_probes(sph_ctx *ctx, uint32_t n, const double *points, const int32_t *frame)
+{
+    if (!ctx) return SPH_ERR_ARG;
+    if (ctx->dead) return SPH_ERR_STATE;
+    if (n > ctx->max_probes || (n && (!points || !frame))) return SPH_ERR_ARG;
+    std::vector<double> pts(points, points + 3 * (size_t)n);
+    std::vector<int32_t> fr(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!finite3(points + 3 * i)) return SPH_ERR_ARG;
+        if (frame[i] < 0) {
+            fr[i] = -1;
+        } else {
+            if ((uint32_t)frame[i] >= ctx->n_objects || ctx->kin_of_object[frame[i]] < 0) return SPH_ERR_ARG;
+            fr[i] = ctx->kin_of_object[frame[i]];
+        }
+    }
+    // the previous upload may still read the host copies
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->probe_host_pts.swap(pts);
+    ctx->probe_host_frame.swap(fr);
+    if (n) {
+        HIPCHK(ctx, hipMemcpyAsync(ctx->probe_pts, ctx->probe_host_pts.data(), 24 * (size_t)n,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->probe_frame, ctx->probe_host_frame.data(), 4 * (size_t)n,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        launch_clear_u32(ctx->stream, (uint32_t *)ctx->probe_out, 2 * (size_t)n);
+    }
+    ctx->n_probes = n;
+    HIPCHK(ctx, hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status sph_read_probes(sph_ctx *ctx, double *rho, uint32_t n)
+{
+    if (!ctx || (n && !rho)) return SPH_ERR_ARG;
+    if (ctx->dead) return SPH_ERR_STATE;
+    if (n != ctx->n_probes) return SPH_ERR_ARG;
+    if (n) HIPCHK(ctx, hipMemcpyAsync(rho, ctx->probe_out, 8 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+    return check_err(ctx);
 }
 
 sph_status sph_reset_smoothing(sph_ctx *ctx, uint32_t object)

@@ -187,6 +187,25 @@ template <>
 __device__ __forceinline__ double grid_R2<double>(const Grid &g) { return g.R2_64; }
 
 
+// Kernel value W(|c - me|) evaluated in FP64 from the exact T-precision
+// coordinate differences: p = k (rho - rho0) turns a relative density error e
+// into e rho / (rho - rho0) (~1e4 e near rest) in the pressure, whose pair
+// terms nearly cancel, so the density sum carries FP64 terms.
+template <typename T>
+__device__ __forceinline__ double kernel_w64(const V4<T> &c, const V4<T> &me, const Phys<T> &ph)
+{
+    const double dx = (double)(c.x - me.x), dy = (double)(c.y - me.y), dz = (double)(c.z - me.z);
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    // r from an FP32 rsqrt seed and one Newton step in FP64 (~1e-14)
+    const double y = (double)frsqrt((float)fmax(r2, 1e-30));
+    double r = r2 * y;
+    r = fma(0.5 * y, fma(-r, r, r2), r);
+    const double q = r * ph.inv_h64;
+    const double t2 = fmax(2.0 - q, 0.0);
+    const double t1 = fmax(1.0 - q, 0.0);
+    return ph.alpha6_64 * (t2 * t2 * t2 - 4.0 * (t1 * t1 * t1));
+}
+
 // --- launchers (k_grid.hip) ---
 template <typename T>
 void launch_keys(hipStream_t s, uint32_t n, const V4<T> *pos, const Grid &g, uint32_t *keys);
@@ -236,6 +255,17 @@ void launch_wrench(hipStream_t s, const BodyArgs &b);
 void launch_set_pose(hipStream_t s, double *pose_slot, const double c[3], const double q[4],
                      const double v[3], const double w[3]);
 void launch_reset_ring(hipStream_t s, uint32_t *ring_count_slot);
+
+struct ProbeArgs {
+    uint32_t n;
+    const double *pts;       // [3n] world or body-frame coordinates
+    const int32_t *frame;    // [n] kinematic index of the body frame, or -1
+    const double *poses;     // [16 nk]
+    double *out;             // [n]
+};
+template <typename T>
+void launch_probe(hipStream_t s, const ProbeArgs &a, State<T> st, const Grid &g, const Phys<T> &ph,
+                  const uint32_t *cstart, const uint32_t *cend);
 
 struct SpringArgs {
     uint32_t rows;

@@ -357,3 +357,62 @@ def test_jittered_dam_break_density(orc):
     rho, _ = orc.density(sc.params, "f64", o.x, sc.mass, sc.type, o.psi, core)
     assert np.abs(rho / 1000.0 - 1.0).max() < 2e-3
     assert abs(rho.mean() / 1000.0 - GOLD["lattice_density_over_rho0"]["value"]) < 2e-4
+
+
+# ---------------------------------------------------------------- density probes
+
+def test_probe_density_lattice(orc):
+    """Eq. density at a free point: at a lattice site it is the site's density
+    (the pinned lattice value); half-way between sites the kernel's aliasing
+    error keeps it within 1e-4 of rho0 (Poisson summation), so a dropped or
+    doubled particle (1/251 of the sum) fails; boundary particles add nothing
+    and soft particles count like fluid."""
+    mp = _mp()
+    x, c = mp.lattice()
+    n = x.shape[0]
+    P = mp.params()
+    mass = np.full(n, 1000.0 * mp.S ** 3)
+    t = np.zeros(n, np.uint8)
+    s = mp.S
+    pts = np.array([x[c], x[c] + [s / 2, s / 2, s / 2], x[c] + [0.3 * s, -0.1 * s, 0.45 * s]])
+    rho = orc.probe_density(P, "f64", x, mass, t, pts)
+    v = GOLD["lattice_density_over_rho0"]["value"]
+    assert rho[0] / 1000.0 == pytest.approx(v, rel=1e-13)
+    assert abs(rho[1] / 1000.0 - 1.0) < 1e-4 and abs(rho[2] / 1000.0 - 1.0) < 1e-4
+    t2 = t.copy()
+    t2[::3] = 1                                    # soft counts like fluid
+    assert np.array_equal(orc.probe_density(P, "f64", x, mass, t2, pts), rho)
+    xb = np.concatenate([x, x[c] + np.array([[0.2 * s, 0, 0], [0, 0.7 * s, 0]])])
+    tb = np.concatenate([t, [2, 2]]).astype(np.uint8)
+    mb = np.concatenate([mass, [5.0, 5.0]])
+    assert np.array_equal(orc.probe_density(P, "f64", xb, mb, tb, pts), rho)   # boundary: nothing
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_probe_density_at_particles_is_density(orc, prec):
+    """A probe placed on a fluid particle reads that particle's density (same
+    predicate, same terms) in a fluid-only scene."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=91, with_soft=False, with_body=False)
+    keep = sc.type == 0
+    x = orc.round_to(sc.x[keep], prec)
+    m = sc.mass[keep]
+    n = x.shape[0]
+    idx = np.arange(0, n, 37)
+    rho, _ = orc.density(sc.params, prec, x, m, np.zeros(n, np.uint8), np.zeros(n), idx)
+    pr = orc.probe_density(sc.params, prec, x, m, np.zeros(n, np.uint8), x[idx])
+    assert np.allclose(pr, rho, rtol=1e-15, atol=0)
+
+
+def test_probe_points_in_body_frame(orc):
+    """Body-frame probes are mapped by c + R(q) p with the current pose."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=92)
+    o = orc.Oracle(sc, "f64")
+    ang = 0.7
+    q = np.array([math.cos(ang / 2), 0.0, 0.0, math.sin(ang / 2)])        # rotation about z
+    o.set_pose(1, [0.01, -0.02, 0.03], q, np.zeros(3), np.zeros(3))
+    w = o.probe_points_world([[0.1, 0.0, 0.0], [0.0, 0.0, 0.05], [0.2, 0.2, 0.2]], [1, 1, -1])
+    assert np.allclose(w[0], [0.01 + 0.1 * math.cos(ang), -0.02 + 0.1 * math.sin(ang), 0.03], atol=1e-15)
+    assert np.allclose(w[1], [0.01, -0.02, 0.08], atol=1e-15)
+    assert np.array_equal(w[2], [0.2, 0.2, 0.2])
