@@ -26,11 +26,21 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+# Plain (non-packed) VALU lane operations per second: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz (the published FP32 figure counts an FMA as 2 and packed
+# FP32 as 2 more: 157.3 / 4).
+PEAK_LANE_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic FLOPs per neighbour pair of the method's pair expressions
-# (density: r^2, r, the cubic spline and the weighted sum; force: r^2, r,
-# dW/dr, the symmetric pressure term, the Brookshaw viscosity term and the
-# vector accumulation), counted as written in the oracle, FMA = 2.
+# Algorithmic work of the neighbour sums in VALU lane operations (add, mul,
+# fma, compare = 1; sqrt, reciprocal = 4): a candidate test costs 7 (three
+# differences, r^2, compare); the method needs 1000 candidate tests per
+# particle (5^3 stencil of cells of size h around each particle) and
+# 14 lane-ops per neighbour for the density term and 45 for the force term.
+LANE_OPS_CANDIDATE = 7
+CANDIDATES_PER_PARTICLE = 1000
+LANE_OPS_DENSITY_PAIR = 14
+LANE_OPS_FORCE_PAIR = 45
+# The same in FLOPs (FMA = 2) as written in the oracle, for reference.
 FLOP_DENSITY_PAIR = 17
 FLOP_FORCE_PAIR = 49
 
@@ -154,12 +164,20 @@ def main():
     cand = (s1["candidates"] - s0["candidates"]) / a.steps
     ms = {k: v[0] / max(v[1], 1) for k, v in phases.items()}
     dom = "forces" if ms["forces"] >= ms["density"] else "density"
-    flops = pairs_f * FLOP_FORCE_PAIR if dom == "forces" else pairs_d * FLOP_DENSITY_PAIR
-    achieved = flops / (ms[dom] * 1e-3) / 1e12
+    lane_ops = {"density": nmov * CANDIDATES_PER_PARTICLE * LANE_OPS_CANDIDATE + pairs_d * LANE_OPS_DENSITY_PAIR,
+                "forces": pairs_f * LANE_OPS_FORCE_PAIR}
+    flops = {"density": pairs_d * FLOP_DENSITY_PAIR, "forces": pairs_f * FLOP_FORCE_PAIR}
+    achieved = lane_ops[dom] / (ms[dom] * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": f"k_{dom}", "achieved": round(achieved, 3),
-            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "peak": round(PEAK_LANE_TOPS, 2), "unit": "Tlane-op/s", "frac": round(achieved / PEAK_LANE_TOPS, 4),
             "traffic": profiled_traffic(f"k_{dom}"), "avg_launch_ms": round(ms[dom], 4),
-            "algorithmic_flops_per_launch": int(flops)}
+            "algorithmic_lane_ops_per_launch": int(lane_ops[dom]),
+            "other_kernel": {k: {"avg_launch_ms": round(ms[k], 4),
+                                 "frac": round(lane_ops[k] / (ms[k] * 1e-3) / 1e12 / PEAK_LANE_TOPS, 4)}
+                             for k in ("density", "forces") if k != dom},
+            "pair_flops": {k: {"tflops": round(flops[k] / (ms[k] * 1e-3) / 1e12, 3),
+                               "frac_of_157.3": round(flops[k] / (ms[k] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)}
+                           for k in ("density", "forces")}}
     out = {
         "metric": "SPH particle-updates/s @1M + haptic wrench Hz: surrogate vs plain, <=5% err",
         "value": value, "unit": "particle-updates/s", "n_gpus": 1, "steps": a.steps,
