@@ -112,6 +112,15 @@ mlp_status mlp_last_loss(mlp_ctx *ctx, double *loss);
 mlp_status mlp_predict_one(mlp_ctx *ctx, const float *x, float *y);
 mlp_status mlp_predict_one_device(mlp_ctx *ctx, const float *x, float *y);
 
+/* Stand-alone product C[M][N] = sum_k A(m,k) B(k,n) of the training
+ * kernels' tile engine (BF16 operands, FP32 accumulation and result), enqueued on
+ * hip_stream.  A(m,k) = A[m*lda + k] (a_layout 0) or A[k*lda + m] (1);
+ * B(k,n) = B[n*ldb + k] (b_layout 0) or B[k*ldb + n] (1).  Operands are BF16
+ * bit patterns in device memory, 16-byte aligned with lda, ldb multiples of 8;
+ * C is FP32 with row stride ldc >= N. */
+mlp_status mlp_gemm_bf16(void *hip_stream, int a_layout, int b_layout, const uint16_t *A, uint32_t lda,
+                         const uint16_t *B, uint32_t ldb, uint32_t M, uint32_t N, uint32_t K, float *C, uint32_t ldc);
+
 /* Release the context (not the workspace).  NULL is accepted. */
 mlp_status mlp_destroy(mlp_ctx *ctx);
 const char *mlp_last_error(const mlp_ctx *ctx);

@@ -14,7 +14,7 @@ PKG = Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 OUT = PKG / "libsph.so"
 BUILD = PKG / "_build"
-SOURCES = ["k_grid.hip", "k_sums.hip", "k_body.hip", "sph_api.hip"]
+SOURCES = ["k_grid.hip", "k_sums.hip", "k_body.hip", "sph_api.hip", "k_mlp.hip", "mlp_api.hip"]
 ARCH = os.environ.get("SPH_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -38,7 +38,7 @@ def _compile(src: str) -> Path:
 
 def build(verbose: bool = False) -> Path:
     BUILD.mkdir(parents=True, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT.with_suffix(".so.tmp%d" % os.getpid())
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp), *map(str, objs)]

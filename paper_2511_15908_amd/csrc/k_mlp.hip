@@ -1,0 +1,427 @@
+// Kernels of the wrench-surrogate MLP (arXiv 2511.15908 Sec. 3.3 haptic-rate
+// force; the network and its training follow include/sph_mlp.h).
+//
+// Matrix products run on the gfx950 matrix cores: v_mfma_f32_16x16x32_bf16
+// (BF16 operands, FP32 accumulation).  One 256-thread workgroup computes a
+// 64x64 tile of C; each of its four wavefronts owns a 32x32 quarter as 2x2
+// MFMA blocks.  Both operands are staged per 32-wide contraction step through
+// LDS as [row][k] BF16 (row stride 40 halves), whatever their layout in HBM
+// (K-contiguous rows are loaded 16 bytes per lane; row-contiguous operands,
+// the transposes that the backward pass needs, are loaded 16 bytes along the
+// rows and scattered into LDS), so one kernel serves every product of the
+// forward and backward passes.  Activation, bias and GELU' are fused into the
+// tile epilogue.  Products whose contraction runs over the batch (weight
+// gradients) are split along it (blockIdx.z) into FP32 partials that a second
+// kernel sums in a fixed order, so every result is bitwise reproducible.
+//
+// MFMA 16x16x32 operand layout (lane l of the wavefront): A row (l mod 16),
+// B column (l mod 16), 8 contraction elements at 8 (l / 16); C/D: column
+// (l mod 16), rows 4 (l / 16) + j, j = 0..3.
+#include "mlp_internal.h"
+
+namespace mlpk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr uint32_t kLdsK = kTileK + 8;   // padded LDS row (halves)
+
+// Round to nearest even BF16; NaN stays a quiet NaN.
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// Stage rows [r0, r0+64) x contraction [k0, k0+32) of one operand into LDS;
+// elements outside (rows >= nrows, k >= ke) read as zero.
+template <int L>
+__device__ __forceinline__ void stage(const uint16_t *__restrict__ p, uint32_t ld, uint32_t nrows, uint32_t r0,
+                                      uint32_t k0, uint32_t ke, uint16_t (*lds)[kLdsK], uint32_t t)
+{
+    if (L == LD_K) {
+        const uint32_t r = t >> 2, kc = (t & 3u) * 8u;
+        const uint32_t row = r0 + r, k = k0 + kc;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (row < nrows) {
+            const uint16_t *src = p + (size_t)row * ld + k;
+            if (k + 8u <= ke) {
+                v = *reinterpret_cast<const uint4 *>(src);
+            } else {
+                uint32_t w[4] = {0u, 0u, 0u, 0u};
+                for (uint32_t i = 0; i < 8u; ++i)
+                    if (k + i < ke) w[i >> 1] |= (uint32_t)src[i] << (16u * (i & 1u));
+                v = make_uint4(w[0], w[1], w[2], w[3]);
+            }
+        }
+        *reinterpret_cast<uint4 *>(&lds[r][kc]) = v;
+    } else {
+        const uint32_t k = t >> 3, rc = (t & 7u) * 8u;
+        const uint32_t kk = k0 + k, row = r0 + rc;
+        uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (kk < ke) {
+            const uint16_t *src = p + (size_t)kk * ld + row;
+            if (row + 8u <= nrows) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(src);
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+                for (int i = 0; i < 8; ++i) e[i] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+            } else {
+                for (uint32_t i = 0; i < 8u; ++i) e[i] = row + i < nrows ? src[i] : (uint16_t)0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[rc + i][k] = e[i];
+    }
+}
+
+__device__ __forceinline__ bf16x8 frag(const uint16_t (*lds)[kLdsK], uint32_t row, uint32_t kc)
+{
+    const uint4 v = *reinterpret_cast<const uint4 *>(&lds[row][kc]);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+template <int AL, int BL, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[kTile][kLdsK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile][kLdsK];
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    const uint32_t m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
+    const uint32_t kb = blockIdx.z * g.k_split;
+    const uint32_t ke = min(g.K, kb + g.k_split);
+    const uint32_t wm = (w >> 1) * 32u, wn = (w & 1u) * 32u;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (uint32_t k0 = kb; k0 < ke; k0 += kTileK) {
+        stage<AL>(g.A, g.lda, g.M, m0, k0, ke, As, t);
+        stage<BL>(g.B, g.ldb, g.N, n0, k0, ke, Bs, t);
+        __syncthreads();
+        const uint32_t kc = 8u * (lane >> 4), rr = lane & 15u;
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = frag(As, wm + 16u * i + rr, kc);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = frag(Bs, wn + 16u * j + rr, kc);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t col = n0 + wn + 16u * j + (lane & 15u);
+            if (col >= g.N) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t row = m0 + wm + 16u * i + 4u * (lane >> 4) + (uint32_t)v;
+                if (row >= g.M) continue;
+                const float x = acc[i][j][v];
+                if (EPI == EPI_GELU) {
+                    const float z = x + g.bias[col];
+                    g.Z[(size_t)row * g.ldz + col] = z;
+                    g.H[(size_t)row * g.ldh + col] = to_bf16(gelu(z));
+                } else if (EPI == EPI_LINEAR) {
+                    g.C[(size_t)row * g.ldc + col] = x + g.bias[col];
+                } else if (EPI == EPI_BWD_GELU) {
+                    g.H[(size_t)row * g.ldh + col] = to_bf16(x * gelu_grad(g.Z[(size_t)row * g.ldz + col]));
+                } else {
+                    g.C[((size_t)blockIdx.z * g.M + row) * g.ldc + col] = x;
+                }
+            }
+        }
+}
+
+template <int AL, int BL, int EPI>
+static void launch3(hipStream_t s, const GemmArgs &g, uint32_t splits)
+{
+    const dim3 grid((g.M + kTile - 1) / kTile, (g.N + kTile - 1) / kTile, splits);
+    hipLaunchKernelGGL((k_gemm<AL, BL, EPI>), grid, dim3(256), 0, s, g);
+}
+
+bool launch_gemm(hipStream_t s, int a_layout, int b_layout, int epi, const GemmArgs &g, uint32_t splits)
+{
+    if (!g.M || !g.N) return true;
+    // the products of the forward and backward passes
+    if (a_layout == LD_K && b_layout == LD_K && epi == EPI_GELU) launch3<LD_K, LD_K, EPI_GELU>(s, g, splits);
+    else if (a_layout == LD_K && b_layout == LD_K && epi == EPI_LINEAR) launch3<LD_K, LD_K, EPI_LINEAR>(s, g, splits);
+    else if (a_layout == LD_K && b_layout == LD_R && epi == EPI_BWD_GELU) launch3<LD_K, LD_R, EPI_BWD_GELU>(s, g, splits);
+    else if (a_layout == LD_R && b_layout == LD_R && epi == EPI_PARTIAL) launch3<LD_R, LD_R, EPI_PARTIAL>(s, g, splits);
+    else if (a_layout == LD_K && b_layout == LD_K && epi == EPI_PARTIAL) launch3<LD_K, LD_K, EPI_PARTIAL>(s, g, splits);
+    else if (a_layout == LD_K && b_layout == LD_R && epi == EPI_PARTIAL) launch3<LD_K, LD_R, EPI_PARTIAL>(s, g, splits);
+    else if (a_layout == LD_R && b_layout == LD_K && epi == EPI_PARTIAL) launch3<LD_R, LD_K, EPI_PARTIAL>(s, g, splits);
+    else return false;
+    return true;
+}
+
+// ------------------------------------------------------------------ helpers
+
+__global__ void k_splitk_reduce(const float *__restrict__ part, uint32_t splits, uint32_t count,
+                                float *__restrict__ out)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.f;
+    for (uint32_t z = 0; z < splits; ++z) s += part[(size_t)z * count + i];
+    out[i] = s;
+}
+
+void launch_splitk_reduce(hipStream_t s, const float *partials, uint32_t splits, uint32_t count, float *out)
+{
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((count + 255) / 256), dim3(256), 0, s, partials, splits, count, out);
+}
+
+__global__ void k_standardize(const float *__restrict__ X, uint32_t m, uint32_t n_in, const float *__restrict__ mu,
+                              const float *__restrict__ sd, uint16_t *__restrict__ Xb)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= m * kIn) return;
+    const uint32_t r = i / kIn, c = i % kIn;
+    float v = 0.f;
+    if (c < n_in) v = (X[(size_t)r * n_in + c] - mu[c]) / sd[c];
+    Xb[i] = to_bf16(v);
+}
+
+void launch_standardize(hipStream_t s, const float *X, uint32_t m, uint32_t n_in, const float *mu, const float *sd,
+                        uint16_t *Xb)
+{
+    if (!m) return;
+    hipLaunchKernelGGL(k_standardize, dim3((m * kIn + 255) / 256), dim3(256), 0, s, X, m, n_in, mu, sd, Xb);
+}
+
+// Loss gradient and per-block partial loss sums (rows of 16 outputs).
+__global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, const float *__restrict__ Y, uint32_t m,
+                                              uint32_t n_out, const float *__restrict__ mu,
+                                              const float *__restrict__ sd, uint16_t *__restrict__ dout,
+                                              double *__restrict__ partials)
+{
+    __shared__ double red[256];
+    const uint32_t t = threadIdx.x;
+    const uint32_t i = blockIdx.x * 256u + t;
+    double sq = 0.0;
+    if (i < m * kOutPad) {
+        const uint32_t r = i / kOutPad, j = i % kOutPad;
+        float gval = 0.f;
+        if (j < n_out) {
+            const float ys = (Y[(size_t)r * n_out + j] - mu[j]) / sd[j];
+            const float d = out[i] - ys;
+            sq = (double)d * (double)d;
+            gval = 2.0f * d / (float)((double)m * n_out);
+        }
+        dout[i] = to_bf16(gval);
+    }
+    red[t] = sq;
+    __syncthreads();
+    for (uint32_t h = 128; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void k_loss_final(const double *__restrict__ partials, uint32_t nblk, double denom, double *__restrict__ loss)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (uint32_t b = 0; b < nblk; ++b) s += partials[b];
+    *loss = s / denom;
+}
+
+uint32_t loss_blocks(uint32_t m) { return (m * kOutPad + 255) / 256; }
+
+void launch_loss(hipStream_t s, const float *out, const float *Y, uint32_t m, uint32_t n_out, const float *mu,
+                 const float *sd, uint16_t *dout, double *partials, uint32_t nblk, double *loss)
+{
+    hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(256), 0, s, out, Y, m, n_out, mu, sd, dout, partials);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, partials, nblk, (double)m * n_out, loss);
+}
+
+// db[c] = sum over rows of dz[r][c]: 64 columns x 4 row groups per block,
+// fixed-order combination.
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *__restrict__ dz, uint32_t m, uint32_t n,
+                                                   uint32_t ld, float *__restrict__ db)
+{
+    __shared__ float red[4][64];
+    const uint32_t c = blockIdx.x * 64u + (threadIdx.x & 63u), g = threadIdx.x >> 6;
+    float s = 0.f;
+    if (c < n)
+        for (uint32_t r = g; r < m; r += 4u) s += from_bf16(dz[(size_t)r * ld + c]);
+    red[g][threadIdx.x & 63u] = s;
+    __syncthreads();
+    if (g == 0 && c < n) db[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+void launch_bias_grad(hipStream_t s, const uint16_t *dz, uint32_t m, uint32_t n, uint32_t ld, float *db)
+{
+    hipLaunchKernelGGL(k_bias_grad, dim3((n + 63) / 64), dim3(256), 0, s, dz, m, n, ld, db);
+}
+
+// Adam (Kingma and Ba, Algorithm 1) with precomputed bias corrections
+// bc1 = 1 - beta1^t, bc2 = 1 - beta2^t; refreshes the BF16 copy.
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m1, float *__restrict__ m2,
+                       const float *__restrict__ g, uint16_t *__restrict__ wb, uint32_t count, float lr, float beta1,
+                       float beta2, float eps, float bc1, float bc2)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float a = beta1 * m1[i] + (1.0f - beta1) * gi;
+    const float b = beta2 * m2[i] + (1.0f - beta2) * gi * gi;
+    m1[i] = a;
+    m2[i] = b;
+    const float mh = a / bc1, vh = b / bc2;
+    const float wi = w[i] - lr * mh / (sqrtf(vh) + eps);
+    w[i] = wi;
+    wb[i] = to_bf16(wi);
+}
+
+void launch_adam(hipStream_t s, float *w, float *m1, float *m2, const float *g, uint16_t *wb, uint32_t count,
+                 float lr, float beta1, float beta2, float eps, float bc1, float bc2)
+{
+    hipLaunchKernelGGL(k_adam, dim3((count + 255) / 256), dim3(256), 0, s, w, m1, m2, g, wb, count, lr, beta1, beta2,
+                       eps, bc1, bc2);
+}
+
+__global__ void k_to_bf16(const float *__restrict__ w, uint16_t *__restrict__ wb, uint32_t count)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < count) wb[i] = to_bf16(w[i]);
+}
+
+void launch_to_bf16(hipStream_t s, const float *w, uint16_t *wb, uint32_t count)
+{
+    hipLaunchKernelGGL(k_to_bf16, dim3((count + 255) / 256), dim3(256), 0, s, w, wb, count);
+}
+
+__global__ void k_destandardize(const float *__restrict__ out, uint32_t m, uint32_t n_out, const float *__restrict__ mu,
+                                const float *__restrict__ sd, float *__restrict__ Y)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= m * n_out) return;
+    const uint32_t r = i / n_out, j = i % n_out;
+    Y[i] = out[(size_t)r * kOutPad + j] * sd[j] + mu[j];
+}
+
+void launch_destandardize(hipStream_t s, const float *out, uint32_t m, uint32_t n_out, const float *mu,
+                          const float *sd, float *Y)
+{
+    if (!m) return;
+    hipLaunchKernelGGL(k_destandardize, dim3((m * n_out + 255) / 256), dim3(256), 0, s, out, m, n_out, mu, sd, Y);
+}
+
+// Column mean and population standard deviation (two passes, FP64 sums, fixed
+// reduction tree); one block per column.
+__global__ __launch_bounds__(256) void k_fit_normalizer(const float *__restrict__ X, uint32_t m, uint32_t cols,
+                                                        float *__restrict__ mu, float *__restrict__ sd)
+{
+    __shared__ double red[256];
+    const uint32_t c = blockIdx.x, t = threadIdx.x;
+    double s = 0.0;
+    for (uint32_t r = t; r < m; r += 256u) s += (double)X[(size_t)r * cols + c];
+    red[t] = s;
+    __syncthreads();
+    for (uint32_t h = 128; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    const double mean = red[0] / (double)m;
+    __syncthreads();
+    double q = 0.0;
+    for (uint32_t r = t; r < m; r += 256u) {
+        const double d = (double)X[(size_t)r * cols + c] - mean;
+        q += d * d;
+    }
+    red[t] = q;
+    __syncthreads();
+    for (uint32_t h = 128; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double dev = sqrt(red[0] / (double)m);
+        mu[c] = (float)mean;
+        sd[c] = dev < 1e-12 ? 1.0f : (float)dev;
+    }
+}
+
+void launch_fit_normalizer(hipStream_t s, const float *X, uint32_t m, uint32_t cols, float *mu, float *sd)
+{
+    if (!cols) return;
+    hipLaunchKernelGGL(k_fit_normalizer, dim3(cols), dim3(256), 0, s, X, m, cols, mu, sd);
+}
+
+__global__ void k_fill_f32(float *__restrict__ p, float v, uint32_t count)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+void launch_fill_f32(hipStream_t s, float *p, float v, uint32_t count)
+{
+    if (!count) return;
+    hipLaunchKernelGGL(k_fill_f32, dim3((count + 255) / 256), dim3(256), 0, s, p, v, count);
+}
+
+// ------------------------------------------------------------------ one haptic tick
+
+// The whole network for one sample in one workgroup: thread u computes unit u
+// of each layer from the previous activation vector held in LDS (BF16 values,
+// FP32 arithmetic, ascending contraction order).
+__global__ __launch_bounds__(256) void k_predict_one(PredictArgs a)
+{
+    __shared__ float act[256];
+    const uint32_t t = threadIdx.x;
+    if (t < kIn) {
+        float v = 0.f;
+        if (t < a.n_in) v = (a.x[t] - a.mu_x[t]) / a.sd_x[t];
+        act[t] = from_bf16(to_bf16(v));
+    }
+    __syncthreads();
+    size_t off = 0;
+    for (uint32_t l = 0; l <= a.layers; ++l) {
+        const uint32_t K = l == 0 ? kIn : a.hidden;
+        const uint32_t N = l == a.layers ? kOutPad : a.hidden;
+        float z = 0.f;
+        if (t < N) {
+            const uint4 *row = reinterpret_cast<const uint4 *>(a.wb + off + (size_t)t * K);
+            float s = 0.f;
+            for (uint32_t k8 = 0; k8 < K / 8u; ++k8) {
+                const uint4 v = row[k8];
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    s = fmaf(from_bf16((uint16_t)(w[i >> 1] >> (16 * (i & 1)))), act[8u * k8 + (uint32_t)i], s);
+            }
+            z = s + a.w[off + (size_t)N * K + t];
+        }
+        __syncthreads();
+        if (l < a.layers) {
+            if (t < N) act[t] = from_bf16(to_bf16(gelu(z)));
+        } else if (t < a.n_out) {
+            a.y[t] = z * a.sd_y[t] + a.mu_y[t];
+        }
+        __syncthreads();
+        off += (size_t)N * K + N;
+    }
+}
+
+void launch_predict_one(hipStream_t s, const PredictArgs &a)
+{
+    hipLaunchKernelGGL(k_predict_one, dim3(1), dim3(256), 0, s, a);
+}
+
+}  // namespace mlpk

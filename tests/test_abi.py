@@ -145,3 +145,72 @@ def test_null_context_calls(P):
     assert L.sph_status_string(5) == b"simulation became unstable"
     assert L.sph_last_error(None) == b"null context"
     assert L.sph_profile_phase_name(5) == b"density"
+
+
+# ---------------------------------------------------------------- surrogate MLP ABI
+
+MLP_HEADER = os.path.join(ROOT, "include", "sph_mlp.h")
+
+
+def test_mlp_exports_every_declared_symbol(P):
+    txt = re.sub(r"/\*.*?\*/", "", open(MLP_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(mlp_[a-z_0-9]+)\s*\(", txt)))
+    assert len(names) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", str(P.LIB_PATH)], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (mlp_\w+)", out))
+    assert not [n for n in names if n not in exported]
+    from paper_2511_15908_amd import mlp
+    assert sorted(mlp.EXPORTED) == names
+
+
+def test_mlp_config_layout(P, tmp_path):
+    from paper_2511_15908_amd import mlp
+    src = tmp_path / "lay.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{MLP_HEADER}"', "int main(void){",
+             'printf("size %zu\\n", sizeof(mlp_config));']
+    for f, _ in mlp.MlpConfig._fields_:
+        lines.append(f'printf("{f} %zu\\n", offsetof(mlp_config, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split("\n") if l)
+    assert int(got["size"]) == C.sizeof(mlp.MlpConfig)
+    for f, _ in mlp.MlpConfig._fields_:
+        assert int(got[f]) == getattr(mlp.MlpConfig, f).offset, f
+
+
+def _mlp_cfg(**over):
+    from paper_2511_15908_amd import mlp
+    c = mlp.MlpConfig()
+    c.abi_version, c.n_in, c.n_out, c.hidden, c.layers, c.max_batch = 1, 126, 6, 256, 3, 4096
+    c.beta1, c.beta2, c.eps = 0.9, 0.999, 1e-8
+    for k, v in over.items():
+        if k == "reserved":
+            c.reserved[0] = v
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def test_mlp_validation_and_workspace(P):
+    from paper_2511_15908_amd import mlp
+    L = mlp.lib()
+    out = C.c_size_t(0)
+    assert L.mlp_workspace_size(C.byref(_mlp_cfg()), C.byref(out)) == 0
+    # parameters: 128x256+256 + 2 (256x256+256) + 16x256+16; activations of 4096 rows
+    assert out.value > 4 * 4 * 168720 + 4096 * 256 * 6 * 3
+    for bad in [dict(n_in=0), dict(n_in=129), dict(n_out=17), dict(hidden=100), dict(hidden=512),
+                dict(layers=0), dict(layers=5), dict(max_batch=0), dict(max_batch=70000), dict(beta1=1.0),
+                dict(eps=0.0), dict(abi_version=2), dict(reserved=1)]:
+        assert L.mlp_workspace_size(C.byref(_mlp_cfg(**bad)), C.byref(out)) == 1, bad
+    ctx = C.c_void_p()
+    # no workspace: rejected before any device work
+    assert L.mlp_init(C.byref(_mlp_cfg()), None, 0, None, C.byref(ctx)) == 2
+    assert L.mlp_destroy(None) == 0
+    assert L.mlp_param_count(None) == 0
+    # the stand-alone product rejects bad layouts and misaligned operands without launching
+    assert L.mlp_gemm_bf16(None, 2, 0, C.c_void_p(256), 8, C.c_void_p(256), 8, 8, 8, 8, C.c_void_p(256), 8) == 1
+    assert L.mlp_gemm_bf16(None, 0, 0, C.c_void_p(258), 8, C.c_void_p(256), 8, 8, 8, 8, C.c_void_p(256), 8) == 1
+    assert L.mlp_gemm_bf16(None, 0, 0, C.c_void_p(256), 4, C.c_void_p(256), 8, 8, 8, 8, C.c_void_p(256), 8) == 1
