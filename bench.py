@@ -2,7 +2,7 @@
 
 Workload: the coupled fluid + soft + rigid scene at 1M fluid particles
 (1,000,000 fluid, 8,000 soft with 66,120 springs, a 3,079-particle grabbed
-sphere driven by a seeded 1 kHz random-walk pose, 58,884 tank particles;
+sphere driven by a seeded 1 kHz random-walk pose, 59,569 tank particles;
 FP32, dt = 2.5e-4 s).  One step = one sph_step (placement, neighbour search,
 springs, density, forces, FP64 body wrench, integration); the sphere's pose
 is set every 4 steps (1 kHz).  Inputs are resident in HBM before timing.

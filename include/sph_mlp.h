@@ -8,7 +8,9 @@
  *
  * Network: x (n_in <= 128 raw features, standardised, zero-padded to 128)
  *   -> L hidden layers of H units (GELU, erf form) -> n_out <= 16 outputs
- *   (standardised targets; de-standardised on output).
+ *   (standardised targets; de-standardised on output).  With residual_from
+ *   = k > 0 the output is y = x[k-1 .. k-2+n_out] + destandardised network
+ *   output, and targets, normaliser and loss refer to y - x[k-1 ..].
  * Precision: GEMM operands (weights, activations, output gradients) in BF16,
  * accumulation in FP32 on the matrix cores; master weights, biases, Adam
  * moments, pre-activations and the loss in FP32 (loss sum in FP64).
@@ -54,7 +56,10 @@ typedef struct {
     uint32_t layers;        /* L hidden layers, 1..4 */
     uint32_t max_batch;     /* most rows per mlp_forward / training call, 1..65536 */
     float beta1, beta2, eps; /* Adam constants (0.9, 0.999, 1e-8 typical) */
-    uint32_t reserved[7];   /* must be zero */
+    uint32_t residual_from; /* 0: the outputs are the network's; k > 0: raw input columns
+                               k-1 .. k-2+n_out are added to them (the network learns the
+                               change from those inputs); k-1+n_out <= n_in */
+    uint32_t reserved[6];   /* must be zero */
 } mlp_config;
 
 typedef struct mlp_ctx mlp_ctx;
@@ -79,7 +84,8 @@ mlp_status mlp_get_params(mlp_ctx *ctx, float *params, size_t n);
  * mlp_fit_normalizer computes mean and population standard deviation of each
  * column of the m x n_in raw inputs X and m x n_out raw targets Y (device,
  * row-major) on the device (FP64 sums); a column whose deviation is below
- * 1e-12 (or zero) gets sd = 1.  mlp_set_normalizer / mlp_get_normalizer move
+ * 1e-12 (or zero) gets sd = 1.  With residual_from the target statistics are
+ * those of Y minus the residual input columns.  mlp_set_normalizer / mlp_get_normalizer move
  * the four host vectors (n_in, n_in, n_out, n_out floats). */
 mlp_status mlp_fit_normalizer(mlp_ctx *ctx, const float *X, const float *Y, uint32_t m);
 mlp_status mlp_set_normalizer(mlp_ctx *ctx, const float *mu_x, const float *sd_x, const float *mu_y,

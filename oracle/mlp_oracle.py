@@ -7,6 +7,9 @@ the HIP library.
 What it computes (plain numpy, binary64):
   * standardisation x' = (x - mu_x)/sd_x, y' = (y - mu_y)/sd_y with the
     column mean and population standard deviation (sd = 1 where < 1e-12);
+  * optionally a residual output: y = x[res_col .. res_col + n_out) + the
+    de-standardised network output, so the targets, their statistics and
+    the loss refer to y - x[res_col ..];
   * the network z_l = a_{l-1} W_l^T + b_l, a_l = GELU(z_l) for the hidden
     layers (GELU in its exact form 0.5 z (1 + erf(z / sqrt 2))), a linear
     output layer; inputs zero-padded to 128 columns, outputs padded to 16;
@@ -82,8 +85,16 @@ def pack(layers_wb):
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers_wb])
 
 
-def fit_normalizer(X, Y):
+def _res(X, n_out, res_col):
+    X = np.asarray(X, np.float64)
+    if res_col is None:
+        return np.zeros((X.shape[0], n_out))
+    return X[:, res_col:res_col + n_out]
+
+
+def fit_normalizer(X, Y, res_col=None):
     X, Y = np.asarray(X, np.float64), np.asarray(Y, np.float64)
+    Y = Y - _res(X, Y.shape[1], res_col)
     mx, my = X.mean(0), Y.mean(0)
     sx, sy = X.std(0), Y.std(0)
     sx = np.where(sx < 1e-12, 1.0, sx)
@@ -95,7 +106,7 @@ def _q(a, quant):
     return bf16(a) if quant else a
 
 
-def forward(params, X, norm, hidden, layers, n_out, quant=True):
+def forward(params, X, norm, hidden, layers, n_out, quant=True, res_col=None):
     """Returns (out in raw units [m][n_out], cache for backward)."""
     mx, sx, my, sy = (np.asarray(v, np.float64) for v in norm)
     X = np.asarray(X, np.float64)
@@ -112,16 +123,16 @@ def forward(params, X, norm, hidden, layers, n_out, quant=True):
             a = _q(gelu(z), quant)
             acts.append(a)
     out_s = zs[-1][:, :n_out]
-    return out_s * sy + my, {"acts": acts, "zs": zs, "out_s": out_s}
+    return out_s * sy + my + _res(X, n_out, res_col), {"acts": acts, "zs": zs, "out_s": out_s}
 
 
-def loss_and_grad(params, X, Y, norm, hidden, layers, n_out, quant=True):
+def loss_and_grad(params, X, Y, norm, hidden, layers, n_out, quant=True, res_col=None):
     """Loss on standardised outputs and its gradient (parameter layout)."""
     mx, sx, my, sy = (np.asarray(v, np.float64) for v in norm)
     Y = np.asarray(Y, np.float64)
     m = Y.shape[0]
-    _, c = forward(params, X, norm, hidden, layers, n_out, quant)
-    ys = (Y - my) / sy
+    _, c = forward(params, X, norm, hidden, layers, n_out, quant, res_col)
+    ys = (Y - _res(X, n_out, res_col) - my) / sy
     d = c["out_s"] - ys
     loss = float(np.sum(d * d) / (m * n_out))
     wb = unpack(params, hidden, layers)

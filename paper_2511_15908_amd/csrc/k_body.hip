@@ -182,13 +182,15 @@ void launch_reset_ring(hipStream_t s, uint32_t *ring_count_slot)
 
 // rho(p) = sum over fluid/soft j with predicate(p, x_j) of m_j W(|p - x_j|):
 // the density field of Sec. 3.4 at arbitrary points, through the cell table.
+// One wavefront per probe: the lanes stride over the particles of each of the
+// 27 cells (coalesced loads), FP64 partial sums, fixed shuffle-tree reduction.
 template <typename T>
-__global__ __launch_bounds__(128) void k_probe(ProbeArgs a, State<T> st, Grid g, Phys<T> ph,
-                                               const uint32_t *__restrict__ cstart,
-                                               const uint32_t *__restrict__ cend)
+__global__ __launch_bounds__(64) void k_probe(ProbeArgs a, State<T> st, Grid g, Phys<T> ph,
+                                              const uint32_t *__restrict__ cstart,
+                                              const uint32_t *__restrict__ cend)
 {
 #pragma clang fp contract(off)
-    const uint32_t i = blockIdx.x * 128u + threadIdx.x;
+    const uint32_t i = blockIdx.x, lane = threadIdx.x;
     if (i >= a.n) return;
     double p[3] = {a.pts[3 * i], a.pts[3 * i + 1], a.pts[3 * i + 2]};
     const int32_t f = a.frame[i];
@@ -215,14 +217,16 @@ __global__ __launch_bounds__(128) void k_probe(ProbeArgs a, State<T> st, Grid g,
         if (nx < 0 || ny < 0 || nz < 0 || nx >= g.dims[0] || ny >= g.dims[1] || nz >= g.dims[2]) continue;
         const uint32_t key = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
         const uint32_t e = cend[key];
-        for (uint32_t j = cstart[key]; j < e; ++j) {
+        for (uint32_t j = cstart[key] + lane; j < e; j += 64u) {
             const V4<T> c = st.pos[j];
             if (c.w < (T)0 || aux_type(st.aux[j]) == TY_BOUNDARY) continue;
             if (!within_support<T>(me, c, R2)) continue;
             acc += (double)c.w * kernel_w64<T>(c, me, ph);
         }
     }
-    a.out[i] = acc;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    if (lane == 0) a.out[i] = acc;
 }
 
 template <typename T>
@@ -230,7 +234,7 @@ void launch_probe(hipStream_t s, const ProbeArgs &a, State<T> st, const Grid &g,
                   const uint32_t *cstart, const uint32_t *cend)
 {
     if (!a.n) return;
-    hipLaunchKernelGGL(k_probe<T>, dim3((a.n + 127) / 128), dim3(128), 0, s, a, st, g, ph, cstart, cend);
+    hipLaunchKernelGGL(k_probe<T>, dim3(a.n), dim3(64), 0, s, a, st, g, ph, cstart, cend);
 }
 template void launch_probe<float>(hipStream_t, const ProbeArgs &, State<float>, const Grid &, const Phys<float> &,
                                   const uint32_t *, const uint32_t *);

@@ -206,7 +206,7 @@ void launch_standardize(hipStream_t s, const float *X, uint32_t m, uint32_t n_in
 // Loss gradient and per-block partial loss sums (rows of 16 outputs).
 __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, const float *__restrict__ Y, uint32_t m,
                                               uint32_t n_out, const float *__restrict__ mu,
-                                              const float *__restrict__ sd, uint16_t *__restrict__ dout,
+                                              const float *__restrict__ sd, Residual res, uint16_t *__restrict__ dout,
                                               double *__restrict__ partials)
 {
     __shared__ double red[256];
@@ -217,7 +217,9 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, con
         const uint32_t r = i / kOutPad, j = i % kOutPad;
         float gval = 0.f;
         if (j < n_out) {
-            const float ys = (Y[(size_t)r * n_out + j] - mu[j]) / sd[j];
+            float y = Y[(size_t)r * n_out + j];
+            if (res.X) y -= res.X[(size_t)r * res.ldx + res.col0 + j];
+            const float ys = (y - mu[j]) / sd[j];
             const float d = out[i] - ys;
             sq = (double)d * (double)d;
             gval = 2.0f * d / (float)((double)m * n_out);
@@ -244,9 +246,9 @@ __global__ void k_loss_final(const double *__restrict__ partials, uint32_t nblk,
 uint32_t loss_blocks(uint32_t m) { return (m * kOutPad + 255) / 256; }
 
 void launch_loss(hipStream_t s, const float *out, const float *Y, uint32_t m, uint32_t n_out, const float *mu,
-                 const float *sd, uint16_t *dout, double *partials, uint32_t nblk, double *loss)
+                 const float *sd, const Residual &res, uint16_t *dout, double *partials, uint32_t nblk, double *loss)
 {
-    hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(256), 0, s, out, Y, m, n_out, mu, sd, dout, partials);
+    hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(256), 0, s, out, Y, m, n_out, mu, sd, res, dout, partials);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, partials, nblk, (double)m * n_out, loss);
 }
 
@@ -308,30 +310,41 @@ void launch_to_bf16(hipStream_t s, const float *w, uint16_t *wb, uint32_t count)
 }
 
 __global__ void k_destandardize(const float *__restrict__ out, uint32_t m, uint32_t n_out, const float *__restrict__ mu,
-                                const float *__restrict__ sd, float *__restrict__ Y)
+                                const float *__restrict__ sd, Residual res, float *__restrict__ Y)
 {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
     if (i >= m * n_out) return;
     const uint32_t r = i / n_out, j = i % n_out;
-    Y[i] = out[(size_t)r * kOutPad + j] * sd[j] + mu[j];
+    float y = out[(size_t)r * kOutPad + j] * sd[j] + mu[j];
+    if (res.X) y += res.X[(size_t)r * res.ldx + res.col0 + j];
+    Y[i] = y;
 }
 
 void launch_destandardize(hipStream_t s, const float *out, uint32_t m, uint32_t n_out, const float *mu,
-                          const float *sd, float *Y)
+                          const float *sd, const Residual &res, float *Y)
 {
     if (!m) return;
-    hipLaunchKernelGGL(k_destandardize, dim3((m * n_out + 255) / 256), dim3(256), 0, s, out, m, n_out, mu, sd, Y);
+    hipLaunchKernelGGL(k_destandardize, dim3((m * n_out + 255) / 256), dim3(256), 0, s, out, m, n_out, mu, sd, res,
+                       Y);
 }
 
 // Column mean and population standard deviation (two passes, FP64 sums, fixed
 // reduction tree); one block per column.
+__device__ __forceinline__ double fit_value(const float *__restrict__ X, uint32_t cols, const Residual &res, uint32_t r,
+                                            uint32_t c)
+{
+    double v = (double)X[(size_t)r * cols + c];
+    if (res.X) v -= (double)res.X[(size_t)r * res.ldx + res.col0 + c];
+    return v;
+}
+
 __global__ __launch_bounds__(256) void k_fit_normalizer(const float *__restrict__ X, uint32_t m, uint32_t cols,
-                                                        float *__restrict__ mu, float *__restrict__ sd)
+                                                        Residual res, float *__restrict__ mu, float *__restrict__ sd)
 {
     __shared__ double red[256];
     const uint32_t c = blockIdx.x, t = threadIdx.x;
     double s = 0.0;
-    for (uint32_t r = t; r < m; r += 256u) s += (double)X[(size_t)r * cols + c];
+    for (uint32_t r = t; r < m; r += 256u) s += fit_value(X, cols, res, r, c);
     red[t] = s;
     __syncthreads();
     for (uint32_t h = 128; h > 0; h >>= 1) {
@@ -342,7 +355,7 @@ __global__ __launch_bounds__(256) void k_fit_normalizer(const float *__restrict_
     __syncthreads();
     double q = 0.0;
     for (uint32_t r = t; r < m; r += 256u) {
-        const double d = (double)X[(size_t)r * cols + c] - mean;
+        const double d = fit_value(X, cols, res, r, c) - mean;
         q += d * d;
     }
     red[t] = q;
@@ -358,10 +371,11 @@ __global__ __launch_bounds__(256) void k_fit_normalizer(const float *__restrict_
     }
 }
 
-void launch_fit_normalizer(hipStream_t s, const float *X, uint32_t m, uint32_t cols, float *mu, float *sd)
+void launch_fit_normalizer(hipStream_t s, const float *X, uint32_t m, uint32_t cols, const Residual &res, float *mu,
+                           float *sd)
 {
     if (!cols) return;
-    hipLaunchKernelGGL(k_fit_normalizer, dim3(cols), dim3(256), 0, s, X, m, cols, mu, sd);
+    hipLaunchKernelGGL(k_fit_normalizer, dim3(cols), dim3(256), 0, s, X, m, cols, res, mu, sd);
 }
 
 __global__ void k_fill_f32(float *__restrict__ p, float v, uint32_t count)
@@ -412,7 +426,9 @@ __global__ __launch_bounds__(256) void k_predict_one(PredictArgs a)
         if (l < a.layers) {
             if (t < N) act[t] = from_bf16(to_bf16(gelu(z)));
         } else if (t < a.n_out) {
-            a.y[t] = z * a.sd_y[t] + a.mu_y[t];
+            float y = z * a.sd_y[t] + a.mu_y[t];
+            if (a.res_col0 >= 0) y += a.x[a.res_col0 + (int32_t)t];
+            a.y[t] = y;
         }
         __syncthreads();
         off += (size_t)N * K + N;

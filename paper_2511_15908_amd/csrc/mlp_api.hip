@@ -87,6 +87,10 @@ mlp_status validate(const mlp_config *c, std::string &why)
         why = "max_batch must be 1..65536";
         return MLP_ERR_ARG;
     }
+    if (c->residual_from && c->residual_from - 1u + c->n_out > c->n_in) {
+        why = "residual columns must lie inside the inputs";
+        return MLP_ERR_ARG;
+    }
     if (!(c->beta1 >= 0.f && c->beta1 < 1.f) || !(c->beta2 >= 0.f && c->beta2 < 1.f) || !(c->eps > 0.f) ||
         !isfinite(c->eps)) {
         why = "Adam constants: 0 <= beta < 1, eps > 0";
@@ -206,11 +210,23 @@ void forward(mlp_ctx *c, const float *X, uint32_t m)
     }
 }
 
-// Loss and gradient into c->grad (forward must have run on the same rows).
-void backward(mlp_ctx *c, const float *Y, uint32_t m)
+Residual residual(const mlp_ctx *c, const float *X)
+{
+    Residual r{nullptr, 0, 0};
+    if (c->cfg.residual_from) {
+        r.X = X;
+        r.ldx = c->cfg.n_in;
+        r.col0 = c->cfg.residual_from - 1u;
+    }
+    return r;
+}
+
+// Loss and gradient into c->grad (forward must have run on the same rows X).
+void backward(mlp_ctx *c, const float *X, const float *Y, uint32_t m)
 {
     hipStream_t s = c->stream;
-    launch_loss(s, c->out, Y, m, c->cfg.n_out, c->mu_y, c->sd_y, c->dout, c->loss_part, loss_blocks(m), c->loss);
+    launch_loss(s, c->out, Y, m, c->cfg.n_out, c->mu_y, c->sd_y, residual(c, X), c->dout, c->loss_part,
+                loss_blocks(m), c->loss);
     uint32_t splits = (m + kSplitRows - 1) / kSplitRows;
     if (splits > c->max_splits) splits = c->max_splits;
     uint32_t ks = (m + splits - 1) / splits;
@@ -372,8 +388,8 @@ mlp_status mlp_fit_normalizer(mlp_ctx *c, const float *X, const float *Y, uint32
     if (!c) return MLP_ERR_ARG;
     if (c->dead) return MLP_ERR_STATE;
     if (m < 1 || !X || !Y) return arg_fail(c, "m >= 1 and device arrays required");
-    launch_fit_normalizer(c->stream, X, m, c->cfg.n_in, c->mu_x, c->sd_x);
-    launch_fit_normalizer(c->stream, Y, m, c->cfg.n_out, c->mu_y, c->sd_y);
+    launch_fit_normalizer(c->stream, X, m, c->cfg.n_in, Residual{nullptr, 0, 0}, c->mu_x, c->sd_x);
+    launch_fit_normalizer(c->stream, Y, m, c->cfg.n_out, residual(c, X), c->mu_y, c->sd_y);
     MLPCHK(c, hipGetLastError());
     std::vector<float> a(kIn), b(kIn), d(kOutPad), e(kOutPad);
     MLPCHK(c, hipMemcpyAsync(a.data(), c->mu_x, kIn * 4, hipMemcpyDeviceToHost, c->stream));
@@ -428,7 +444,7 @@ mlp_status mlp_forward(mlp_ctx *c, const float *X, uint32_t m, float *out)
     if (st != MLP_OK) return st;
     if (!out) return arg_fail(c, "null output");
     forward(c, X, m);
-    launch_destandardize(c->stream, c->out, m, c->cfg.n_out, c->mu_y, c->sd_y, out);
+    launch_destandardize(c->stream, c->out, m, c->cfg.n_out, c->mu_y, c->sd_y, residual(c, X), out);
     MLPCHK(c, hipGetLastError());
     return MLP_OK;
 }
@@ -441,7 +457,7 @@ mlp_status mlp_gradients(mlp_ctx *c, const float *X, const float *Y, uint32_t m,
     if (st != MLP_OK) return st;
     if (!Y || !grad) return arg_fail(c, "null array");
     forward(c, X, m);
-    backward(c, Y, m);
+    backward(c, X, Y, m);
     MLPCHK(c, hipGetLastError());
     MLPCHK(c, hipMemcpyAsync(grad, c->grad, c->P * sizeof(float), hipMemcpyDeviceToHost, c->stream));
     double l = 0.0;
@@ -471,7 +487,7 @@ mlp_status mlp_train_step(mlp_ctx *c, const float *X, const float *Y, uint32_t m
     if (st != MLP_OK) return st;
     if (!Y || !(lr >= 0.f) || !isfinite(lr)) return arg_fail(c, "null targets or bad rate");
     forward(c, X, m);
-    backward(c, Y, m);
+    backward(c, X, Y, m);
     return adam(c, lr);
 }
 
@@ -499,6 +515,7 @@ static PredictArgs predict_args(mlp_ctx *c, const float *x, float *y)
     a.n_out = c->cfg.n_out;
     a.hidden = c->H;
     a.layers = c->L;
+    a.res_col0 = c->cfg.residual_from ? (int32_t)c->cfg.residual_from - 1 : -1;
     return a;
 }
 

@@ -42,16 +42,22 @@ bool launch_gemm(hipStream_t s, int a_layout, int b_layout, int epi, const GemmA
 void launch_splitk_reduce(hipStream_t s, const float *partials, uint32_t splits, uint32_t count, float *out);
 void launch_standardize(hipStream_t s, const float *X, uint32_t m, uint32_t n_in, const float *mu,
                         const float *sd, uint16_t *Xb);
+// Residual input columns added to the outputs: X[r * ldx + col0 + j] (X null: none).
+struct Residual {
+    const float *X;
+    uint32_t ldx, col0;
+};
 void launch_loss(hipStream_t s, const float *out, const float *Y, uint32_t m, uint32_t n_out, const float *mu,
-                 const float *sd, uint16_t *dout, double *partials, uint32_t nblk, double *loss);
+                 const float *sd, const Residual &res, uint16_t *dout, double *partials, uint32_t nblk, double *loss);
 uint32_t loss_blocks(uint32_t m);
 void launch_bias_grad(hipStream_t s, const uint16_t *dz, uint32_t m, uint32_t n, uint32_t ld, float *db);
 void launch_adam(hipStream_t s, float *w, float *m1, float *m2, const float *g, uint16_t *wb, uint32_t count,
                  float lr, float beta1, float beta2, float eps, float bc1, float bc2);
 void launch_to_bf16(hipStream_t s, const float *w, uint16_t *wb, uint32_t count);
 void launch_destandardize(hipStream_t s, const float *out, uint32_t m, uint32_t n_out, const float *mu,
-                          const float *sd, float *Y);
-void launch_fit_normalizer(hipStream_t s, const float *X, uint32_t m, uint32_t cols, float *mu, float *sd);
+                          const float *sd, const Residual &res, float *Y);
+void launch_fit_normalizer(hipStream_t s, const float *X, uint32_t m, uint32_t cols, const Residual &res, float *mu,
+                           float *sd);
 void launch_fill_f32(hipStream_t s, float *p, float v, uint32_t count);
 
 struct PredictArgs {
@@ -61,6 +67,7 @@ struct PredictArgs {
     const float *w;      // FP32 parameters (biases are read from here)
     const float *mu_x, *sd_x, *mu_y, *sd_y;
     uint32_t n_in, n_out, hidden, layers;
+    int32_t res_col0;    // first residual input column, or -1
 };
 void launch_predict_one(hipStream_t s, const PredictArgs &a);
 

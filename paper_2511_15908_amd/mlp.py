@@ -31,7 +31,8 @@ class MlpError(RuntimeError):
 class MlpConfig(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("n_in", C.c_uint32), ("n_out", C.c_uint32),
                 ("hidden", C.c_uint32), ("layers", C.c_uint32), ("max_batch", C.c_uint32),
-                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("reserved", C.c_uint32 * 7)]
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("residual_from", C.c_uint32),
+                ("reserved", C.c_uint32 * 6)]
 
 
 _declared = False
@@ -82,7 +83,7 @@ class Mlp:
     """A network of `layers` hidden layers of `hidden` units on one GPU."""
 
     def __init__(self, n_in, n_out, hidden=256, layers=3, max_batch=4096, device="cuda", stream=None,
-                 beta1=0.9, beta2=0.999, eps=1e-8):
+                 beta1=0.9, beta2=0.999, eps=1e-8, residual_col=None):
         import torch
         self.torch = torch
         self.L = lib()
@@ -92,6 +93,7 @@ class Mlp:
         cfg.abi_version = MLP_ABI_VERSION
         cfg.n_in, cfg.n_out, cfg.hidden, cfg.layers, cfg.max_batch = n_in, n_out, hidden, layers, max_batch
         cfg.beta1, cfg.beta2, cfg.eps = beta1, beta2, eps
+        cfg.residual_from = 0 if residual_col is None else int(residual_col) + 1
         self.cfg = cfg
         nb = C.c_size_t(0)
         st = self.L.mlp_workspace_size(C.byref(cfg), C.byref(nb))

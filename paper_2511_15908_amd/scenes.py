@@ -112,6 +112,48 @@ def tank_sites(nx: int, ny: int, nz: int) -> np.ndarray:
     return np.concatenate([floor, walls[per]], 0)
 
 
+# Initial fluid placement near boundaries.  With boundary volumes psi_b from
+# the boundary particles' own neighbourhoods, a single-layer wall one spacing
+# from the first fluid layer reads about 1.37 rho0 there (its psi_b stands in
+# for the missing half space but sits closer than it); a gap of 1.7 spacings
+# reads about rho0 and starts the fluid near rest.  Obstacles keep fluid
+# sites at least OBSTACLE_CLEARANCE spacings from their particles.
+WALL_GAP = 1.7
+OBSTACLE_CLEARANCE = 1.5
+
+
+def open_tank(Wx: float, Wy: float, nz: int, s: float) -> np.ndarray:
+    """Open-top single-layer tank: floor z = 0 over [0, Wx] x [0, Wy], walls at
+    x = 0, Wx and y = 0, Wy for z = s .. nz s; each side sampled at the
+    spacing nearest s that divides it."""
+    xs = np.linspace(0.0, Wx, int(round(Wx / s)) + 1)
+    ys = np.linspace(0.0, Wy, int(round(Wy / s)) + 1)
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    floor = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], 1)
+    ring = np.concatenate([np.stack([xs, np.zeros_like(xs)], 1), np.stack([xs, np.full_like(xs, Wy)], 1),
+                           np.stack([np.zeros(ys.size - 2), ys[1:-1]], 1),
+                           np.stack([np.full(ys.size - 2, Wx), ys[1:-1]], 1)])
+    walls = [np.concatenate([ring, np.full((ring.shape[0], 1), k * s)], 1) for k in range(1, nz + 1)]
+    return np.concatenate([floor] + walls, 0)
+
+
+def tank_width(n_columns: int, s: float) -> float:
+    """Inner width of a tank holding n_columns fluid columns WALL_GAP spacings
+    from both walls."""
+    return (n_columns - 1 + 2.0 * WALL_GAP) * s
+
+
+def clearance(points: np.ndarray, dmin: float):
+    """exclude_fn: true for positions closer than dmin to any of points."""
+    from scipy.spatial import cKDTree
+    tree = cKDTree(np.asarray(points, np.float64))
+
+    def fn(xyz):
+        d, _ = tree.query(xyz, k=1)
+        return d < dmin
+    return fn
+
+
 def block_surface_sites(i0, i1, j0, j1, k0, k1) -> np.ndarray:
     g = _grid(i0, i1, j0, j1, k0, k1)
     surf = ((g[:, 0] == i0) | (g[:, 0] == i1) | (g[:, 1] == j0) | (g[:, 1] == j1)
@@ -127,9 +169,11 @@ def fibonacci_sphere(n: int, r: float, c) -> np.ndarray:
     return np.asarray(c, np.float64) + r * np.stack([rho * np.cos(phi), rho * np.sin(phi), z], 1)
 
 
-def fill_to_count(n_fluid, i_range, j_range, s, occupied: set, exclude_fn=None, k_start=1):
+def fill_to_count(n_fluid, i_range, j_range, s, occupied: set, exclude_fn=None, k_start=1, gap=1.0):
     """Take tank-interior lattice sites in (k, j, i) order, skipping occupied
-    sites and sites for which exclude_fn(xyz) is true, until n_fluid are placed."""
+    sites and sites for which exclude_fn(xyz) is true, until n_fluid are placed.
+    Site index a maps to position (a + gap - 1) s (gap = 1: on the lattice of
+    the tank); returns the integer sites."""
     out = []
     need = n_fluid
     k = k_start
@@ -142,7 +186,7 @@ def fill_to_count(n_fluid, i_range, j_range, s, occupied: set, exclude_fn=None, 
             keep = np.array([tuple(t) not in occupied for t in ijk.tolist()], bool)
             ijk = ijk[keep]
         if exclude_fn is not None and ijk.shape[0]:
-            ijk = ijk[~exclude_fn(ijk.astype(np.float64) * s)]
+            ijk = ijk[~exclude_fn((ijk.astype(np.float64) + (gap - 1.0)) * s)]
         take = ijk[:need]
         out.append(take)
         need -= take.shape[0]
@@ -176,6 +220,14 @@ def soft_cube_springs(ijk: np.ndarray):
             if m is not None:
                 pairs.append((n, m))
     return np.asarray(pairs, np.int64).reshape(-1, 2)
+
+
+def viscosity_for(h: float) -> float:
+    """Kinematic viscosity proportional to the smoothing length, 1e-3 m^2/s at
+    h = 1 cm: c h / nu stays about 158 (c = sqrt(250) m/s) at every
+    resolution, i.e. the same damping per particle spacing (an artificial
+    viscosity alpha = 8 nu / (c h) of about 0.05)."""
+    return 1e-3 * h / 0.01
 
 
 def _params(h, dt, lo, hi, precision, k_pressure=250.0, nu=1e-3, rho0=1000.0,
@@ -218,19 +270,24 @@ def _assemble(name, precision, params, s, parts, kin, poses, springs=None, info=
 
 def dam_break(seed: int = 1, precision: str = "f64") -> Scene:
     """Dam break, 8,000 fluid particles (20^3 lattice, spacing 0.02 m, h = 2
-    spacing), an open tank and a fixed 0.1 m cube, 5,960 boundary particles,
-    dt = 1e-3 s, +-1e-4 m seeded jitter."""
+    spacing, +-1e-4 m seeded jitter) in the corner of an open 1.0 m long
+    tank as wide as the column, a fixed 0.1 m cube (single-layer surface)
+    1.7 spacings beyond the column, dt = 1e-3 s."""
     s, h, dt = 0.02, 0.04, 1e-3
-    fl = _grid(1, 20, 1, 20, 1, 20).astype(np.float64) * s
+    g = WALL_GAP
+    fl = (_grid(1, 20, 1, 20, 1, 20).astype(np.float64) + (g - 1.0)) * s
     rng = SplitMix64(seed, P_JITTER)
     fl = fl + (2.0 * rng.uniform(fl.size).reshape(fl.shape) - 1.0) * 1e-4
-    tank = tank_sites(50, 21, 33).astype(np.float64) * s
-    cube = block_surface_sites(22, 27, 8, 13, 1, 6).astype(np.float64) * s
-    c_cube = np.array([24.5, 10.5, 3.5]) * s
+    Wx, Wy = 50 * s, tank_width(20, s)
+    tank = open_tank(Wx, Wy, 33, s)
+    x0 = (g + 19 + g) * s
+    y0 = 0.5 * (Wy - 5 * s)
+    cube = block_surface_sites(0, 5, 0, 5, 1, 6).astype(np.float64) * s + np.array([x0, y0, 0.0])
+    c_cube = np.array([x0 + 2.5 * s, y0 + 2.5 * s, 3.5 * s])
     m = 1000.0 * s ** 3
     lo = (-0.5 * s, -0.5 * s, -0.5 * s)
-    hi = (50.5 * s, 21.5 * s, 40.5 * s)
-    params = _params(h, dt, lo, hi, precision)
+    hi = (Wx + 0.5 * s, Wy + 0.5 * s, 40.5 * s)
+    params = _params(h, dt, lo, hi, precision, nu=viscosity_for(h), flags=1)
     poses = [[0, 0, 0, 1, 0, 0, 0], list(c_cube) + [1, 0, 0, 0]]
     return _assemble("dam_break_8k", precision, params, s,
                      [(fl, FLUID, -1, m), (tank, BOUNDARY, 0, 0.0), (cube, BOUNDARY, 1, 0.0)],
@@ -238,21 +295,23 @@ def dam_break(seed: int = 1, precision: str = "f64") -> Scene:
 
 
 def stirring_tank(seed: int = 2, n_fluid: int = 250_000, precision: str = "f32") -> Scene:
-    """Stirring tank: tank of about 1.01 x 0.51 x 0.6 m, a 4 x 25 x 40 paddle
-    (4,000 kinematic boundary particles) on a seeded 1 Hz, 0.1 m sinusoid,
-    n_fluid fluid particles filled layer by layer, dt = 5e-4 s."""
+    """Stirring tank: 100 x 50 fluid columns at spacing 0.01 m in an open tank
+    of about 1.02 x 0.52 x 0.6 m, a solid 4 x 25 x 40 lattice paddle (4,000
+    kinematic boundary particles) on a seeded 1 Hz, 0.1 m sinusoid, n_fluid
+    fluid particles filled layer by layer, dt = 5e-4 s."""
     s, h, dt = 0.01, 0.02, 5e-4
-    tank = tank_sites(101, 51, 60).astype(np.float64) * s
-    pad_ijk = _grid(49, 52, 13, 37, 6, 45)
-    occ = set(map(tuple, pad_ijk.tolist()))
-    fl = fill_to_count(n_fluid, (1, 100), (1, 50), s, occ).astype(np.float64) * s
-    pad = pad_ijk.astype(np.float64) * s
+    g = WALL_GAP
+    Wx, Wy = tank_width(100, s), tank_width(50, s)
+    tank = open_tank(Wx, Wy, 60, s)
+    pad = (_grid(49, 52, 13, 37, 6, 45).astype(np.float64) + (g - 1.0)) * s
+    fl = (fill_to_count(n_fluid, (1, 100), (1, 50), s, set(), clearance(pad, OBSTACLE_CLEARANCE * s), gap=g)
+          .astype(np.float64) + (g - 1.0)) * s
     c0 = pad.mean(0)
     m = 1000.0 * s ** 3
     phase = 2.0 * math.pi * float(SplitMix64(seed, P_PHASE).uniform(1)[0])
     lo = (-0.5 * s, -0.5 * s, -0.5 * s)
-    hi = (101.5 * s, 51.5 * s, 70.5 * s)
-    params = _params(h, dt, lo, hi, precision)
+    hi = (Wx + 1.5 * s, Wy + 1.5 * s, 70.5 * s)
+    params = _params(h, dt, lo, hi, precision, nu=viscosity_for(h), flags=1)
     poses = [[0, 0, 0, 1, 0, 0, 0], list(c0) + [1, 0, 0, 0]]
     return _assemble(f"stirring_tank_{n_fluid}", precision, params, s,
                      [(fl, FLUID, -1, m), (tank, BOUNDARY, 0, 0.0), (pad, BOUNDARY, 1, 0.0)],
@@ -261,12 +320,15 @@ def stirring_tank(seed: int = 2, n_fluid: int = 250_000, precision: str = "f32")
 
 
 def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") -> Scene:
-    """Coupled fluid + soft + rigid: tank 0.505 x 0.505 x 0.6 m, a 20^3 soft
-    cube (66,120 springs, k_s = 100 N/m), a grabbed sphere of radius 0.05 m as
-    three Fibonacci shells (3,079 particles), n_fluid fluid particles,
-    spacing 5 mm, h = 1 cm, dt = 2.5e-4 s."""
+    """Coupled fluid + soft + rigid: 100 x 100 fluid columns at spacing 5 mm in
+    an open tank of about 0.51 x 0.51 x 0.6 m, a 20^3 soft cube on the fluid
+    lattice (66,120 springs, k_s = 100 N/m), a grabbed sphere of radius
+    0.05 m as three Fibonacci shells (3,079 particles), n_fluid fluid
+    particles, h = 1 cm, dt = 2.5e-4 s."""
     s, h, dt = 0.005, 0.01, 2.5e-4
-    tank = tank_sites(101, 101, 120).astype(np.float64) * s
+    g = WALL_GAP
+    W = tank_width(100, s)
+    tank = open_tank(W, W, 120, s)
     soft_ijk = _grid(11, 30, 41, 60, 1, 20)
     occ = set(map(tuple, soft_ijk.tolist()))
     c0 = np.array([0.30, 0.25, 0.25])
@@ -274,12 +336,9 @@ def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") 
     shells = [fibonacci_sphere(int(round(4 * math.pi * r * r / (s * s))), r, c0)
               for r in (R, R - s, R - 2 * s)]
     sph = np.concatenate(shells, 0)
-
-    def excl(xyz):
-        return np.linalg.norm(xyz - c0, axis=1) < R + 0.5 * s
-
-    fl = fill_to_count(n_fluid, (1, 100), (1, 100), s, occ, excl).astype(np.float64) * s
-    soft = soft_ijk.astype(np.float64) * s
+    fl = (fill_to_count(n_fluid, (1, 100), (1, 100), s, occ, clearance(sph, OBSTACLE_CLEARANCE * s), gap=g)
+          .astype(np.float64) + (g - 1.0)) * s
+    soft = (soft_ijk.astype(np.float64) + (g - 1.0)) * s
     m = 1000.0 * s ** 3
     ij = soft_cube_springs(soft_ijk)
     L0 = np.linalg.norm(soft[ij[:, 0]] - soft[ij[:, 1]], axis=1)
@@ -288,8 +347,8 @@ def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") 
     nf = fl.shape[0]
     ij_glob = ij + nf                       # soft particles follow the fluid
     lo = (-0.5 * s, -0.5 * s, -0.5 * s)
-    hi = (101.5 * s, 101.5 * s, 125.0 * s)          # 32 cells of 2h (1 + 2^-10) per axis
-    params = _params(h, dt, lo, hi, precision)
+    hi = (W + 1.5 * s, W + 1.5 * s, 125.0 * s)          # at most 32 cells of 2h (1 + 2^-10) per axis
+    params = _params(h, dt, lo, hi, precision, nu=viscosity_for(h), flags=1)
     poses = [[0, 0, 0, 1, 0, 0, 0], list(c0) + [1, 0, 0, 0]]
     return _assemble(f"coupled_{n_fluid}", precision, params, s,
                      [(fl, FLUID, -1, m), (soft, SOFT, -1, m), (tank, BOUNDARY, 0, 0.0),
@@ -297,6 +356,42 @@ def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") 
                      kin=[0, 1], poses=poses,
                      springs=(ij_glob, L0, np.full(len(L0), ks), np.full(len(L0), cs)),
                      info={"body": 1, "radius": R, "c0": c0})
+
+
+def haptic_scene(seed: int = 5, n_fluid: int = 100_000, precision: str = "f32") -> Scene:
+    """The coupled scene's resolution and grabbed sphere (spacing 5 mm,
+    h = 1 cm, dt = 2.5e-4 s, radius 0.05 m as three Fibonacci shells) in a
+    tank whose square footprint holds n_fluid particles about 0.3 m deep,
+    for the haptic-rate surrogate's training and validation runs.  The
+    sphere starts submerged at the footprint centre; walk box and probe
+    radius in info."""
+    s, h, dt = 0.005, 0.01, 2.5e-4
+    g = WALL_GAP
+    nin = max(8, int(round(math.sqrt(n_fluid / 60.0))))       # fluid columns per side
+    depth = n_fluid / (nin * nin) * s
+    nz = int(math.ceil(depth / s * 1.35)) + 2
+    W = tank_width(nin, s)
+    tank = open_tank(W, W, nz, s)
+    R = 0.05
+    c0 = np.array([0.5 * W, 0.5 * W, min(0.17, 0.55 * depth)])
+    shells = [fibonacci_sphere(int(round(4 * math.pi * r * r / (s * s))), r, c0)
+              for r in (R, R - s, R - 2 * s)]
+    sph = np.concatenate(shells, 0)
+    fl = (fill_to_count(n_fluid, (1, nin), (1, nin), s, set(), clearance(sph, OBSTACLE_CLEARANCE * s), gap=g)
+          .astype(np.float64) + (g - 1.0)) * s
+    m = 1000.0 * s ** 3
+    lo = (-0.5 * s, -0.5 * s, -0.5 * s)
+    hi = (W + 1.5 * s, W + 1.5 * s, (nz + 3) * s)
+    # haptic output: rolling mean over 160 steps = 40 ticks of 1 ms
+    params = _params(h, dt, lo, hi, precision, nu=viscosity_for(h), flags=1, smoothing_window=160)
+    poses = [[0, 0, 0, 1, 0, 0, 0], list(c0) + [1, 0, 0, 0]]
+    margin = R + 5 * s
+    info = {"body": 1, "radius": R, "c0": c0, "fluid_depth": depth,
+            "walk_lo": (margin, margin, R + 6 * s), "walk_hi": (W - margin, W - margin, depth),
+            "probe_radius": R + s}
+    return _assemble(f"haptic_{n_fluid}", precision, params, s,
+                     [(fl, FLUID, -1, m), (tank, BOUNDARY, 0, 0.0), (sph, BOUNDARY, 1, 0.0)],
+                     kin=[0, 1], poses=poses, info=info)
 
 
 def small_scene(seed: int = 11, nf=(14, 9, 8), precision: str = "f32", with_soft=True,
@@ -410,6 +505,51 @@ def random_walk(seed: int, n_ticks: int, c0, tick=1e-3, box_lo=(0.12, 0.12, 0.12
             elif c[a] > hi[a]:
                 c[a] = 2 * hi[a] - c[a]
                 v[a] = -v[a]
+        q = quat_normalize(q + 0.5 * tick * quat_mul(np.array([0.0, *w]), q))
+    return C, Q, V, W
+
+
+def smooth_walk(seed: int, n_ticks: int, c0, box_lo, box_hi, tick=1e-3, tau_a=0.08, tau_v=0.1,
+                rms_a=0.5, f_spring=1.5, tau_target=1.0, tau_alpha=0.08, tau_w=0.3, rms_alpha=6.0):
+    """Hand-like pose stream at 1 kHz.  A target point wanders over the box
+    (Ornstein-Uhlenbeck, correlation time tau_target, spread 0.18 of the box
+    per axis); the centre follows it through a spring of frequency f_spring
+    with velocity relaxation tau_v, plus an Ornstein-Uhlenbeck
+    acceleration (tau_a, RMS rms_a m/s^2); the angular velocity relaxes with
+    tau_w under an Ornstein-Uhlenbeck angular acceleration (tau_alpha,
+    rms_alpha rad/s^2).  The box reflects the centre (rarely reached).
+    Returns c, q, v, w arrays (n_ticks, .)."""
+    rng = SplitMix64(seed, P_WALK + 10)
+    ra, rv = math.exp(-tick / tau_a), math.exp(-tick / tau_v)
+    rb, rw = math.exp(-tick / tau_alpha), math.exp(-tick / tau_w)
+    rt = math.exp(-tick / tau_target)
+    sa, sb, st = (rms_a * math.sqrt(1 - ra * ra), rms_alpha * math.sqrt(1 - rb * rb), math.sqrt(1 - rt * rt))
+    kap = (2.0 * math.pi * f_spring) ** 2
+    c = np.asarray(c0, np.float64).copy()
+    q = np.array([1.0, 0, 0, 0])
+    v, w, a, al = np.zeros(3), np.zeros(3), np.zeros(3), np.zeros(3)
+    lo, hi = np.asarray(box_lo, np.float64), np.asarray(box_hi, np.float64)
+    mid, spread = 0.5 * (lo + hi), 0.18 * (hi - lo)
+    u = (c - mid) / spread                      # target in units of the spread
+    C, Q, V, W = (np.zeros((n_ticks, 3)), np.zeros((n_ticks, 4)),
+                  np.zeros((n_ticks, 3)), np.zeros((n_ticks, 3)))
+    for t in range(n_ticks):
+        C[t], Q[t], V[t], W[t] = c, q, v, w
+        nz = rng.normal(9)
+        a = ra * a + sa * nz[:3]
+        al = rb * al + sb * nz[3:6]
+        u = rt * u + st * nz[6:]
+        target = np.clip(mid + spread * u, lo, hi)
+        v = rv * v + tick * (a - kap * (c - target))
+        w = rw * w + tick * al
+        c = c + tick * v
+        for k in range(3):
+            if c[k] < lo[k]:
+                c[k] = 2 * lo[k] - c[k]
+                v[k] = -v[k]
+            elif c[k] > hi[k]:
+                c[k] = 2 * hi[k] - c[k]
+                v[k] = -v[k]
         q = quat_normalize(q + 0.5 * tick * quat_mul(np.array([0.0, *w]), q))
     return C, Q, V, W
 

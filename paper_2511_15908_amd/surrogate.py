@@ -29,3 +29,252 @@ def init_params(seed, hidden, layers, n_in, n_out):
             W[n_out:] = 0.0
         parts += [W.ravel(), np.zeros(n)]
     return np.concatenate(parts).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# haptic loop bookkeeping
+# --------------------------------------------------------------------------
+# Per 1 kHz tick t the haptic loop knows: the device pose and velocities at t
+# (13 inputs), the last N_HIST wrenches that SPH delivered at its slower rate,
+# every SPH_EVERY ticks (the newest, W(t0), as is; the older ones as
+# differences from it: 48), the probe densities of the SPH state at t0 (64
+# body-frame points at probe_radius), and t - t0 in units of SPH_EVERY (1):
+# 126 inputs.  The network predicts the change W(t) - W(t0) (residual output
+# over input columns RES_COL..RES_COL+5).
+
+N_HIST = 8
+SPH_EVERY = 10
+N_PROBES = 64
+N_FEATURES = 13 + 6 * N_HIST + N_PROBES + 1
+RES_COL = 13
+
+
+def probe_points(scene):
+    """Body-frame probe points: a Fibonacci sphere of N_PROBES points one
+    lattice spacing outside the grabbed sphere."""
+    return scenes.fibonacci_sphere(N_PROBES, scene.info["probe_radius"], (0.0, 0.0, 0.0))
+
+
+def make_sim(scene, device="cuda"):
+    from ._binding import Sim
+    sim = Sim(scene, device=device, max_probes=N_PROBES)
+    sim.set_probes(probe_points(scene), np.full(N_PROBES, scene.info["body"], np.int32))
+    return sim
+
+
+def make_net(max_batch=4096, device="cuda", seed=1, hidden=256, layers=3):
+    from .mlp import Mlp
+    net = Mlp(N_FEATURES, 6, hidden=hidden, layers=layers, max_batch=max_batch, device=device, residual_col=RES_COL)
+    net.set_params(init_params(seed, hidden, layers, N_FEATURES, 6))
+    return net
+
+
+def collect(sim, scene, walk, per_tick=4):
+    """Drive the grabbed body with `walk` (c, q, v, w per tick), `per_tick`
+    SPH steps per tick; log per tick the pose, the haptic wrench (the rolling
+    mean of the per-step wrenches over the scene's smoothing window) and the
+    probe densities."""
+    C, Q, V, W = walk
+    n = C.shape[0]
+    body = scene.info["body"]
+    wr = np.zeros((n, 6))
+    pr = np.zeros((n, N_PROBES))
+    for t in range(n):
+        sim.set_body_pose(body, C[t], Q[t], V[t], W[t])
+        sim.step(per_tick)
+        F, T = sim.wrench(body, smoothed=True)
+        wr[t, :3], wr[t, 3:] = F, T
+        pr[t] = sim.read_probes()
+    q = np.where(Q[:, :1] < 0, -Q, Q)
+    return {"c": C.copy(), "q": q, "v": V.copy(), "w": W.copy(), "wrench": wr, "probes": pr}
+
+
+def feature_rows(log, ticks, lags):
+    """Input rows and targets W(t) for ticks t whose last SPH update came
+    d = lags ticks earlier."""
+    t = np.asarray(ticks, np.int64)
+    d = np.asarray(lags, np.int64)
+    t0 = t - d
+    W = log["wrench"]
+    w0 = W[t0]
+    hist = [w0] + [W[t0 - SPH_EVERY * k] - w0 for k in range(1, N_HIST)]
+    X = np.concatenate([log["c"][t], log["q"][t], log["v"][t], log["w"][t]] + hist +
+                       [log["probes"][t0], (d / SPH_EVERY)[:, None]], 1)
+    return X.astype(np.float32), W[t].astype(np.float32)
+
+
+def first_tick():
+    return SPH_EVERY * (N_HIST - 1) + SPH_EVERY - 1
+
+
+def training_rows(log):
+    """Every tick with every phase of the SPH update grid."""
+    n = log["c"].shape[0]
+    t = np.arange(first_tick(), n)
+    tt = np.repeat(t, SPH_EVERY)
+    dd = np.tile(np.arange(SPH_EVERY), t.size)
+    return feature_rows(log, tt, dd)
+
+
+def eval_rows(log, phase=0):
+    """Ticks t >= first_tick() with SPH updates at ticks = phase mod SPH_EVERY."""
+    n = log["c"].shape[0]
+    t = np.arange(first_tick(), n)
+    d = (t - phase) % SPH_EVERY
+    return t, d, feature_rows(log, t, d)
+
+
+def baselines(log, t, d, k_avg=SPH_EVERY):
+    """The haptic loop without the network: zero-order hold of the last SPH
+    wrench, and the hold followed by a rolling mean over the last k_avg ticks
+    (Sec. 3.3)."""
+    W = log["wrench"]
+    zoh = W[t - d]
+    acc = np.zeros_like(zoh)
+    for j in range(k_avg):
+        tj = t - j
+        dj = (d - j) % SPH_EVERY
+        acc += W[tj - dj]
+    return zoh, acc / k_avg
+
+
+def predict(net, X, chunk=None):
+    """Batched network outputs for the rows X (numpy), through mlp_forward."""
+    import torch
+    chunk = chunk or net.cfg.max_batch
+    out = []
+    for s in range(0, X.shape[0], chunk):
+        xt = torch.from_numpy(np.ascontiguousarray(X[s:s + chunk])).to(net.device)
+        out.append(net.forward(xt).cpu().numpy())
+    return np.concatenate(out, 0).astype(np.float64)
+
+
+def wrench_errors(pred, truth, scene):
+    """Relative wrench error per tick with the floors of the parity norms:
+    |dF| / max(|F|, rho0 g V), |dT| / max(|T|, rho0 g V L) (V the body volume,
+    L its diameter); returns the larger of the two per tick."""
+    R = scene.info["radius"]
+    V = 4.0 / 3.0 * math.pi * R ** 3
+    fF = scene.params["rho0"] * 9.81 * V
+    fT = fF * 2 * R
+    eF = np.linalg.norm(pred[:, :3] - truth[:, :3], axis=1) / np.maximum(np.linalg.norm(truth[:, :3], axis=1), fF)
+    eT = np.linalg.norm(pred[:, 3:] - truth[:, 3:], axis=1) / np.maximum(np.linalg.norm(truth[:, 3:], axis=1), fT)
+    return np.maximum(eF, eT)
+
+
+def train(net, X, Y, steps, batch=4096, lr0=1e-3, lr1=1e-5, seed=1, holdout=None, every=250):
+    """Adam on random minibatches (the library's kernels) with a cosine
+    learning-rate decay; X, Y float32 device tensors.  With holdout =
+    (log, scene) the parameters with the smallest held-out wrench error
+    (checked every `every` steps) are kept.  Returns [(step, loss,
+    held-out error)]."""
+    import torch
+    rng = scenes.SplitMix64(seed, P_BATCH)
+    n = X.shape[0]
+    net.fit_normalizer(X, Y)
+    if holdout is not None:
+        hlog, hscene = holdout
+        th, dh, (Xh, Yh) = eval_rows(hlog)
+    hist, best = [], (float("inf"), None)
+    for it in range(steps):
+        idx = torch.from_numpy((rng.uniform(batch) * n).astype(np.int64)).to(X.device)
+        lr = lr1 + 0.5 * (lr0 - lr1) * (1.0 + math.cos(math.pi * it / max(steps - 1, 1)))
+        net.train_step(X.index_select(0, idx), Y.index_select(0, idx), lr)
+        if (it + 1) % every == 0 or it == steps - 1:
+            e = float("nan")
+            if holdout is not None:
+                e = float(wrench_errors(predict(net, Xh), Yh.astype(np.float64), hscene)[dh > 0].mean())
+                if e < best[0]:
+                    best = (e, net.get_params())
+            hist.append((it + 1, net.last_loss(), e))
+    if best[1] is not None:
+        net.set_params(best[1])
+    return hist
+
+
+def evaluate(net, log, scene):
+    """Errors of the surrogate and of the two baselines on the ticks between
+    SPH updates (d > 0), against the plain-SPH haptic wrench at every tick."""
+    t, d, (X, Y) = eval_rows(log)
+    truth = Y.astype(np.float64)
+    zoh, avg = baselines(log, t, d)
+    out = {}
+    for name, p in (("surrogate", predict(net, X)), ("zero_order_hold", zoh), ("hold_rolling_mean", avg)):
+        e = wrench_errors(p, truth, scene)[d > 0]
+        out[name] = {"mean": float(e.mean()), "p50": float(np.median(e)), "p95": float(np.percentile(e, 95)),
+                     "max": float(e.max())}
+    return out
+
+
+def haptic_rate(net, X, n=500):
+    """Haptic ticks per second of the one-workgroup chain: host round trip
+    (features in, wrench out, synchronised) and device-only back to back."""
+    import time
+    import torch
+    for k in range(10):
+        net.predict_one(X[k % X.shape[0]])
+    t0 = time.perf_counter()
+    for k in range(n):
+        net.predict_one(X[k % X.shape[0]])
+    host = n / (time.perf_counter() - t0)
+    xd = torch.from_numpy(np.ascontiguousarray(X[:n])).to(net.device)
+    yd = torch.zeros((xd.shape[0], 6), device=net.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(xd.shape[0]):
+        net.predict_one_device(xd[k], yd[k])
+    e1.record()
+    torch.cuda.synchronize()
+    dev = xd.shape[0] / (e0.elapsed_time(e1) * 1e-3)
+    return {"host_round_trip_hz": host, "device_chain_hz": dev}
+
+
+def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=1500, steps=1500, seed=1,
+                   warmup_ticks=300, log=print):
+    """Collect plain-SPH haptic logs (a 1 kHz smooth walk per segment, 4 SPH
+    steps per tick), train on the first segments with early stopping on a
+    held-out segment, evaluate on a last one.  Returns a summary dict."""
+    import time
+    import torch
+    sc = scenes.haptic_scene(n_fluid=n_fluid)
+    sim = make_sim(sc)
+    lo, hi = sc.info["walk_lo"], sc.info["walk_hi"]
+    c = sc.info["c0"]
+    logs = []
+    segs = [(warmup_ticks, 11)] + [(ticks, 101 + i) for i in range(train_segments)] + \
+        [(eval_ticks, 901), (eval_ticks, 902)]
+    t0 = time.perf_counter()
+    for n, sd in segs:
+        walk = scenes.smooth_walk(sd, n, c, lo, hi)
+        logs.append(collect(sim, sc, walk))
+        c = walk[0][-1] + 1e-3 * walk[2][-1]
+        log(f"  collected {n} ticks (walk seed {sd})")
+    t_collect = time.perf_counter() - t0
+    rows = [training_rows(lg) for lg in logs[1:1 + train_segments]]
+    X = torch.from_numpy(np.concatenate([r[0] for r in rows])).to("cuda")
+    Y = torch.from_numpy(np.concatenate([r[1] for r in rows])).to("cuda")
+    net = make_net(seed=seed)
+    t0 = time.perf_counter()
+    hist = train(net, X, Y, steps, seed=seed, holdout=(logs[-2], sc))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    errs = evaluate(net, logs[-1], sc)
+    rate = haptic_rate(net, eval_rows(logs[-1])[2][0])
+    return {"scene": sc.name, "n_particles": int(sc.n), "training_rows": int(X.shape[0]),
+            "ticks_collected": int(sum(n for n, _ in segs)), "collect_s": t_collect, "train_s": t_train,
+            "train_steps": steps, "best_holdout_error": min(h[2] for h in hist), "errors": errs, **rate}
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="plain-SPH haptic logs -> surrogate training -> evaluation")
+    ap.add_argument("--n-fluid", type=int, default=100_000)
+    ap.add_argument("--segments", type=int, default=4)
+    ap.add_argument("--ticks", type=int, default=3000)
+    ap.add_argument("--eval-ticks", type=int, default=1500)
+    ap.add_argument("--steps", type=int, default=1500)
+    a = ap.parse_args()
+    r = run_experiment(a.n_fluid, a.segments, a.ticks, a.eval_ticks, a.steps,
+                       log=lambda m: print(m, flush=True))
+    print(json.dumps(r), flush=True)

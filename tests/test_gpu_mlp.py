@@ -171,3 +171,31 @@ def test_training_reduces_loss(torch):
     _, l1 = net.gradients(dX[:4096], dY[:4096])
     print(f"loss {l0:.4f} -> {l1:.4f}")
     assert l1 < 0.1 * l0
+
+
+def test_residual_output_matches_oracle(torch):
+    """Residual mode (the outputs add raw input columns 13..18): normaliser,
+    forward (batched and one-sample) and gradient against the oracle."""
+    from paper_2511_15908_amd import mlp, surrogate
+    rc = 13
+    X, Y = _data(5, 500)
+    Y = (Y + X[:, rc:rc + N_OUT]).astype(np.float32)
+    net = mlp.Mlp(N_IN, N_OUT, hidden=H, layers=LAYERS, max_batch=1024, residual_col=rc)
+    p = surrogate.init_params(16, H, LAYERS, N_IN, N_OUT)
+    net.set_params(p)
+    dX, dY = torch.tensor(X, device="cuda"), torch.tensor(Y, device="cuda")
+    net.fit_normalizer(dX, dY)
+    norm_g = [np.asarray(v, np.float64) for v in net.get_normalizer()]
+    for a, b in zip(norm_g, M.fit_normalizer(X, Y, res_col=rc)):
+        assert np.allclose(a, b, rtol=2e-6, atol=1e-6)
+    out_g = net.forward(dX).cpu().numpy().astype(np.float64)
+    out_o, _ = M.forward(p.astype(np.float64), X, norm_g, H, LAYERS, N_OUT, quant=True, res_col=rc)
+    scale = np.abs(out_o).max()
+    assert np.abs(out_g - out_o).max() / scale < 5e-3
+    y1 = net.predict_one(X[7]).astype(np.float64)
+    assert np.abs(y1 - out_o[7]).max() / scale < 5e-3
+    g_gpu, loss_gpu = net.gradients(dX, dY)
+    loss_o, g_o = M.loss_and_grad(p.astype(np.float64), X, Y, norm_g, H, LAYERS, N_OUT, quant=True, res_col=rc)
+    assert loss_gpu == pytest.approx(loss_o, rel=2e-3)
+    rel = np.linalg.norm(g_gpu - g_o) / np.linalg.norm(g_o)
+    assert rel < 2e-3

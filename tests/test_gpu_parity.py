@@ -133,7 +133,7 @@ def test_small_scene_three_steps_fp64(gpu, orc):
 
 
 def test_dam_break_fp64_trajectory(gpu, orc):
-    """Dam break (8,000 fluid, 5,960 boundary, FP64): 100 steps of GPU and
+    """Dam break (8,000 fluid, 6,077 boundary, FP64): 100 steps of GPU and
     oracle from the same seeded state.  Step 1 matches to 1e-12 (density) and
     1e-10 (forces); afterwards the two FP64 trajectories separate only through
     rounding-order differences amplified by the flow: positions stay within

@@ -94,6 +94,29 @@ def test_zero_hidden_weights_closed_form():
     assert np.allclose(out, b * norm[3] + norm[2], rtol=1e-14)
 
 
+def test_residual_output_closed_form():
+    """With every weight zero and a residual block of inputs, the output is
+    those inputs plus the de-standardised output bias; the target statistics
+    are those of y minus the residual inputs, and a target equal to the
+    residual inputs plus mu_y costs b^2."""
+    hidden, layers, n_out, rc = 64, 2, 6, 4
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((13, 20))
+    Y = X[:, rc:rc + n_out] + rng.standard_normal((13, n_out)) * 0.5
+    norm = M.fit_normalizer(X, Y, res_col=rc)
+    d = Y - X[:, rc:rc + n_out]
+    assert np.allclose(norm[2], d.mean(0), rtol=1e-14) and np.allclose(norm[3], d.std(0), rtol=1e-14)
+    p = np.zeros(M.param_count(hidden, layers))
+    b = rng.standard_normal(n_out)
+    p[-16:-16 + n_out] = b
+    out, _ = M.forward(p, X, norm, hidden, layers, n_out, quant=False, res_col=rc)
+    assert np.allclose(out, X[:, rc:rc + n_out] + b * norm[3] + norm[2], rtol=1e-14)
+    Yc = X[:, rc:rc + n_out] + norm[2]
+    L, g = M.loss_and_grad(p, X, Yc, norm, hidden, layers, n_out, quant=False, res_col=rc)
+    assert L == pytest.approx(np.mean(b ** 2), rel=1e-13)
+    assert np.allclose(g[-16:-16 + n_out], 2 * b / n_out, rtol=1e-13)
+
+
 def test_adam_closed_forms():
     """Step 1 from zero moments moves every weight by lr g/(|g| + eps); a
     constant gradient keeps the bias-corrected moments at g and g^2 exactly,
