@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--workload", default="coupled_1m")
     ap.add_argument("--n-fluid", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the haptic-rate surrogate leg (100k haptic scene: logs, training, evaluation)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
@@ -203,6 +205,20 @@ def main():
     out["cells"] = {"occupied": int(cnt.size), "mean": float(cnt.mean()), "max": int(cnt.max()),
                     "over64": int((cnt > 64).sum()),
                     "passes_per_target": float(np.ceil(cnt / 64).sum() * 64 / cnt.sum())}
+    del sim
+    if not a.no_surrogate:
+        from paper_2511_15908_amd import surrogate as S
+        log("surrogate leg: plain-SPH haptic logs of the 100k haptic scene, training, evaluation ...", a.quiet)
+        r = S.run_experiment(log=lambda m: log(m, a.quiet))
+        e = r["errors"]
+        out["surrogate"] = {
+            "scene": r["scene"], "n_particles": r["n_particles"], "sph_update_hz": 100, "haptic_hz": 1000,
+            "error_vs_plain_sph": {k: round(v["mean"], 4) for k, v in e.items()},
+            "error_p95": {k: round(v["p95"], 4) for k, v in e.items()},
+            "tick_rate_hz": {"host_round_trip": round(r["host_round_trip_hz"], 1),
+                             "device_chain": round(r["device_chain_hz"], 1)},
+            "training": {"rows": r["training_rows"], "steps": r["train_steps"], "seconds": round(r["train_s"], 2),
+                         "ticks_simulated": r["ticks_collected"], "collect_seconds": round(r["collect_s"], 1)}}
     log(json.dumps(out, indent=1), a.quiet)
     if not a.no_cpu_baseline:
         log("timing the CPU oracle on one step of the same scene ...", a.quiet)
