@@ -81,6 +81,8 @@ def lib():
         L.orc_body_frame.argtypes = [C.c_int64, d, i32, C.c_int32, d, d]
         L.orc_body_place.argtypes = [C.c_int64, i32, C.c_int32, d, d, d, d, d, d, d]
         L.orc_pose_advance.argtypes = [d, d, d, d, C.c_double]
+        L.orc_body_mass_props.argtypes = [C.c_int64, d, d, i32, C.c_int32, d, d, d, d]
+        L.orc_body_velocity_step.argtypes = [d, d, C.c_double, d, d, d, C.c_double, d, d]
         L.orc_density.argtypes = [P, C.c_int64, d, d, u8, d, C.c_int64, i64, i64, i64, i64, d, d]
         L.orc_probe_density.argtypes = [P, C.c_int64, d, d, u8, C.c_int64, d, d]
         L.orc_springs.argtypes = [C.c_int64, d, d, C.c_int64, u32, d, d, d, d]
@@ -185,6 +187,25 @@ def quat_to_R(q):
     R = np.zeros(9)
     lib().orc_quat_to_R(_p(q, C.c_double), _p(R, C.c_double))
     return R.reshape(3, 3)
+
+
+def body_mass_props(x, mass, obj, o, q0):
+    """Mass, centre of mass and body-frame inertia of object o's particles."""
+    x, mass = _f64(x), _f64(mass)
+    obj = np.ascontiguousarray(obj, np.int32)
+    com, m, I = np.zeros(3), np.zeros(1), np.zeros(9)
+    lib().orc_body_mass_props(x.shape[0], _p(x, C.c_double), _p(mass, C.c_double), _p(obj, C.c_int32), int(o),
+                              _p(_f64(q0), C.c_double), _p(com, C.c_double), _p(m, C.c_double), _p(I, C.c_double))
+    return float(m[0]), com, I.reshape(3, 3)
+
+
+def body_velocity_step(F, T, m, I_body, q, g, dt, v, w):
+    """Semi-implicit Euler velocity step of a free body; returns new (v, w)."""
+    v, w = _f64(v).copy(), _f64(w).copy()
+    lib().orc_body_velocity_step(_p(_f64(F), C.c_double), _p(_f64(T), C.c_double), float(m),
+                                 _p(_f64(np.asarray(I_body).ravel()), C.c_double), _p(_f64(q), C.c_double),
+                                 _p(_f64(g), C.c_double), float(dt), _p(v, C.c_double), _p(w, C.c_double))
+    return v, w
 
 
 def pose_advance(c, q, v, w, dt):
@@ -298,7 +319,10 @@ class Oracle:
     The state starts from the scene rounded to the run's precision (the same
     rounding the GPU library applies at initialisation).  Kinematic objects
     carry a pose (c, q, v, w); between pose updates the pose is advanced by
-    c += v dt, q <- normalise(q + dt/2 (0,w) q) after every step.
+    c += v dt, q <- normalise(q + dt/2 (0,w) q) after every step.  Dynamic
+    objects (object_kinematic 2) carry the pose of their centre of mass and,
+    while not grabbed, first update v and w from the step's wrench, gravity
+    and their inertia (body_velocity_step).
     """
 
     def __init__(self, scene, precision=None):
@@ -314,9 +338,16 @@ class Oracle:
         self.obj = np.ascontiguousarray(scene.object, np.int32)
         self.kin = [o for o in range(len(scene.object_kinematic)) if scene.object_kinematic[o]]
         self.pose = {}
+        self.free = {}          # dynamic objects: True while integrated, False while grabbed
+        self.body = {}          # dynamic objects: (mass, body-frame inertia)
         self.r_loc = np.zeros((self.n, 3))
         for o in self.kin:
-            p0 = _f64(scene.object_pose0[o])
+            p0 = _f64(scene.object_pose0[o]).copy()
+            if scene.object_kinematic[o] == 2:
+                m, com, I = body_mass_props(scene.x, scene.mass, self.obj, o, p0[3:])
+                p0[:3] = com
+                self.body[o] = (m, I)
+                self.free[o] = True
             lib().orc_body_frame(self.n, _p(_f64(scene.x), C.c_double), _p(self.obj, C.c_int32), o,
                                  _p(p0, C.c_double), _p(self.r_loc, C.c_double))
             q = p0[3:] / np.linalg.norm(p0[3:])
@@ -339,6 +370,16 @@ class Oracle:
                                _p(fc, C.c_int64), _p(fo, C.c_int64), _p(ids, C.c_int64),
                                _p(psi, C.c_double))
         return psi
+
+    def grab(self, o):
+        """A dynamic object follows set_pose from now on (smoothing restarts)."""
+        self.free[o] = False
+        self.samples[o] = []
+
+    def release(self, o):
+        """A grabbed dynamic object moves under its wrench again."""
+        self.free[o] = True
+        self.samples[o] = []
 
     def set_pose(self, o, c, q, v, w):
         q = _f64(q)
@@ -438,6 +479,10 @@ class Oracle:
                             _p(self.x, C.c_double), _p(self.v, C.c_double))
         for o in self.kin:
             c, q, v, w = self.pose[o]
+            if self.free.get(o, False):
+                m, I = self.body[o]
+                F, T = out["wrench"][o]
+                v, w = body_velocity_step(F, T, m, I, q, self.params["gravity"], self.params["dt"], v, w)
             c2, q2 = pose_advance(c, q, v, w, self.params["dt"])
             self.pose[o] = [c2, q2, v, w]
         self.nsteps += 1

@@ -439,6 +439,90 @@ void orc_pose_advance(double c[3], double q[4], const double v[3], const double 
 }
 
 /* ------------------------------------------------------------------ */
+/* Free rigid bodies (Sec. 3.2: a rigid body takes the summed point      */
+/* forces of its particles; Sec. 3.3: a released body moves under them). */
+/* Mass properties from the body's particles: m = sum m_i, centre of     */
+/* mass, inertia about it in the body frame I = sum m_i (|r|^2 1 - r r^T) */
+/* with r = R(q0)^T (x_i - com).  Velocity step (semi-implicit Euler, as */
+/* Eq. euler for particles): v += dt (F/m + g); with the world inertia   */
+/* I_w = R I R^T, w += dt I_w^{-1} (T - w x (I_w w)) (Euler's equations). */
+/* ------------------------------------------------------------------ */
+
+void orc_body_mass_props(int64_t n, const double *x, const double *mass, const int32_t *object, int32_t o,
+                         const double q0[4], double com[3], double *m_out, double I_body[9])
+{
+    double m = 0.0, s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        if (object[i] != o) continue;
+        m += mass[i];
+        for (int a = 0; a < 3; ++a) s[a] += mass[i] * x[3 * i + a];
+    }
+    for (int a = 0; a < 3; ++a) com[a] = s[a] / m;
+    *m_out = m;
+    double q[4], R[9];
+    quat_unit(q0, q);
+    orc_quat_to_R(q, R);
+    for (int k = 0; k < 9; ++k) I_body[k] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (object[i] != o) continue;
+        double d[3] = {x[3 * i] - com[0], x[3 * i + 1] - com[1], x[3 * i + 2] - com[2]};
+        double r[3];
+        for (int a = 0; a < 3; ++a) r[a] = R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2];
+        double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) I_body[3 * a + b] += mass[i] * ((a == b ? rr : 0.0) - r[a] * r[b]);
+    }
+}
+
+/* inverse of a 3x3 matrix by cofactors */
+static void inv3(const double A[9], double B[9])
+{
+    double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+    double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    B[0] = c00 / det;
+    B[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+    B[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+    B[3] = c01 / det;
+    B[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+    B[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    B[6] = c02 / det;
+    B[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+    B[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+}
+
+void orc_body_velocity_step(const double F[3], const double T[3], double m, const double I_body[9],
+                            const double q_in[4], const double g[3], double dt, double v[3], double w[3])
+{
+    double q[4], R[9], Iw[9], Iwi[9], tmp[9];
+    quat_unit(q_in, q);
+    orc_quat_to_R(q, R);
+    /* I_w = R I R^T */
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double t = 0.0;
+            for (int k = 0; k < 3; ++k) t += R[3 * a + k] * I_body[3 * k + b];
+            tmp[3 * a + b] = t;
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double t = 0.0;
+            for (int k = 0; k < 3; ++k) t += tmp[3 * a + k] * R[3 * b + k];
+            Iw[3 * a + b] = t;
+        }
+    inv3(Iw, Iwi);
+    double L[3];
+    for (int a = 0; a < 3; ++a) L[a] = Iw[3 * a] * w[0] + Iw[3 * a + 1] * w[1] + Iw[3 * a + 2] * w[2];
+    double rhs[3] = {T[0] - (w[1] * L[2] - w[2] * L[1]), T[1] - (w[2] * L[0] - w[0] * L[2]),
+                     T[2] - (w[0] * L[1] - w[1] * L[0])};
+    double wd[3];
+    for (int a = 0; a < 3; ++a) wd[a] = Iwi[3 * a] * rhs[0] + Iwi[3 * a + 1] * rhs[1] + Iwi[3 * a + 2] * rhs[2];
+    for (int a = 0; a < 3; ++a) {
+        v[a] += dt * (F[a] / m + g[a]);
+        w[a] += dt * wd[a];
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Density and pressure (Eqs. density, pressure; Alg. 1 first pass).    */
 /* rho_i = sum_{j in N(i)} mass_j W_ij, boundary mass = psi_b.          */
 /* ------------------------------------------------------------------ */

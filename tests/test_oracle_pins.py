@@ -416,3 +416,91 @@ def test_probe_points_in_body_frame(orc):
     assert np.allclose(w[0], [0.01 + 0.1 * math.cos(ang), -0.02 + 0.1 * math.sin(ang), 0.03], atol=1e-15)
     assert np.allclose(w[1], [0.01, -0.02, 0.08], atol=1e-15)
     assert np.array_equal(w[2], [0.2, 0.2, 0.2])
+
+
+# ---------------------------------------------------------------- free rigid bodies
+
+def _quat_axis(axis, ang):
+    axis = np.asarray(axis, float) / np.linalg.norm(axis)
+    return np.r_[math.cos(ang / 2), math.sin(ang / 2) * axis]
+
+
+def test_body_inertia_closed_form(orc):
+    """Eight point masses at the corners (+-a, +-b, +-c): centre of mass at the
+    centre, body-frame inertia 8 m diag(b^2 + c^2, a^2 + c^2, a^2 + b^2), also
+    when the box is rotated and q0 is that rotation."""
+    a, b, c, m = 0.3, 0.2, 0.1, 0.5
+    pts = np.array([[sx * a, sy * b, sz * c] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)])
+    expect = 8 * m * np.diag([b * b + c * c, a * a + c * c, a * a + b * b])
+    for q0 in (np.array([1.0, 0, 0, 0]), _quat_axis([1, 2, 3], 0.7)):
+        R = orc.quat_to_R(q0).reshape(3, 3)
+        x = pts @ R.T + np.array([1.0, -2.0, 0.5])
+        M, com, I = orc.body_mass_props(x, np.full(8, m), np.zeros(8, np.int32), 0, q0)
+        assert M == pytest.approx(8 * m)
+        assert np.allclose(com, [1.0, -2.0, 0.5], atol=1e-15)
+        assert np.allclose(I, expect, atol=1e-14)
+
+
+def test_body_velocity_step_euler_equations(orc):
+    """I = diag(1, 2, 3), w = (1, 1, 1), no torque: Euler's equations
+    I1 w1' = (I2 - I3) w2 w3 etc. give w' = (-1, 1, -1/3); rotated 90 degrees
+    about z the world inertia is diag(2, 1, 3) and w' = (-1, 1, 1/3).  The
+    linear part is v += dt (F/m + g)."""
+    I = np.diag([1.0, 2.0, 3.0])
+    dt = 1e-3
+    v, w = orc.body_velocity_step([0, 0, 0], [0, 0, 0], 2.0, I, [1, 0, 0, 0], [0, 0, 0], dt, [0, 0, 0], [1, 1, 1])
+    assert np.allclose(w, np.array([1, 1, 1]) + dt * np.array([-1, 1, -1 / 3]), rtol=0, atol=1e-15)
+    v, w = orc.body_velocity_step([0, 0, 0], [0, 0, 0], 2.0, I, _quat_axis([0, 0, 1], math.pi / 2), [0, 0, 0], dt,
+                                  [0, 0, 0], [1, 1, 1])
+    assert np.allclose(w, np.array([1, 1, 1]) + dt * np.array([-1, 1, 1 / 3]), rtol=0, atol=1e-14)
+    v, w = orc.body_velocity_step([3, 0, -1], [0, 0, 6], 2.0, I, [1, 0, 0, 0], [0, 0, -9.81], dt, [1, 2, 3], [0, 0, 0])
+    assert np.allclose(v, [1 + dt * 1.5, 2, 3 + dt * (-0.5 - 9.81)], rtol=0, atol=1e-15)
+    assert np.allclose(w, [0, 0, dt * 2.0], rtol=0, atol=1e-15)
+
+
+def test_torque_free_body_conserves_energy_and_momentum(orc):
+    """Torque-free asymmetric body, 2000 small steps: kinetic energy and the
+    world angular momentum stay constant to O(dt)."""
+    I = np.diag([1.0, 2.0, 3.0])
+    q = np.array([1.0, 0, 0, 0])
+    w = np.array([0.3, 1.0, 0.2])
+    c = np.zeros(3)
+    dt = 1e-4
+
+    def inv(q, w):
+        R = orc.quat_to_R(q).reshape(3, 3)
+        Iw = R @ I @ R.T
+        return 0.5 * w @ Iw @ w, Iw @ w
+    E0, L0 = inv(q, w)
+    for _ in range(2000):
+        _, w = orc.body_velocity_step([0, 0, 0], [0, 0, 0], 1.0, I, q, [0, 0, 0], dt, [0, 0, 0], w)
+        c, q = orc.pose_advance(c, q, [0, 0, 0], w, dt)
+    E1, L1 = inv(q, w)
+    assert abs(E1 - E0) / E0 < 2e-3
+    assert np.linalg.norm(L1 - L0) / np.linalg.norm(L0) < 2e-3
+
+
+def test_free_body_falls_and_spins_in_empty_tank(orc):
+    """A dynamic cube alone (no fluid): the wrench is zero, so the centre of
+    mass follows symplectic-Euler free fall exactly and a cube (isotropic
+    inertia) keeps its spin."""
+    from paper_2511_15908_amd import scenes
+    s = 0.01
+    cube = scenes.block_surface_sites(0, 3, 0, 3, 0, 3).astype(float) * s + 0.1
+    n = cube.shape[0]
+    params = scenes._params(2 * s, 1e-3, (-0.1,) * 3, (0.4,) * 3, "f64")
+    sc = scenes.Scene(name="cube", precision="f64", params=params, x=cube, v=np.zeros_like(cube),
+                      mass=np.full(n, 0.01), type=np.full(n, 2, np.uint8), object=np.zeros(n, np.int32),
+                      object_kinematic=np.array([2], np.uint8), object_pose0=np.array([[0.0, 0, 0, 1, 0, 0, 0]]),
+                      spacing=s)
+    o = orc.Oracle(sc, "f64")
+    c0 = o.pose[0][0].copy()
+    assert np.allclose(c0, 0.1 + 1.5 * s)
+    o.pose[0][3] = np.array([0.0, 0.0, 2.0])
+    N, dt, g = 30, 1e-3, 9.81
+    for _ in range(N):
+        o.step()
+    c, q, v, w = o.pose[0]
+    assert v[2] == pytest.approx(-N * g * dt, rel=1e-12)
+    assert c[2] == pytest.approx(c0[2] - g * dt * dt * N * (N + 1) / 2, rel=1e-12)
+    assert np.allclose(w, [0, 0, 2.0], atol=1e-12)
