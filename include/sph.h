@@ -90,21 +90,28 @@ typedef struct {
     double domain_hi[3];
     double v_max;              /* |v| above this flags SPH_ERR_UNSTABLE; 0 = only non-finite */
     uint32_t max_probes;       /* capacity of density probe points (sph_set_probes), <= 2^20; 0 = none */
-    uint32_t reserved[7];      /* must be zero */
+    uint32_t log_steps;        /* capacity of the per-step body log (sph_read_log), steps; 0 = none */
+    uint32_t reserved[6];      /* must be zero */
 } sph_params;
 
 typedef struct {               /* caller-owned host arrays, read only during sph_init */
     uint32_t n;                /* number of particles (all types) */
     const double *x;           /* [3n] initial positions (rounded to the run precision) */
     const double *v;           /* [3n] initial velocities */
-    const double *mass;        /* [n] mass of fluid/soft particles; ignored for boundary particles */
+    const double *mass;        /* [n] mass of fluid/soft particles and of the particles of free
+                                  rigid bodies (their mass elements); ignored for other boundary
+                                  particles */
     const uint8_t *type;       /* [n] SPH_FLUID / SPH_SOFT / SPH_BOUNDARY */
     const int32_t *object;     /* [n] object id of boundary particles (0..n_objects-1), -1 otherwise */
     uint32_t n_objects;        /* boundary objects */
-    const uint8_t *object_kinematic; /* [n_objects] 1: pose-driven (grabbed) body, 0: static */
+    const uint8_t *object_kinematic; /* [n_objects] 0: static, 1: pose-driven (grabbed) body,
+                                        2: free rigid body (Sec. 3.2 rigid bodies under the summed
+                                        particle forces; grab/release below) */
     const double *object_pose0;      /* [7 n_objects] reference point c[3] and unit quaternion
                                         q[4] = (w,x,y,z) of each object; body-frame offsets are
-                                        taken from x at this pose */
+                                        taken from x at this pose.  For a free rigid body the
+                                        reference point is replaced by its particles' centre of
+                                        mass (the body frame keeps q) */
     uint32_t n_springs;        /* soft-body springs (Sec. 3.2 mass-spring model) */
     const uint32_t *spring_ij; /* [2 n_springs] particle ids of the two ends (soft particles) */
     const double *spring_L0;   /* [n_springs] rest length [m] */
@@ -143,6 +150,64 @@ sph_status sph_init(const sph_params *params, const sph_scene *scene, void *d_wo
  */
 sph_status sph_set_body_pose(sph_ctx *ctx, uint32_t object, const double c[3], const double q[4],
                              const double v[3], const double w[3]);
+
+/*
+ * Free rigid bodies (object_kinematic 2).  Mass m = sum of the body's particle
+ * masses, inertia about their centre of mass from the same particles; each
+ * step, after the wrench, the velocities take a semi-implicit Euler step in
+ * binary64: v += dt (F/m + g), w += dt I_w^-1 (T - w x (I_w w)) with
+ * I_w = R I R^T (Euler's equations), then the pose advances as for a
+ * kinematic body.  There is no contact between rigid bodies or with the tank
+ * (boundary-boundary pairs exert nothing).  sph_set_body_pose also sets the
+ * state of a free body.
+ * sph_grab_body: the body follows sph_set_body_pose (device-driven) until
+ * sph_release_body hands it back to the integration; both keep the current
+ * pose and velocities and restart the rolling average.  SPH_ERR_ARG for an
+ * object that is not a free rigid body.
+ * sph_get_body_state: current c, q, v, w of a kinematic or free body
+ * (synchronises the stream).
+ */
+sph_status sph_grab_body(sph_ctx *ctx, uint32_t object);
+sph_status sph_release_body(sph_ctx *ctx, uint32_t object);
+sph_status sph_get_body_state(sph_ctx *ctx, uint32_t object, double c[3], double q[4], double v[3], double w[3]);
+
+/*
+ * Batches: independent scenes stepped together (one context, one launch per
+ * kernel for all scenes).  params[k] and scenes[k] describe scene k exactly
+ * as for sph_init; the scenes share precision, dt, gravity, v_max,
+ * smoothing_window and log_steps, and take no density probes.  Each scene
+ * keeps its own h, grid, constants and flags.  In the context, particle ids,
+ * object ids and spring ends of scene k follow those of scenes 0..k-1 (a
+ * scene's particle i is id part0_k + i, part0_k = sum of the previous scenes'
+ * n), and every call below works on those global ids.  sph_init is the batch
+ * of one.
+ */
+sph_status sph_batch_workspace_size(const sph_params *params, const sph_scene *scenes, uint32_t n_scenes,
+                                    size_t *bytes);
+sph_status sph_batch_init(const sph_params *params, const sph_scene *scenes, uint32_t n_scenes, void *d_workspace,
+                          size_t ws_bytes, void *hip_stream, sph_ctx **out);
+
+/*
+ * Per-step body log (params.log_steps > 0): every step appends, for each
+ * kinematic or free body in kinematic-index order (ascending object id), 20
+ * doubles: c[3], q[4], v[3], w[3] of the pose the step's forces saw, F[3],
+ * T[3] (the wrench of sph_get_body_wrench, unsmoothed), and the record's step
+ * number.  The log keeps the last log_steps steps.  sph_read_log copies the
+ * kept steps, oldest first, as [steps][bodies][20] into out (n_doubles must
+ * hold them), writes their number to n_steps, empties the log and
+ * synchronises.
+ */
+sph_status sph_read_log(sph_ctx *ctx, double *out, size_t n_doubles, uint32_t *n_steps);
+
+/*
+ * Graph replay (enable != 0): sph_step launches a HIP graph of two captured
+ * steps (captured at the first use, on that call's stream) instead of their
+ * kernels one by one; an odd remainder runs as a plain step.  Needs a
+ * non-default stream (SPH_ERR_ARG otherwise).  Poses, grab/release and
+ * smoothing resets are plain stream work between replays; changing the probe
+ * set or disabling drops the graph.  Profiling steps run without the graph.
+ */
+sph_status sph_set_graph(sph_ctx *ctx, int enable);
 
 /* Enqueue n_steps full steps on hip_stream (no host synchronisation). */
 sph_status sph_step(sph_ctx *ctx, uint32_t n_steps, void *hip_stream);

@@ -33,7 +33,8 @@ EXPORTED = ["sph_workspace_size", "sph_init", "sph_set_body_pose", "sph_step", "
             "sph_reset_smoothing", "sph_read_field", "sph_debug_neighbors", "sph_debug_neighbors_of",
             "sph_get_stats", "sph_get_info",
             "sph_synchronize", "sph_profile_begin", "sph_profile_read", "sph_profile_phase_name",
-            "sph_set_probes", "sph_read_probes",
+            "sph_set_probes", "sph_read_probes", "sph_grab_body", "sph_release_body", "sph_get_body_state",
+            "sph_batch_workspace_size", "sph_batch_init", "sph_read_log", "sph_set_graph",
             "sph_destroy", "sph_status_string", "sph_last_error"]
 
 
@@ -48,7 +49,8 @@ class SphParams(C.Structure):
                 ("smoothing_window", C.c_uint32), ("h", C.c_double), ("rho0", C.c_double),
                 ("k_pressure", C.c_double), ("nu", C.c_double), ("gravity", C.c_double * 3),
                 ("dt", C.c_double), ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
-                ("v_max", C.c_double), ("max_probes", C.c_uint32), ("reserved", C.c_uint32 * 7)]
+                ("v_max", C.c_double), ("max_probes", C.c_uint32), ("log_steps", C.c_uint32),
+                ("reserved", C.c_uint32 * 6)]
 
 
 class SphScene(C.Structure):
@@ -103,6 +105,13 @@ def load_library(path=None):
     L.sph_profile_phase_name.restype = C.c_char_p
     L.sph_set_probes.argtypes = [vp, C.c_uint32, d3, C.POINTER(C.c_int32)]
     L.sph_read_probes.argtypes = [vp, d3, C.c_uint32]
+    L.sph_grab_body.argtypes = [vp, C.c_uint32]
+    L.sph_batch_workspace_size.argtypes = [C.POINTER(SphParams), C.POINTER(SphScene), C.c_uint32, C.POINTER(sz)]
+    L.sph_batch_init.argtypes = [C.POINTER(SphParams), C.POINTER(SphScene), C.c_uint32, vp, sz, vp, C.POINTER(vp)]
+    L.sph_read_log.argtypes = [vp, d3, sz, C.POINTER(C.c_uint32)]
+    L.sph_set_graph.argtypes = [vp, C.c_int]
+    L.sph_release_body.argtypes = [vp, C.c_uint32]
+    L.sph_get_body_state.argtypes = [vp, C.c_uint32, d3, d3, d3, d3]
     L.sph_destroy.argtypes = [vp]
     L.sph_status_string.argtypes = [C.c_int]
     L.sph_status_string.restype = C.c_char_p
@@ -120,7 +129,8 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None and a.size else None
 
 
-def make_params(params: dict, precision: str, v_max: float = 0.0, max_probes: int = 0) -> SphParams:
+def make_params(params: dict, precision: str, v_max: float = 0.0, max_probes: int = 0,
+                log_steps: int = 0) -> SphParams:
     P = SphParams()
     P.abi_version = SPH_ABI_VERSION
     P.precision = SPH_FP64 if precision == "f64" else SPH_FP32
@@ -133,6 +143,7 @@ def make_params(params: dict, precision: str, v_max: float = 0.0, max_probes: in
     P.domain_hi[:] = list(params["domain_hi"])
     P.v_max = float(v_max)
     P.max_probes = int(max_probes)
+    P.log_steps = int(log_steps)
     return P
 
 
@@ -180,38 +191,51 @@ def workspace_size(scene, precision=None, v_max=0.0) -> int:
 class Sim:
     """One simulation context on a GPU.
 
-    scene: a paper_2511_15908_amd.scenes.Scene.  The workspace is a torch
-    uint8 tensor on `device`; kernels run on torch's current stream of that
-    device (or `stream`, a torch.cuda.Stream).
+    scene: a paper_2511_15908_amd.scenes.Scene, or a list of them (a batch
+    stepped together; particle and object ids of scene k follow those of the
+    earlier scenes).  The workspace is a torch uint8 tensor on `device`;
+    kernels run on torch's current stream of that device (or `stream`, a
+    torch.cuda.Stream).
     """
 
-    def __init__(self, scene, precision=None, device="cuda", stream=None, v_max=0.0, params=None, max_probes=0):
+    def __init__(self, scene, precision=None, device="cuda", stream=None, v_max=0.0, params=None, max_probes=0,
+                 log_steps=0):
         import torch
         self.torch = torch
         self.L = load_library()
-        self.precision = precision or scene.precision
+        scenes = list(scene) if isinstance(scene, (list, tuple)) else [scene]
+        self.precision = precision or scenes[0].precision
         self.device = torch.device(device)
         self._stream = stream
-        pr = dict(scene.params)
-        if params:
-            pr.update(params)
-        self.P = make_params(pr, self.precision, v_max, max_probes)
-        A = _SceneArrays(scene)
+        ns = len(scenes)
+        self.P = (SphParams * ns)()
+        self._arrays = [_SceneArrays(sc) for sc in scenes]
+        S = (SphScene * ns)()
+        for k, sc in enumerate(scenes):
+            pr = dict(sc.params)
+            if params:
+                pr.update(params)
+            self.P[k] = make_params(pr, self.precision, v_max, max_probes, log_steps)
+            S[k] = self._arrays[k].struct
         out = C.c_size_t(0)
-        st = self.L.sph_workspace_size(C.byref(self.P), C.byref(A.struct), C.byref(out))
+        st = self.L.sph_batch_workspace_size(self.P, S, ns, C.byref(out))
         if st:
-            raise SphError(st, "sph_workspace_size")
+            raise SphError(st, "sph_batch_workspace_size")
         self.ws_bytes = int(out.value)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         aligned = (base + 255) & ~255
         self.ctx = C.c_void_p()
-        st = self.L.sph_init(C.byref(self.P), C.byref(A.struct), C.c_void_p(aligned),
-                             self.ws_bytes, self.stream_handle(), C.byref(self.ctx))
+        st = self.L.sph_batch_init(self.P, S, ns, C.c_void_p(aligned), self.ws_bytes, self.stream_handle(),
+                                   C.byref(self.ctx))
         if st:
-            raise SphError(st, "sph_init")
-        self.n = scene.n
-        self.kinematic = [o for o in range(len(scene.object_kinematic)) if scene.object_kinematic[o]]
+            raise SphError(st, "sph_batch_init")
+        self.n = sum(sc.n for sc in scenes)
+        self.part0 = np.cumsum([0] + [sc.n for sc in scenes])
+        self.obj0 = np.cumsum([0] + [len(sc.object_kinematic) for sc in scenes])
+        self.kinematic = [int(self.obj0[k]) + o for k, sc in enumerate(scenes)
+                          for o in range(len(sc.object_kinematic)) if sc.object_kinematic[o]]
+        self.log_steps = int(log_steps)
 
     # -- plumbing
     def stream_handle(self):
@@ -239,6 +263,33 @@ class Sim:
         if check:
             self._check(st, "sph_get_body_wrench")
         return F, T
+
+    def set_graph(self, enable=True):
+        """Replay steps as a captured two-step HIP graph (non-default stream)."""
+        self._check(self.L.sph_set_graph(self.ctx, int(bool(enable))), "sph_set_graph")
+
+    def read_log(self):
+        """Per-step body records [steps][bodies][20] (c, q, v, w, F, T, step),
+        oldest first; empties the log."""
+        nb = len(self.kinematic)
+        out = np.zeros(max(self.log_steps, 1) * max(nb, 1) * 20)
+        m = C.c_uint32(0)
+        self._check(self.L.sph_read_log(self.ctx, _dp(out), out.size, C.byref(m)), "sph_read_log")
+        return out[:m.value * nb * 20].reshape(m.value, nb, 20)
+
+    def grab(self, obj):
+        """A free rigid body follows set_body_pose until release()."""
+        self._check(self.L.sph_grab_body(self.ctx, int(obj)), "sph_grab_body")
+
+    def release(self, obj):
+        self._check(self.L.sph_release_body(self.ctx, int(obj)), "sph_release_body")
+
+    def body_state(self, obj):
+        """(c, q, v, w) of a kinematic or free body (synchronises)."""
+        c, q, v, w = np.zeros(3), np.zeros(4), np.zeros(3), np.zeros(3)
+        self._check(self.L.sph_get_body_state(self.ctx, int(obj), _dp(c), _dp(q), _dp(v), _dp(w)),
+                    "sph_get_body_state")
+        return c, q, v, w
 
     def reset_smoothing(self, obj):
         self._check(self.L.sph_reset_smoothing(self.ctx, int(obj)), "sph_reset_smoothing")

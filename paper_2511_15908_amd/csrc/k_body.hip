@@ -120,9 +120,48 @@ __global__ __launch_bounds__(64) void k_wrench_final(BodyArgs b)
         double *slot = b.ring + ((size_t)o * b.K + (cnt % b.K)) * 6u;
         for (int c = 0; c < 6; ++c) slot[c] = v[c];
         b.ring_count[o] = cnt + 1u;
-        // pose advance: c += v dt, q <- normalise(q + dt/2 (0, w) q)
         double *pz = b.poses + 16u * o;
         const double dt = b.dt;
+        if (b.log_cap) {
+            // the step's record: the pose and velocities the forces saw, the wrench
+            const uint32_t row = b.log_count[o];
+            double *r = b.log + ((size_t)(row % b.log_cap) * b.nk + o) * 20u;
+            for (int a = 0; a < 13; ++a) r[a] = pz[a];
+            for (int c = 0; c < 6; ++c) r[13 + c] = v[c];
+            r[19] = (double)row;
+            b.log_count[o] = row + 1u;
+        }
+        if (b.props && b.props[24u * o + kPropFree] != 0.0) {
+            // free body: v += dt (F/m + g); w += dt I_w^-1 (T - w x I_w w),
+            // I_w = R I R^T and I_w^-1 = R I^-1 R^T (Euler's equations)
+            const double *pr = b.props + 24u * o;
+            double R[9];
+            quat_R(pz + 3, R);
+            double Iw[9], Iwi[9];
+            for (int r = 0; r < 3; ++r)
+                for (int c2 = 0; c2 < 3; ++c2) {
+                    double a1 = 0.0, a2 = 0.0;
+                    for (int k = 0; k < 3; ++k)
+                        for (int l = 0; l < 3; ++l) {
+                            a1 += R[3 * r + k] * pr[1 + 3 * k + l] * R[3 * c2 + l];
+                            a2 += R[3 * r + k] * pr[10 + 3 * k + l] * R[3 * c2 + l];
+                        }
+                    Iw[3 * r + c2] = a1;
+                    Iwi[3 * r + c2] = a2;
+                }
+            const double w0 = pz[10], w1 = pz[11], w2 = pz[12];
+            const double L0 = Iw[0] * w0 + Iw[1] * w1 + Iw[2] * w2;
+            const double L1 = Iw[3] * w0 + Iw[4] * w1 + Iw[5] * w2;
+            const double L2 = Iw[6] * w0 + Iw[7] * w1 + Iw[8] * w2;
+            const double r0 = v[3] - (w1 * L2 - w2 * L1);
+            const double r1 = v[4] - (w2 * L0 - w0 * L2);
+            const double r2 = v[5] - (w0 * L1 - w1 * L0);
+            for (int a = 0; a < 3; ++a) {
+                pz[7 + a] = pz[7 + a] + dt * (v[a] / pr[0] + b.g[a]);
+                pz[10 + a] = pz[10 + a] + dt * (Iwi[3 * a] * r0 + Iwi[3 * a + 1] * r1 + Iwi[3 * a + 2] * r2);
+            }
+        }
+        // pose advance: c += v dt, q <- normalise(q + dt/2 (0, w) q)
         for (int a = 0; a < 3; ++a) pz[a] = pz[a] + pz[7 + a] * dt;
         const double qw = pz[3], qx = pz[4], qy = pz[5], qz = pz[6];
         const double wx = pz[10], wy = pz[11], wz = pz[12];
@@ -178,6 +217,16 @@ void launch_reset_ring(hipStream_t s, uint32_t *ring_count_slot)
     hipLaunchKernelGGL(k_reset_ring, dim3(1), dim3(64), 0, s, ring_count_slot);
 }
 
+__global__ void k_set_double(double *__restrict__ slot, double v)
+{
+    if (threadIdx.x == 0) slot[0] = v;
+}
+
+void launch_set_double(hipStream_t s, double *slot, double v)
+{
+    hipLaunchKernelGGL(k_set_double, dim3(1), dim3(64), 0, s, slot, v);
+}
+
 // ------------------------------------------------------------------ density probes
 
 // rho(p) = sum over fluid/soft j with predicate(p, x_j) of m_j W(|p - x_j|):
@@ -185,13 +234,15 @@ void launch_reset_ring(hipStream_t s, uint32_t *ring_count_slot)
 // One wavefront per probe: the lanes stride over the particles of each of the
 // 27 cells (coalesced loads), FP64 partial sums, fixed shuffle-tree reduction.
 template <typename T>
-__global__ __launch_bounds__(64) void k_probe(ProbeArgs a, State<T> st, Grid g, Phys<T> ph,
+__global__ __launch_bounds__(64) void k_probe(ProbeArgs a, State<T> st, Batch<T> b,
                                               const uint32_t *__restrict__ cstart,
                                               const uint32_t *__restrict__ cend)
 {
 #pragma clang fp contract(off)
     const uint32_t i = blockIdx.x, lane = threadIdx.x;
     if (i >= a.n) return;
+    const Grid g = b.sc[0].g;          // probes are offered for single-scene contexts
+    const Phys<T> ph = b.sc[0].ph;
     double p[3] = {a.pts[3 * i], a.pts[3 * i + 1], a.pts[3 * i + 2]};
     const int32_t f = a.frame[i];
     if (f >= 0) {
@@ -215,7 +266,7 @@ __global__ __launch_bounds__(64) void k_probe(ProbeArgs a, State<T> st, Grid g, 
         stencil_offset(k, ox, oy, oz);
         const int nx = cx + ox, ny = cy + oy, nz = cz + oz;
         if (nx < 0 || ny < 0 || nz < 0 || nx >= g.dims[0] || ny >= g.dims[1] || nz >= g.dims[2]) continue;
-        const uint32_t key = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
+        const uint32_t key = g.slot0 + morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
         const uint32_t e = cend[key];
         for (uint32_t j = cstart[key] + lane; j < e; j += 64u) {
             const V4<T> c = st.pos[j];
@@ -230,16 +281,16 @@ __global__ __launch_bounds__(64) void k_probe(ProbeArgs a, State<T> st, Grid g, 
 }
 
 template <typename T>
-void launch_probe(hipStream_t s, const ProbeArgs &a, State<T> st, const Grid &g, const Phys<T> &ph,
-                  const uint32_t *cstart, const uint32_t *cend)
+void launch_probe(hipStream_t s, const ProbeArgs &a, State<T> st, const Batch<T> &b, const uint32_t *cstart,
+                  const uint32_t *cend)
 {
     if (!a.n) return;
-    hipLaunchKernelGGL(k_probe<T>, dim3(a.n), dim3(64), 0, s, a, st, g, ph, cstart, cend);
+    hipLaunchKernelGGL(k_probe<T>, dim3(a.n), dim3(64), 0, s, a, st, b, cstart, cend);
 }
-template void launch_probe<float>(hipStream_t, const ProbeArgs &, State<float>, const Grid &, const Phys<float> &,
+template void launch_probe<float>(hipStream_t, const ProbeArgs &, State<float>, const Batch<float> &,
                                   const uint32_t *, const uint32_t *);
-template void launch_probe<double>(hipStream_t, const ProbeArgs &, State<double>, const Grid &,
-                                   const Phys<double> &, const uint32_t *, const uint32_t *);
+template void launch_probe<double>(hipStream_t, const ProbeArgs &, State<double>, const Batch<double> &,
+                                   const uint32_t *, const uint32_t *);
 
 // ------------------------------------------------------------------ springs
 

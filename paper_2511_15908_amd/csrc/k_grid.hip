@@ -12,28 +12,29 @@ namespace sphk {
 // ---------------------------------------------------------------- cell keys
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_keys(uint32_t n, const V4<T> *__restrict__ pos, Grid g,
+__global__ __launch_bounds__(256) void k_keys(uint32_t n, const V4<T> *__restrict__ pos, Batch<T> b,
                                               uint32_t *__restrict__ keys)
 {
     uint32_t i = blockIdx.x * 256u + threadIdx.x;
     if (i >= n) return;
+    const Grid g = b.sc[scene_of_particle(b, i)].g;
     T lo[3], inv;
     grid_lo_inv<T>(g, lo, inv);
     V4<T> p = pos[i];
     int cx = cell_coord<T>(p.x, lo[0], inv, g.dims[0]);
     int cy = cell_coord<T>(p.y, lo[1], inv, g.dims[1]);
     int cz = cell_coord<T>(p.z, lo[2], inv, g.dims[2]);
-    keys[i] = morton3((uint32_t)cx, (uint32_t)cy, (uint32_t)cz);
+    keys[i] = g.slot0 + morton3((uint32_t)cx, (uint32_t)cy, (uint32_t)cz);
 }
 
 template <typename T>
-void launch_keys(hipStream_t s, uint32_t n, const V4<T> *pos, const Grid &g, uint32_t *keys)
+void launch_keys(hipStream_t s, uint32_t n, const V4<T> *pos, const Batch<T> &b, uint32_t *keys)
 {
     if (!n) return;
-    hipLaunchKernelGGL(k_keys<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, g, keys);
+    hipLaunchKernelGGL(k_keys<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, b, keys);
 }
-template void launch_keys<float>(hipStream_t, uint32_t, const V4<float> *, const Grid &, uint32_t *);
-template void launch_keys<double>(hipStream_t, uint32_t, const V4<double> *, const Grid &, uint32_t *);
+template void launch_keys<float>(hipStream_t, uint32_t, const V4<float> *, const Batch<float> &, uint32_t *);
+template void launch_keys<double>(hipStream_t, uint32_t, const V4<double> *, const Batch<double> &, uint32_t *);
 
 // ---------------------------------------------------------------- radix sort
 // Tile of 2048 keys per block (256 threads x 8 rounds).  hist is digit-major:
@@ -249,7 +250,7 @@ template void launch_reorder<double>(hipStream_t, uint32_t, const uint32_t *, co
 
 // psi_b = rho0 / sum_{k in N(b), same object} W(r_bk), written as pos.w = -psi_b.
 template <typename T>
-__global__ __launch_bounds__(128) void k_psi(uint32_t n, State<T> st, Grid g, Phys<T> ph,
+__global__ __launch_bounds__(128) void k_psi(uint32_t n, State<T> st, Batch<T> b,
                                              const uint32_t *__restrict__ cstart,
                                              const uint32_t *__restrict__ cend,
                                              const int32_t *__restrict__ obj_of_id)
@@ -257,6 +258,9 @@ __global__ __launch_bounds__(128) void k_psi(uint32_t n, State<T> st, Grid g, Ph
     uint32_t p = blockIdx.x * 128u + threadIdx.x;
     if (p >= n) return;
     if (aux_type(st.aux[p]) != TY_BOUNDARY) return;
+    const SceneC<T> &scn = b.sc[scene_of_particle(b, p)];
+    const Grid g = scn.g;
+    const Phys<T> ph = scn.ph;
     const V4<T> me = st.pos[p];
     const int32_t ob = obj_of_id[st.id[p]];
     T lo[3], inv;
@@ -271,7 +275,7 @@ __global__ __launch_bounds__(128) void k_psi(uint32_t n, State<T> st, Grid g, Ph
         stencil_offset(k, ox, oy, oz);
         const int nx = cx + ox, ny = cy + oy, nz = cz + oz;
         if (nx < 0 || ny < 0 || nz < 0 || nx >= g.dims[0] || ny >= g.dims[1] || nz >= g.dims[2]) continue;
-        const uint32_t key = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
+        const uint32_t key = g.slot0 + morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
         const uint32_t e = cend[key];
         for (uint32_t j = cstart[key]; j < e; ++j) {
             if (aux_type(st.aux[j]) != TY_BOUNDARY) continue;
@@ -290,11 +294,11 @@ __global__ __launch_bounds__(128) void k_psi(uint32_t n, State<T> st, Grid g, Ph
 }
 
 template <typename T>
-static void launch_psi_impl(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
-                     const uint32_t *cstart, const uint32_t *cend, const int32_t *obj_of_id)
+static void launch_psi_impl(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, const uint32_t *cstart,
+                            const uint32_t *cend, const int32_t *obj_of_id)
 {
     if (!n) return;
-    hipLaunchKernelGGL(k_psi<T>, dim3((n + 127) / 128), dim3(128), 0, s, n, st, g, ph, cstart, cend, obj_of_id);
+    hipLaunchKernelGGL(k_psi<T>, dim3((n + 127) / 128), dim3(128), 0, s, n, st, b, cstart, cend, obj_of_id);
 }
 
 }  // namespace sphk
@@ -302,13 +306,13 @@ static void launch_psi_impl(hipStream_t s, uint32_t n, State<T> st, const Grid &
 // explicit entry used by the API translation unit
 namespace sphk {
 template <typename T>
-void launch_psi_obj(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
-                    const uint32_t *cstart, const uint32_t *cend, const int32_t *obj_of_id)
+void launch_psi_obj(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, const uint32_t *cstart,
+                    const uint32_t *cend, const int32_t *obj_of_id)
 {
-    launch_psi_impl<T>(s, n, st, g, ph, cstart, cend, obj_of_id);
+    launch_psi_impl<T>(s, n, st, b, cstart, cend, obj_of_id);
 }
-template void launch_psi_obj<float>(hipStream_t, uint32_t, State<float>, const Grid &, const Phys<float> &,
-                                    const uint32_t *, const uint32_t *, const int32_t *);
-template void launch_psi_obj<double>(hipStream_t, uint32_t, State<double>, const Grid &, const Phys<double> &,
-                                     const uint32_t *, const uint32_t *, const int32_t *);
+template void launch_psi_obj<float>(hipStream_t, uint32_t, State<float>, const Batch<float> &, const uint32_t *,
+                                    const uint32_t *, const int32_t *);
+template void launch_psi_obj<double>(hipStream_t, uint32_t, State<double>, const Batch<double> &, const uint32_t *,
+                                     const uint32_t *, const int32_t *);
 }  // namespace sphk

@@ -62,7 +62,7 @@ __device__ __forceinline__ uint32_t share(uint32_t c, uint32_t s, uint32_t S)
     return c > s ? (c - s + S - 1u) / S : 0u;
 }
 
-// Load the 27 cells around `cell`, choose S so every super-chunk fits
+// Load the 27 cells around `cell` (index in its scene's grid), choose S so every super-chunk fits
 // kScWords words, and lay the super-chunks out in words.  Returns false
 // (uniformly) when the neighbourhood exceeds kMaxWords words.
 __device__ __forceinline__ bool load_nbhd(uint32_t cell, const Grid &g, const uint32_t *__restrict__ cs,
@@ -75,7 +75,7 @@ __device__ __forceinline__ bool load_nbhd(uint32_t cell, const Grid &g, const ui
         stencil_offset((int)lane, ox, oy, oz);
         const int nx = cx + ox, ny = cy + oy, nz = cz + oz;
         if (nx >= 0 && ny >= 0 && nz >= 0 && nx < g.dims[0] && ny < g.dims[1] && nz < g.dims[2]) {
-            const uint32_t k = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
+            const uint32_t k = g.slot0 + morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
             st = cs[k];
             cnt = ce[k] - st;
         }
@@ -196,7 +196,7 @@ constexpr uint32_t kLeftD = SPH_LEFT_DENSITY;   // most leftover targets of the 
 constexpr uint32_t kLeftF = SPH_LEFT_FORCE;     // of the force pass
 
 template <typename T>
-__global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n, State<T> st, Grid g, Phys<T> ph,
+__global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n, State<T> st, Batch<T> b,
                                                 const uint32_t *__restrict__ cstart,
                                                 const uint32_t *__restrict__ cend, V2<T> *__restrict__ dens,
                                                 uint64_t *__restrict__ masks, uint32_t *__restrict__ err,
@@ -207,11 +207,14 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
     __shared__ uint32_t mlds[2 * kScWords][kWave];
     __shared__ double accl[kLeftD > 0 ? kLeftD : 1];
     const uint32_t lane = threadIdx.x;
-    const uint32_t cell = cell_of_block(blockIdx.x, g.nslots);
-    if (cell >= g.nslots) return;
-    const uint32_t s0 = cstart[cell], e0 = cend[cell];
+    const uint32_t slot = cell_of_block(blockIdx.x, b.nslots);
+    if (slot >= b.nslots) return;
+    const uint32_t s0 = cstart[slot], e0 = cend[slot];
     if (s0 >= e0) return;
-    if (!load_nbhd(cell, g, cstart, cend, nb, lane)) {
+    const SceneC<T> &scn = b.sc[scene_of_slot(b, slot)];
+    const Grid g = scn.g;
+    const Phys<T> ph = scn.ph;
+    if (!load_nbhd(slot - g.slot0, g, cstart, cend, nb, lane)) {
         if (lane == 0) atomicOr(err, ERR_CAPACITY);
         return;
     }
@@ -430,7 +433,7 @@ __device__ __forceinline__ void store_force(uint32_t p, uint32_t aux, T ma, doub
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, Phys<T> ph,
+__global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T> b,
                                                const uint32_t *__restrict__ cstart,
                                                const uint32_t *__restrict__ cend, const V2<T> *__restrict__ dens,
                                                const uint64_t *__restrict__ masks,
@@ -444,11 +447,14 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, 
     __shared__ uint32_t mlds[2 * kScWords][kWave];
     __shared__ double accf[kLeftF > 0 ? kLeftF : 1][3];
     const uint32_t lane = threadIdx.x;
-    const uint32_t cell = cell_of_block(blockIdx.x, g.nslots);
-    if (cell >= g.nslots) return;
-    const uint32_t s0 = cstart[cell], e0 = cend[cell];
+    const uint32_t slot = cell_of_block(blockIdx.x, b.nslots);
+    if (slot >= b.nslots) return;
+    const uint32_t s0 = cstart[slot], e0 = cend[slot];
     if (s0 >= e0) return;
-    if (!load_nbhd(cell, g, cstart, cend, nb, lane)) return;   // flagged by the density pass
+    const SceneC<T> &scn = b.sc[scene_of_slot(b, slot)];
+    const Grid g = scn.g;
+    const Phys<T> ph = scn.ph;
+    if (!load_nbhd(slot - g.slot0, g, cstart, cend, nb, lane)) return;   // flagged by the density pass
     const uint32_t S = nb.stride;
     const uint32_t ncell = e0 - s0, rem = ncell % kWave;
     const bool use_left = ncell > (uint32_t)kWave && rem != 0u && rem <= kLeftF;
@@ -567,37 +573,34 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Grid g, 
 }
 
 template <typename T>
-void launch_density(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
-                    const uint32_t *cstart, const uint32_t *cend, V2<T> *dens, uint64_t *masks, uint32_t *err,
-                    unsigned long long *stats)
+void launch_density(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, const uint32_t *cstart,
+                    const uint32_t *cend, V2<T> *dens, uint64_t *masks, uint32_t *err, unsigned long long *stats)
 {
     if (!n) return;
-    hipLaunchKernelGGL(k_density<T>, dim3(g.nslots), dim3(64), 0, s, n, st, g, ph, cstart, cend, dens, masks,
-                       err, stats);
+    hipLaunchKernelGGL(k_density<T>, dim3(b.nslots), dim3(64), 0, s, n, st, b, cstart, cend, dens, masks, err,
+                       stats);
 }
 
 template <typename T>
-void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
-                   const uint32_t *cstart, const uint32_t *cend, const V2<T> *dens, const uint64_t *masks,
-                   const V4<T> *fspring, V4<T> *force, double *fbody, uint32_t *err, unsigned long long *stats)
+void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, const uint32_t *cstart,
+                   const uint32_t *cend, const V2<T> *dens, const uint64_t *masks, const V4<T> *fspring,
+                   V4<T> *force, double *fbody, uint32_t *err, unsigned long long *stats)
 {
     (void)err;
     if (!n) return;
-    hipLaunchKernelGGL(k_forces<T>, dim3(g.nslots), dim3(64), 0, s, n, st, g, ph, cstart, cend, dens, masks,
-                       fspring, force, fbody, stats);
+    hipLaunchKernelGGL(k_forces<T>, dim3(b.nslots), dim3(64), 0, s, n, st, b, cstart, cend, dens, masks, fspring,
+                       force, fbody, stats);
 }
 
-template void launch_density<float>(hipStream_t, uint32_t, State<float>, const Grid &, const Phys<float> &,
-                                    const uint32_t *, const uint32_t *, V2<float> *, uint64_t *, uint32_t *,
-                                    unsigned long long *);
-template void launch_density<double>(hipStream_t, uint32_t, State<double>, const Grid &, const Phys<double> &,
-                                     const uint32_t *, const uint32_t *, V2<double> *, uint64_t *, uint32_t *,
-                                     unsigned long long *);
-template void launch_forces<float>(hipStream_t, uint32_t, State<float>, const Grid &, const Phys<float> &,
-                                   const uint32_t *, const uint32_t *, const V2<float> *, const uint64_t *,
-                                   const V4<float> *, V4<float> *, double *, uint32_t *, unsigned long long *);
-template void launch_forces<double>(hipStream_t, uint32_t, State<double>, const Grid &, const Phys<double> &,
-                                    const uint32_t *, const uint32_t *, const V2<double> *, const uint64_t *,
-                                    const V4<double> *, V4<double> *, double *, uint32_t *, unsigned long long *);
+template void launch_density<float>(hipStream_t, uint32_t, State<float>, const Batch<float> &, const uint32_t *,
+                                    const uint32_t *, V2<float> *, uint64_t *, uint32_t *, unsigned long long *);
+template void launch_density<double>(hipStream_t, uint32_t, State<double>, const Batch<double> &, const uint32_t *,
+                                     const uint32_t *, V2<double> *, uint64_t *, uint32_t *, unsigned long long *);
+template void launch_forces<float>(hipStream_t, uint32_t, State<float>, const Batch<float> &, const uint32_t *,
+                                   const uint32_t *, const V2<float> *, const uint64_t *, const V4<float> *,
+                                   V4<float> *, double *, uint32_t *, unsigned long long *);
+template void launch_forces<double>(hipStream_t, uint32_t, State<double>, const Batch<double> &, const uint32_t *,
+                                    const uint32_t *, const V2<double> *, const uint64_t *, const V4<double> *,
+                                    V4<double> *, double *, uint32_t *, unsigned long long *);
 
 }  // namespace sphk

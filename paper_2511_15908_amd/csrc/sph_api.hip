@@ -41,10 +41,24 @@ struct sph_ctx {
     uint32_t nb = 0, nk = 0, n_objects = 0, rows = 0, nsprings = 0, nblk_w = 0, K = 1;
     std::vector<int32_t> kin_of_object;   // object -> kinematic index or -1
     std::vector<uint32_t> kin_objects;    // kinematic index -> object
-    Grid grid{};
+    std::vector<uint8_t> dynamic;         // kinematic index -> free rigid body type (object_kinematic 2)
+    std::vector<uint8_t> free_now;        // kinematic index -> currently integrated (not grabbed)
+    Grid grid{};                          // scene 0's grid
     double cell_size = 0;
-    Phys<float> phf{};
+    Phys<float> phf{};                    // scene 0's constants (dt, gravity, v_max are shared)
     Phys<double> phd{};
+    uint32_t nscenes = 1, nslots = 0;     // scenes of the batch, key slots of all scenes
+    std::vector<Grid> grids;              // per scene, slot0 set
+    std::vector<uint32_t> part0;          // first particle id of each scene (+ total)
+    void *scene_tab = nullptr;            // device SceneC<T>[nscenes]
+    // per-step log of every kinematic / free body
+    uint32_t log_cap = 0;
+    double *log = nullptr;
+    uint32_t *log_count = nullptr;
+    // graph replay of two steps
+    bool graph_on = false;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_parity = 0;
     hipStream_t stream = nullptr;
     // device buffers
     void *pos[2] = {nullptr, nullptr}, *vel[2] = {nullptr, nullptr};
@@ -58,7 +72,7 @@ struct sph_ctx {
     uint32_t *row_id = nullptr, *row_ptr = nullptr, *partner = nullptr;
     double *sprm = nullptr;
     uint32_t *slot_id = nullptr, *slot_obj = nullptr;
-    double *r_loc = nullptr, *poses = nullptr, *fbody = nullptr, *partials = nullptr;
+    double *r_loc = nullptr, *poses = nullptr, *fbody = nullptr, *partials = nullptr, *props = nullptr;
     uint32_t *blk_obj = nullptr, *blk_first = nullptr, *blk_count = nullptr, *obj_blk0 = nullptr;
     double *ring = nullptr;
     uint32_t *ring_count = nullptr;
@@ -74,6 +88,7 @@ struct sph_ctx {
     bool dead = false;
     std::string last_error;
     std::vector<uint8_t> type_of_id;      // host copy of types (read_field)
+    std::vector<sph_params> prms;         // per scene
     // profiling
     uint32_t prof_left = 0;
     std::vector<hipEvent_t> prof_ev;      // pairs per (step, phase)
@@ -102,8 +117,80 @@ sph_status dev_fail(sph_ctx *c, hipError_t e, const char *what)
 
 bool finite3(const double *v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
 
+void quat_normalise(const double *q, double *out)
+{
+    const double s = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 4; ++k) out[k] = q[k] / s;
+}
+
+void quat_to_R(const double *q, double R[9])
+{
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Mass, centre of mass, body-frame inertia about it (and its inverse) of the
+// particles of object o; the body frame is that of the initial quaternion.
+// False when the inertia tensor is (numerically) singular.
+bool body_mass_props(const sph_scene *s, uint32_t o, double *m_out, double com[3], double I[9], double Ii[9])
+{
+    double m = 0, sx[3] = {0, 0, 0};
+    for (uint32_t i = 0; i < s->n; ++i) {
+        if (s->type[i] != SPH_BOUNDARY || s->object[i] != (int32_t)o) continue;
+        m += s->mass[i];
+        for (int a = 0; a < 3; ++a) sx[a] += s->mass[i] * s->x[3 * i + a];
+    }
+    if (!(m > 0)) return false;
+    for (int a = 0; a < 3; ++a) com[a] = sx[a] / m;
+    double q[4], R[9];
+    quat_normalise(s->object_pose0 + 7 * o + 3, q);
+    quat_to_R(q, R);
+    for (int a = 0; a < 9; ++a) I[a] = 0;
+    for (uint32_t i = 0; i < s->n; ++i) {
+        if (s->type[i] != SPH_BOUNDARY || s->object[i] != (int32_t)o) continue;
+        const double d[3] = {s->x[3 * i] - com[0], s->x[3 * i + 1] - com[1], s->x[3 * i + 2] - com[2]};
+        double r[3];
+        for (int a = 0; a < 3; ++a) r[a] = R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2];
+        const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) I[3 * a + b] += s->mass[i] * ((a == b ? rr : 0.0) - r[a] * r[b]);
+    }
+    *m_out = m;
+    // inverse by Gauss-Jordan elimination with partial pivoting
+    double A[3][6];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 6; ++b) A[a][b] = b < 3 ? I[3 * a + b] : (b - 3 == a ? 1.0 : 0.0);
+    const double scale = fabs(I[0]) + fabs(I[4]) + fabs(I[8]);
+    for (int col = 0; col < 3; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 3; ++r)
+            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+        if (!(fabs(A[piv][col]) > 1e-12 * scale)) return false;
+        if (piv != col)
+            for (int b = 0; b < 6; ++b) std::swap(A[piv][b], A[col][b]);
+        const double d = A[col][col];
+        for (int b = 0; b < 6; ++b) A[col][b] /= d;
+        for (int r = 0; r < 3; ++r)
+            if (r != col) {
+                const double f = A[r][col];
+                for (int b = 0; b < 6; ++b) A[r][b] -= f * A[col][b];
+            }
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Ii[3 * a + b] = A[a][b + 3];
+    return true;
+}
+
 struct Plan {
-    uint32_t n, nb, nk, rows, nsp2, nblk_w, nslots, K, nblk_sort, max_probes;
+    uint32_t n, nb, nk, rows, nsp2, nblk_w, nslots, K, nblk_sort, max_probes, nscenes, log_steps;
     int prec;
 };
 
@@ -201,8 +288,8 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
     }
     uint32_t nk = 0, nb = 0, nsoft = 0;
     for (uint32_t o = 0; o < s->n_objects; ++o) {
-        if (s->object_kinematic[o] > 1) {
-            why = "object_kinematic must be 0 or 1";
+        if (s->object_kinematic[o] > 2) {
+            why = "object_kinematic must be 0 (static), 1 (kinematic) or 2 (free rigid body)";
             return SPH_ERR_ARG;
         }
         const double *pz = s->object_pose0 + 7 * o;
@@ -217,7 +304,7 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
             why = "zero quaternion";
             return SPH_ERR_ARG;
         }
-        nk += s->object_kinematic[o];
+        nk += s->object_kinematic[o] ? 1u : 0u;
     }
     std::vector<uint32_t> per_obj(s->n_objects, 0);
     for (uint32_t i = 0; i < n; ++i) {
@@ -239,6 +326,10 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
             }
             per_obj[o]++;
             if (s->object_kinematic[o]) ++nb;
+            if (s->object_kinematic[o] == 2 && (!(s->mass[i] > 0) || !isfinite(s->mass[i]))) {
+                why = "particles of a free rigid body need positive finite masses";
+                return SPH_ERR_ARG;
+            }
         } else {
             if (!(s->mass[i] > 0) || !isfinite(s->mass[i])) {
                 why = "fluid/soft mass must be positive and finite";
@@ -266,8 +357,16 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
         }
     }
     uint32_t nblk_w = 0;
-    for (uint32_t o = 0; o < s->n_objects; ++o)
+    for (uint32_t o = 0; o < s->n_objects; ++o) {
         if (s->object_kinematic[o]) nblk_w += (per_obj[o] + 255) / 256;
+        if (s->object_kinematic[o] == 2) {
+            double m = 0, com[3], I[9], Ii[9];
+            if (!per_obj[o] || !body_mass_props(s, o, &m, com, I, Ii)) {
+                why = "a free rigid body needs particles whose inertia tensor is invertible";
+                return SPH_ERR_ARG;
+            }
+        }
+    }
     pl.n = n;
     pl.nb = nb;
     pl.nk = nk;
@@ -279,6 +378,124 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
     pl.nblk_sort = (n + 2047) / 2048;
     pl.prec = p->precision;
     pl.max_probes = p->max_probes;
+    pl.nscenes = 1;
+    pl.log_steps = p->log_steps;
+    return SPH_OK;
+}
+
+// The scenes of a batch concatenated: particle ids, object ids and spring
+// ends of scene k follow those of scenes < k.
+struct Merged {
+    std::vector<double> x, v, mass, pose0, L0, ks, cs;
+    std::vector<uint8_t> type, kin;
+    std::vector<int32_t> object;
+    std::vector<uint32_t> ij;
+    std::vector<uint32_t> part0;          // first particle id of each scene, then the total
+    sph_scene view{};
+};
+
+void merge(const sph_scene *sc, uint32_t ns, Merged &m)
+{
+    m.part0.assign(1, 0);
+    uint32_t obj0 = 0;
+    for (uint32_t k = 0; k < ns; ++k) {
+        const sph_scene &s = sc[k];
+        const uint32_t p0 = m.part0.back();
+        m.x.insert(m.x.end(), s.x, s.x + 3 * (size_t)s.n);
+        m.v.insert(m.v.end(), s.v, s.v + 3 * (size_t)s.n);
+        m.mass.insert(m.mass.end(), s.mass, s.mass + s.n);
+        m.type.insert(m.type.end(), s.type, s.type + s.n);
+        for (uint32_t i = 0; i < s.n; ++i) m.object.push_back(s.object[i] >= 0 ? s.object[i] + (int32_t)obj0 : -1);
+        if (s.n_objects) {
+            m.kin.insert(m.kin.end(), s.object_kinematic, s.object_kinematic + s.n_objects);
+            m.pose0.insert(m.pose0.end(), s.object_pose0, s.object_pose0 + 7 * (size_t)s.n_objects);
+        }
+        for (uint32_t e = 0; e < 2 * s.n_springs; ++e) m.ij.push_back(s.spring_ij[e] + p0);
+        if (s.n_springs) {
+            m.L0.insert(m.L0.end(), s.spring_L0, s.spring_L0 + s.n_springs);
+            m.ks.insert(m.ks.end(), s.spring_k, s.spring_k + s.n_springs);
+            m.cs.insert(m.cs.end(), s.spring_c, s.spring_c + s.n_springs);
+        }
+        obj0 += s.n_objects;
+        m.part0.push_back(p0 + s.n);
+    }
+    sph_scene &w = m.view;
+    w.n = m.part0.back();
+    w.x = m.x.data();
+    w.v = m.v.data();
+    w.mass = m.mass.data();
+    w.type = m.type.data();
+    w.object = m.object.data();
+    w.n_objects = obj0;
+    w.object_kinematic = m.kin.data();
+    w.object_pose0 = m.pose0.data();
+    w.n_springs = (uint32_t)m.L0.size();
+    w.spring_ij = m.ij.data();
+    w.spring_L0 = m.L0.data();
+    w.spring_k = m.ks.data();
+    w.spring_c = m.cs.data();
+}
+
+// Validate every scene of a batch with its parameters, the shared settings,
+// and the batch totals; grids get their slot0 in the batch's key space.
+sph_status validate_batch(const sph_params *p, const sph_scene *sc, uint32_t ns, Plan &pl, std::string &why,
+                          std::vector<Grid> *grids, std::vector<double> *csz, Merged *merged)
+{
+    if (!p || !sc || ns < 1 || ns > 65536u) {
+        why = "need 1..65536 scenes with their parameters";
+        return SPH_ERR_ARG;
+    }
+    Plan tot{};
+    uint64_t slots = 0, n = 0;
+    if (grids) grids->clear();
+    if (csz) csz->clear();
+    for (uint32_t k = 0; k < ns; ++k) {
+        Plan pk{};
+        Grid g{};
+        double cs = 0;
+        const sph_status st = validate(&p[k], &sc[k], pk, why, &g, &cs);
+        if (st != SPH_OK) {
+            if (ns > 1) why = "scene " + std::to_string(k) + ": " + why;
+            return st;
+        }
+        if (k > 0) {
+            const sph_params &a = p[0], &b = p[k];
+            if (a.precision != b.precision || a.dt != b.dt || a.v_max != b.v_max ||
+                a.smoothing_window != b.smoothing_window || a.log_steps != b.log_steps ||
+                a.gravity[0] != b.gravity[0] || a.gravity[1] != b.gravity[1] || a.gravity[2] != b.gravity[2]) {
+                why = "the scenes of a batch share precision, dt, gravity, v_max, smoothing_window, log_steps";
+                return SPH_ERR_ARG;
+            }
+        }
+        if (ns > 1 && p[k].max_probes) {
+            why = "density probes are offered for single-scene contexts";
+            return SPH_ERR_UNSUPPORTED;
+        }
+        g.slot0 = (uint32_t)slots;
+        slots += g.nslots;
+        n += pk.n;
+        if (grids) grids->push_back(g);
+        if (csz) csz->push_back(cs);
+        tot.nb += pk.nb;
+        tot.nk += pk.nk;
+        tot.rows += pk.rows;
+        tot.nsp2 += pk.nsp2;
+        tot.nblk_w += pk.nblk_w;
+        tot.max_probes = pk.max_probes;
+    }
+    if (n > (1u << 24) - 1u || slots > (1u << 30)) {
+        why = "batch above 2^24-1 particles or 2^30 cell slots";
+        return SPH_ERR_UNSUPPORTED;
+    }
+    tot.n = (uint32_t)n;
+    tot.nslots = (uint32_t)slots;
+    tot.K = p[0].smoothing_window;
+    tot.nblk_sort = (tot.n + 2047) / 2048;
+    tot.prec = p[0].precision;
+    tot.nscenes = ns;
+    tot.log_steps = p[0].log_steps;
+    pl = tot;
+    if (merged) merge(sc, ns, *merged);
     return SPH_OK;
 }
 
@@ -321,6 +538,7 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
     c->blk_count = cv.take<uint32_t>((size_t)pl.nblk_w * 4);
     c->obj_blk0 = cv.take<uint32_t>((size_t)(pl.nk + 1) * 4);
     c->poses = cv.take<double>((size_t)pl.nk * 16 * 8);
+    c->props = cv.take<double>((size_t)pl.nk * 24 * 8);
     c->ring = cv.take<double>((size_t)pl.nk * pl.K * 6 * 8);
     c->ring_count = cv.take<uint32_t>((size_t)pl.nk * 4);
     c->err = cv.take<uint32_t>(16);
@@ -329,6 +547,9 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
     c->probe_pts = cv.take<double>((size_t)pl.max_probes * 3 * 8);
     c->probe_frame = cv.take<int32_t>((size_t)pl.max_probes * 4);
     c->probe_out = cv.take<double>((size_t)pl.max_probes * 8);
+    c->scene_tab = cv.take<void>((size_t)pl.nscenes * std::max(sizeof(SceneC<float>), sizeof(SceneC<double>)));
+    c->log = cv.take<double>((size_t)pl.log_steps * pl.nk * 20 * 8);
+    c->log_count = cv.take<uint32_t>((size_t)pl.nk * 4);
     *total = cv.off + 256;
 }
 
@@ -356,8 +577,13 @@ BodyArgs body_args(sph_ctx *c)
     b.nk = c->nk;
     b.ring = c->ring;
     b.ring_count = c->ring_count;
+    b.props = c->props;
+    for (int a = 0; a < 3; ++a) b.g[a] = c->prm.gravity[a];
     b.K = c->K;
     b.dt = c->prm.dt;
+    b.log = c->log;
+    b.log_count = c->log_count;
+    b.log_cap = c->log_cap;
     return b;
 }
 
@@ -370,20 +596,33 @@ void prof_mark(sph_ctx *c, int phase, bool begin)
     ++c->prof_used;
 }
 
+template <typename T>
+Batch<T> batch(const sph_ctx *c)
+{
+    return Batch<T>{(const SceneC<T> *)c->scene_tab, c->nscenes, c->nslots};
+}
+
+int key_bits(uint32_t nslots)
+{
+    int b = 0;
+    while (b < 32 && (1ull << b) < nslots) ++b;
+    return b;
+}
+
 // Neighbour search: keys, radix sort, cell table, reorder into the other buffer.
 template <typename T>
 void neighbour_search(sph_ctx *c)
 {
     const uint32_t n = c->n;
     prof_mark(c, 1, true);
-    launch_keys<T>(c->stream, n, (const V4<T> *)c->pos[c->cur], c->grid, c->sort.keys_a);
+    launch_keys<T>(c->stream, n, (const V4<T> *)c->pos[c->cur], batch<T>(c), c->sort.keys_a);
     prof_mark(c, 1, false);
     prof_mark(c, 2, true);
-    launch_radix_sort(c->stream, n, 3 * c->grid.bits, c->sort, &c->sorted_keys, &c->sorted_vals);
+    launch_radix_sort(c->stream, n, key_bits(c->nslots), c->sort, &c->sorted_keys, &c->sorted_vals);
     prof_mark(c, 2, false);
     prof_mark(c, 3, true);
-    launch_clear_u32(c->stream, c->cstart, c->grid.nslots);
-    launch_clear_u32(c->stream, c->cend, c->grid.nslots);
+    launch_clear_u32(c->stream, c->cstart, c->nslots);
+    launch_clear_u32(c->stream, c->cend, c->nslots);
     launch_reorder<T>(c->stream, n, c->sorted_vals, c->sorted_keys, state<T>(c, c->cur), state<T>(c, 1 - c->cur),
                       c->inv_perm, c->cstart, c->cend);
     c->cur = 1 - c->cur;
@@ -412,17 +651,16 @@ void one_step(sph_ctx *c)
     launch_springs<T>(s, sa, c->inv_perm, st, (V4<T> *)c->fspring);
     prof_mark(c, 4, false);
     prof_mark(c, 5, true);
-    launch_density<T>(s, c->n, st, c->grid, phys<T>(c), c->cstart, c->cend, (V2<T> *)c->dens, c->masks, c->err,
-                     c->stats);
+    launch_density<T>(s, c->n, st, batch<T>(c), c->cstart, c->cend, (V2<T> *)c->dens, c->masks, c->err, c->stats);
     prof_mark(c, 5, false);
     prof_mark(c, 6, true);
-    launch_forces<T>(s, c->n, st, c->grid, phys<T>(c), c->cstart, c->cend, (const V2<T> *)c->dens, c->masks,
+    launch_forces<T>(s, c->n, st, batch<T>(c), c->cstart, c->cend, (const V2<T> *)c->dens, c->masks,
                      (const V4<T> *)c->fspring, (V4<T> *)c->force, c->fbody, c->err, c->stats);
     prof_mark(c, 6, false);
     prof_mark(c, 9, true);
     if (c->n_probes) {
         ProbeArgs pa{c->n_probes, c->probe_pts, c->probe_frame, c->poses, c->probe_out};
-        launch_probe<T>(s, pa, st, c->grid, phys<T>(c), c->cstart, c->cend);
+        launch_probe<T>(s, pa, st, batch<T>(c), c->cstart, c->cend);
     }
     prof_mark(c, 9, false);
     prof_mark(c, 7, true);
@@ -459,25 +697,6 @@ void fill_phys(Phys<T> &ph, const sph_params *p)
     ph.flags = p->flags;
 }
 
-void quat_normalise(const double *q, double *out)
-{
-    const double s = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    for (int k = 0; k < 4; ++k) out[k] = q[k] / s;
-}
-
-void quat_to_R(const double *q, double R[9])
-{
-    const double w = q[0], x = q[1], y = q[2], z = q[3];
-    R[0] = 1.0 - 2.0 * (y * y + z * z);
-    R[1] = 2.0 * (x * y - w * z);
-    R[2] = 2.0 * (x * z + w * y);
-    R[3] = 2.0 * (x * y + w * z);
-    R[4] = 1.0 - 2.0 * (x * x + z * z);
-    R[5] = 2.0 * (y * z - w * x);
-    R[6] = 2.0 * (x * z - w * y);
-    R[7] = 2.0 * (y * z + w * x);
-    R[8] = 1.0 - 2.0 * (x * x + y * y);
-}
 
 template <typename T>
 sph_status upload(sph_ctx *c, const sph_scene *s)
@@ -516,11 +735,23 @@ sph_status upload(sph_ctx *c, const sph_scene *s)
     }
     // kinematic bodies: slots ordered by kinematic index then particle id
     std::vector<uint32_t> slot_id, slot_obj, blk_obj, blk_first, blk_count, obj_blk0;
-    std::vector<double> r_loc, poses(16 * (size_t)c->nk, 0.0);
+    std::vector<double> r_loc, poses(16 * (size_t)c->nk, 0.0), props(24 * (size_t)c->nk, 0.0);
     std::vector<uint32_t> slot_of(n, 0);
     for (uint32_t k = 0; k < c->nk; ++k) {
         const uint32_t o = c->kin_objects[k];
-        const double *pz = s->object_pose0 + 7 * o;
+        double pz[7];
+        for (int a = 0; a < 7; ++a) pz[a] = s->object_pose0[7 * o + a];
+        if (c->dynamic[k]) {
+            // free body: the pose reference point is the particles' centre of mass
+            double m = 0, I[9], Ii[9];
+            body_mass_props(s, o, &m, pz, I, Ii);
+            props[24 * k] = m;
+            for (int a = 0; a < 9; ++a) {
+                props[24 * k + 1 + a] = I[a];
+                props[24 * k + 10 + a] = Ii[a];
+            }
+            props[24 * k + kPropFree] = 1.0;
+        }
         double q[4], R[9];
         quat_normalise(pz + 3, q);
         quat_to_R(q, R);
@@ -582,6 +813,7 @@ sph_status upload(sph_ctx *c, const sph_scene *s)
     HIPCHK(c, H2D(c->blk_count, blk_count.data(), blk_count.size() * 4));
     HIPCHK(c, H2D(c->obj_blk0, obj_blk0.data(), obj_blk0.size() * 4));
     HIPCHK(c, H2D(c->poses, poses.data(), poses.size() * 8));
+    HIPCHK(c, H2D(c->props, props.data(), props.size() * 8));
     // zero what must start at zero (fill kernels, no memset nodes)
     launch_clear_u32(st, c->ring_count, c->nk);
     launch_clear_u32(st, c->err, 4);
@@ -590,11 +822,21 @@ sph_status upload(sph_ctx *c, const sph_scene *s)
     launch_clear_u32(st, (uint32_t *)c->force, (size_t)n * 4 * sizeof(T) / 4);
     launch_clear_u32(st, (uint32_t *)c->fspring, (size_t)c->rows * 4 * sizeof(T) / 4);
     launch_clear_u32(st, (uint32_t *)c->fbody, (size_t)c->nb * 6);
+    {
+        std::vector<SceneC<T>> tab(c->nscenes);
+        for (uint32_t k = 0; k < c->nscenes; ++k) {
+            tab[k].g = c->grids[k];
+            fill_phys(tab[k].ph, &c->prms[k]);
+            tab[k].p0 = c->part0[k];
+        }
+        HIPCHK(c, H2D(c->scene_tab, tab.data(), tab.size() * sizeof(SceneC<T>)));
+    }
+    launch_clear_u32(st, c->log_count, c->nk);
     // first neighbour search, then boundary volumes from the initial configuration
     c->cur = 0;
     if (n) {
         neighbour_search<T>(c);
-        launch_psi_obj<T>(st, n, state<T>(c, c->cur), c->grid, phys<T>(c), c->cstart, c->cend, c->obj_of_id);
+        launch_psi_obj<T>(st, n, state<T>(c, c->cur), batch<T>(c), c->cstart, c->cend, c->obj_of_id);
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
@@ -618,6 +860,28 @@ sph_status check_err(sph_ctx *c)
         c->last_error = "non-finite or over-speed particle";
         return SPH_ERR_UNSTABLE;
     }
+    return SPH_OK;
+}
+
+// Capture two steps (one of each buffer parity) into a graph on the context's stream.
+template <typename T>
+sph_status capture_two_steps(sph_ctx *c)
+{
+    hipGraph_t g = nullptr;
+    const uint64_t steps = c->steps;
+    const uint32_t prof = c->prof_left;
+    c->prof_left = 0;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->graph_parity = c->cur;
+    one_step<T>(c);
+    one_step<T>(c);
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->steps = steps;
+    c->prof_left = prof;
+    HIPCHK(c, e);
+    const hipError_t e2 = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(c, e2);
     return SPH_OK;
 }
 
@@ -648,28 +912,35 @@ const char *sph_last_error(const sph_ctx *ctx)
 
 const char *sph_profile_phase_name(uint32_t phase) { return phase < kPhases ? kPhaseNames[phase] : nullptr; }
 
-sph_status sph_workspace_size(const sph_params *params, const sph_scene *scene, size_t *bytes)
+sph_status sph_batch_workspace_size(const sph_params *params, const sph_scene *scenes, uint32_t n_scenes,
+                                    size_t *bytes)
 {
     if (!bytes) return SPH_ERR_ARG;
     Plan pl{};
     std::string why;
-    sph_status st = validate(params, scene, pl, why, nullptr, nullptr);
+    sph_status st = validate_batch(params, scenes, n_scenes, pl, why, nullptr, nullptr, nullptr);
     if (st != SPH_OK) return st;
     sph_ctx tmp;
     carve(&tmp, pl, nullptr, bytes);
     return SPH_OK;
 }
 
-sph_status sph_init(const sph_params *params, const sph_scene *scene, void *d_workspace, size_t ws_bytes,
-                    void *hip_stream, sph_ctx **out)
+sph_status sph_workspace_size(const sph_params *params, const sph_scene *scene, size_t *bytes)
+{
+    return sph_batch_workspace_size(params, scene, 1, bytes);
+}
+
+sph_status sph_batch_init(const sph_params *params, const sph_scene *scenes, uint32_t n_scenes, void *d_workspace,
+                          size_t ws_bytes, void *hip_stream, sph_ctx **out)
 {
     if (!out) return SPH_ERR_ARG;
     *out = nullptr;
     Plan pl{};
     std::string why;
-    Grid g{};
-    double cs = 0;
-    sph_status st = validate(params, scene, pl, why, &g, &cs);
+    std::vector<Grid> grids;
+    std::vector<double> csz;
+    Merged mg;
+    sph_status st = validate_batch(params, scenes, n_scenes, pl, why, &grids, &csz, &mg);
     if (st != SPH_OK) return st;
     size_t need = 0;
     {
@@ -679,8 +950,10 @@ sph_status sph_init(const sph_params *params, const sph_scene *scene, void *d_wo
     if (!d_workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_workspace) & 255u)) return SPH_ERR_WORKSPACE;
     sph_ctx *c = new (std::nothrow) sph_ctx();
     if (!c) return SPH_ERR_DEVICE;
-    c->prm = *params;
-    c->prec = params->precision;
+    const sph_scene *scene = &mg.view;
+    c->prm = params[0];
+    c->prms.assign(params, params + n_scenes);
+    c->prec = params[0].precision;
     c->n = pl.n;
     c->nb = pl.nb;
     c->nk = pl.nk;
@@ -690,14 +963,21 @@ sph_status sph_init(const sph_params *params, const sph_scene *scene, void *d_wo
     c->K = pl.K;
     c->n_objects = scene->n_objects;
     c->max_probes = pl.max_probes;
-    c->grid = g;
-    c->cell_size = cs;
+    c->nscenes = n_scenes;
+    c->nslots = pl.nslots;
+    c->grids = grids;
+    c->part0 = mg.part0;
+    c->grid = grids[0];
+    c->cell_size = csz[0];
+    c->log_cap = pl.log_steps;
     c->stream = (hipStream_t)hip_stream;
     c->kin_of_object.assign(scene->n_objects, -1);
     for (uint32_t o = 0; o < scene->n_objects; ++o)
         if (scene->object_kinematic[o]) {
             c->kin_of_object[o] = (int32_t)c->kin_objects.size();
             c->kin_objects.push_back(o);
+            c->dynamic.push_back(scene->object_kinematic[o] == 2 ? 1 : 0);
+            c->free_now.push_back(scene->object_kinematic[o] == 2 ? 1 : 0);
         }
     for (uint32_t i = 0; i < scene->n; ++i) {
         if (scene->type[i] == SPH_FLUID) ++c->n_fluid;
@@ -715,6 +995,12 @@ sph_status sph_init(const sph_params *params, const sph_scene *scene, void *d_wo
     }
     *out = c;
     return SPH_OK;
+}
+
+sph_status sph_init(const sph_params *params, const sph_scene *scene, void *d_workspace, size_t ws_bytes,
+                    void *hip_stream, sph_ctx **out)
+{
+    return sph_batch_init(params, scene, 1, d_workspace, ws_bytes, hip_stream, out);
 }
 
 sph_status sph_set_body_pose(sph_ctx *ctx, uint32_t object, const double c[3], const double q[4], const double v[3],
@@ -735,6 +1021,80 @@ sph_status sph_set_body_pose(sph_ctx *ctx, uint32_t object, const double c[3], c
     return SPH_OK;
 }
 
+static sph_status set_free(sph_ctx *ctx, uint32_t object, bool free_)
+{
+    if (!ctx) return SPH_ERR_ARG;
+    if (ctx->dead) return SPH_ERR_STATE;
+    if (object >= ctx->n_objects || ctx->kin_of_object[object] < 0) return SPH_ERR_ARG;
+    const uint32_t k = (uint32_t)ctx->kin_of_object[object];
+    if (!ctx->dynamic[k]) {
+        ctx->last_error = "not a free rigid body";
+        return SPH_ERR_ARG;
+    }
+    ctx->free_now[k] = free_ ? 1 : 0;
+    launch_set_double(ctx->stream, ctx->props + 24 * k + kPropFree, free_ ? 1.0 : 0.0);
+    launch_reset_ring(ctx->stream, ctx->ring_count + k);
+    HIPCHK(ctx, hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status sph_grab_body(sph_ctx *ctx, uint32_t object) { return set_free(ctx, object, false); }
+sph_status sph_release_body(sph_ctx *ctx, uint32_t object) { return set_free(ctx, object, true); }
+
+sph_status sph_get_body_state(sph_ctx *ctx, uint32_t object, double c[3], double q[4], double v[3], double w[3])
+{
+    if (!ctx) return SPH_ERR_ARG;
+    if (ctx->dead) return SPH_ERR_STATE;
+    if (!c || !q || !v || !w || object >= ctx->n_objects || ctx->kin_of_object[object] < 0) return SPH_ERR_ARG;
+    double pz[16];
+    HIPCHK(ctx, hipMemcpyAsync(pz, ctx->poses + 16 * ctx->kin_of_object[object], sizeof(pz), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int a = 0; a < 3; ++a) {
+        c[a] = pz[a];
+        v[a] = pz[7 + a];
+        w[a] = pz[10 + a];
+    }
+    for (int a = 0; a < 4; ++a) q[a] = pz[3 + a];
+    return check_err(ctx);
+}
+
+sph_status sph_read_log(sph_ctx *ctx, double *out, size_t n_doubles, uint32_t *n_steps)
+{
+    if (!ctx || !n_steps) return SPH_ERR_ARG;
+    if (ctx->dead) return SPH_ERR_STATE;
+    *n_steps = 0;
+    if (!ctx->log_cap || !ctx->nk) return SPH_OK;
+    uint32_t cnt = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&cnt, ctx->log_count, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const uint32_t m = std::min(cnt, ctx->log_cap);
+    const size_t row = (size_t)ctx->nk * 20;
+    if (m && (!out || n_doubles < m * row)) return SPH_ERR_ARG;
+    // oldest first: ring rows cnt-m .. cnt-1
+    const uint32_t first = (cnt - m) % ctx->log_cap;
+    const uint32_t a = std::min(m, ctx->log_cap - first);
+    if (a)
+        HIPCHK(ctx, hipMemcpyAsync(out, ctx->log + first * row, a * row * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (m > a) HIPCHK(ctx, hipMemcpyAsync(out + a * row, ctx->log, (m - a) * row * 8, hipMemcpyDeviceToHost, ctx->stream));
+    launch_clear_u32(ctx->stream, ctx->log_count, ctx->nk);
+    HIPCHK(ctx, hipGetLastError());
+    *n_steps = m;
+    return check_err(ctx);
+}
+
+sph_status sph_set_graph(sph_ctx *ctx, int enable)
+{
+    if (!ctx) return SPH_ERR_ARG;
+    if (ctx->dead) return SPH_ERR_STATE;
+    if (ctx->graph_exec) {
+        HIPCHK(ctx, hipGraphExecDestroy(ctx->graph_exec));
+        ctx->graph_exec = nullptr;
+    }
+    ctx->graph_on = enable != 0;
+    return SPH_OK;
+}
+
 sph_status sph_step(sph_ctx *ctx, uint32_t n_steps, void *hip_stream)
 {
     if (!ctx) return SPH_ERR_ARG;
@@ -744,11 +1104,31 @@ sph_status sph_step(sph_ctx *ctx, uint32_t n_steps, void *hip_stream)
         ctx->steps += n_steps;
         return SPH_OK;
     }
-    for (uint32_t k = 0; k < n_steps; ++k) {
+    if (ctx->graph_on && !hip_stream) {
+        ctx->last_error = "graph replay needs a non-default stream";
+        return SPH_ERR_ARG;
+    }
+    uint32_t k = 0;
+    while (k < n_steps) {
+        // graph replay: two steps per launch, from the parity the graph was captured at
+        if (ctx->graph_on && !ctx->prof_left && n_steps - k >= 2) {
+            if (!ctx->graph_exec) {
+                const sph_status st =
+                    ctx->prec == SPH_FP64 ? capture_two_steps<double>(ctx) : capture_two_steps<float>(ctx);
+                if (st != SPH_OK) return st;
+            }
+            if (ctx->cur == ctx->graph_parity) {
+                HIPCHK(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+                ctx->steps += 2;
+                k += 2;
+                continue;
+            }
+        }
         if (ctx->prec == SPH_FP64)
             one_step<double>(ctx);
         else
             one_step<float>(ctx);
+        ++k;
     }
     HIPCHK(ctx, hipGetLastError());
     return SPH_OK;
@@ -813,6 +1193,10 @@ sph_status sph_set_probes(sph_ctx *ctx, uint32_t n, const double *points, const 
     }
     // the previous upload may still read the host copies
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->graph_exec) {
+        HIPCHK(ctx, hipGraphExecDestroy(ctx->graph_exec));
+        ctx->graph_exec = nullptr;
+    }
     ctx->probe_host_pts.swap(pts);
     ctx->probe_host_frame.swap(fr);
     if (n) {
@@ -958,7 +1342,7 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t nt, const uint32_t *targets, uint32
 {
     const uint32_t n = c->n;
     hipStream_t s = c->stream;
-    std::vector<uint32_t> ids(n), aux(n), keys(n), cs(c->grid.nslots), ce(c->grid.nslots);
+    std::vector<uint32_t> ids(n), aux(n), keys(n), cs(c->nslots), ce(c->nslots);
     std::vector<uint64_t> masks((size_t)kMaxWords * n);
     if (n) {
         HIPCHK(c, hipMemcpyAsync(ids.data(), c->id[c->cur], (size_t)n * 4, hipMemcpyDeviceToHost, s));
@@ -974,12 +1358,14 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t nt, const uint32_t *targets, uint32
     std::vector<uint8_t> want(n, targets ? 0 : 1);
     if (targets)
         for (uint32_t t = 0; t < nt; ++t) want[targets[t]] = 1;
-    const Grid &g = c->grid;
     for (uint32_t p = 0; p < n; ++p) {
         if (!want[ids[p]]) continue;
         const uint32_t a = aux[p];
         if (aux_type(a) == TY_BOUNDARY && !aux_kin(a)) continue;
-        const uint32_t home = keys[p];
+        uint32_t sc = 0;
+        while (sc + 1 < c->nscenes && c->grids[sc + 1].slot0 <= keys[p]) ++sc;
+        const Grid &g = c->grids[sc];
+        const uint32_t home = keys[p] - g.slot0;
         const int cx = (int)compact3(home), cy = (int)compact3(home >> 1), cz = (int)compact3(home >> 2);
         uint32_t start[27], cnt[27], L = 0;
         for (int k = 0; k < 27; ++k) {
@@ -988,7 +1374,7 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t nt, const uint32_t *targets, uint32
             const int nx = cx + ox, ny = cy + oy, nz = cz + oz;
             uint32_t stt = 0, ct = 0;
             if (nx >= 0 && ny >= 0 && nz >= 0 && nx < g.dims[0] && ny < g.dims[1] && nz < g.dims[2]) {
-                const uint32_t key = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
+                const uint32_t key = g.slot0 + morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
                 stt = cs[key];
                 ct = ce[key] - stt;
             }
@@ -1105,7 +1491,7 @@ sph_status sph_get_info(const sph_ctx *ctx, sph_info *info)
     f.n_kinematic = ctx->nk;
     for (int a = 0; a < 3; ++a) f.grid_dims[a] = (uint32_t)ctx->grid.dims[a];
     f.grid_bits = (uint32_t)ctx->grid.bits;
-    f.cell_slots = ctx->grid.nslots;
+    f.cell_slots = ctx->nslots;
     f.max_candidates = (uint32_t)(kMaxWords * kWave);   // in cell-aligned words
     f.steps = ctx->steps;
     f.cell_size = ctx->cell_size;
@@ -1159,6 +1545,7 @@ sph_status sph_destroy(sph_ctx *ctx)
     if (!ctx) return SPH_OK;
     if (!ctx->dead) (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     delete ctx;
     return SPH_OK;
 }

@@ -86,7 +86,8 @@ struct Grid {
     float R2_32;
     int dims[3];
     int bits;
-    uint32_t nslots;
+    uint32_t nslots;   // 2^(3 bits) key slots of this grid
+    uint32_t slot0;    // first key of this grid in the batch's key space
     double lo64[3];
     double inv_cs64;
     double R2_64;
@@ -206,9 +207,51 @@ __device__ __forceinline__ double kernel_w64(const V4<T> &c, const V4<T> &me, co
     return ph.alpha6_64 * (t2 * t2 * t2 - 4.0 * (t1 * t1 * t1));
 }
 
+// --- batches of independent scenes ---
+// Every context steps a batch of scenes (one scene is a batch of one).  Each
+// scene has its own grid and constants; the key of a particle is the slot0
+// of its scene's grid plus its Morton code, so one sort orders the batch
+// scene-major and the particles of scene s always occupy the sorted indices
+// [p0_s, p0_{s+1}).  Kernels find a work item's scene by binary search.
+template <typename T>
+struct SceneC {
+    Grid g;
+    Phys<T> ph;
+    uint32_t p0;       // first (sorted) particle index of the scene
+    uint32_t pad[3];
+};
+template <typename T>
+struct Batch {
+    const SceneC<T> *sc;   // [n] device table
+    uint32_t n;            // scenes
+    uint32_t nslots;       // key slots of all scenes
+};
+template <typename T>
+__device__ __forceinline__ uint32_t scene_of_particle(const Batch<T> &b, uint32_t i)
+{
+    uint32_t lo = 0, hi = b.n;
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (b.sc[mid].p0 <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+template <typename T>
+__device__ __forceinline__ uint32_t scene_of_slot(const Batch<T> &b, uint32_t k)
+{
+    uint32_t lo = 0, hi = b.n;
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (b.sc[mid].g.slot0 <= k) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // --- launchers (k_grid.hip) ---
 template <typename T>
-void launch_keys(hipStream_t s, uint32_t n, const V4<T> *pos, const Grid &g, uint32_t *keys);
+void launch_keys(hipStream_t s, uint32_t n, const V4<T> *pos, const Batch<T> &b, uint32_t *keys);
 void launch_radix_sort(hipStream_t s, uint32_t n, int key_bits, Sort &st, uint32_t **sorted_keys,
                        uint32_t **sorted_vals);
 void launch_clear_u32(hipStream_t s, uint32_t *p, size_t count);
@@ -216,16 +259,16 @@ template <typename T>
 void launch_reorder(hipStream_t s, uint32_t n, const uint32_t *perm, const uint32_t *keys,
                     State<T> in, State<T> out, uint32_t *inv_perm, uint32_t *cstart, uint32_t *cend);
 template <typename T>
-void launch_psi_obj(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
-                    const uint32_t *cstart, const uint32_t *cend, const int32_t *obj_of_id);
+void launch_psi_obj(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, const uint32_t *cstart,
+                    const uint32_t *cend, const int32_t *obj_of_id);
 
 // --- launchers (k_sums.hip) ---
 template <typename T>
-void launch_density(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
+void launch_density(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b,
                     const uint32_t *cstart, const uint32_t *cend, V2<T> *dens, uint64_t *masks,
                     uint32_t *err, unsigned long long *stats);
 template <typename T>
-void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Grid &g, const Phys<T> &ph,
+void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b,
                    const uint32_t *cstart, const uint32_t *cend, const V2<T> *dens,
                    const uint64_t *masks, const V4<T> *fspring, V4<T> *force, double *fbody,
                    uint32_t *err, unsigned long long *stats);
@@ -248,13 +291,20 @@ struct BodyArgs {
     uint32_t *ring_count;      // [nk] samples pushed (monotone; reset by sph_reset_smoothing)
     uint32_t K;
     double dt;
+    const double *props;       // [24 nk]: mass, I_body[9], I_body^-1[9], free flag (1: integrate), pad
+    double g[3];               // gravity (free bodies)
+    double *log;               // [log_cap][nk][20]: c, q, v, w, F, T, step (or null)
+    uint32_t *log_count;       // [nk] rows written
+    uint32_t log_cap;
 };
+constexpr int kPropFree = 19;
 template <typename T>
 void launch_place(hipStream_t s, const BodyArgs &b, const uint32_t *inv_perm, State<T> st);
 void launch_wrench(hipStream_t s, const BodyArgs &b);
 void launch_set_pose(hipStream_t s, double *pose_slot, const double c[3], const double q[4],
                      const double v[3], const double w[3]);
 void launch_reset_ring(hipStream_t s, uint32_t *ring_count_slot);
+void launch_set_double(hipStream_t s, double *slot, double v);
 
 struct ProbeArgs {
     uint32_t n;
@@ -264,7 +314,7 @@ struct ProbeArgs {
     double *out;             // [n]
 };
 template <typename T>
-void launch_probe(hipStream_t s, const ProbeArgs &a, State<T> st, const Grid &g, const Phys<T> &ph,
+void launch_probe(hipStream_t s, const ProbeArgs &a, State<T> st, const Batch<T> &b,
                   const uint32_t *cstart, const uint32_t *cend);
 
 struct SpringArgs {

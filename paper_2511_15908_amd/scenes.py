@@ -394,6 +394,67 @@ def haptic_scene(seed: int = 5, n_fluid: int = 100_000, precision: str = "f32") 
                      kin=[0, 1], poses=poses, info=info)
 
 
+def stirring_batch(seed: int = 4, n_scenes: int = 256, n_min: int = 2000, n_max: int = 30000,
+                   precision: str = "f32"):
+    """Independent stirring tanks for batched data generation: fluid counts
+    N_k = floor(exp(U(ln n_min, ln n_max))); scene k is the stirring tank
+    (1 x 0.5 m footprint, fluid ~0.5 m deep, 0.6 m walls) at spacing
+    s_k = 0.5 / n_y, n_y = round((N_k / 2)^(1/3)), h_k = 2 s_k, with a paddle
+    of the same physical size (0.04 x 0.25 x 0.40 m) as a solid lattice block
+    at s_k; dt = 5e-4 s.  Each paddle follows its own band-limited path
+    (batch_pose): four sinusoids, frequencies U(0.2, 3] Hz, amplitudes
+    summing to 0.075 m, so the excursion stays within 0.15 m."""
+    rng = SplitMix64(seed, P_BATCH)
+    u = rng.uniform(n_scenes)
+    counts = np.floor(np.exp(math.log(n_min) + u * (math.log(n_max) - math.log(n_min)))).astype(int)
+    out = []
+    for k, nf in enumerate(counts):
+        ny = max(4, int(round((nf / 2.0) ** (1.0 / 3.0))))
+        s = 0.5 / ny
+        h, dt = 2.0 * s, 5e-4
+        g = WALL_GAP
+        nx = 2 * ny
+        Wx, Wy = tank_width(nx, s), tank_width(ny, s)
+        nz = int(math.ceil(0.6 / s))
+        tank = open_tank(Wx, Wy, nz, s)
+        pi = max(1, int(round(0.04 / s)))
+        pj = max(1, int(round(0.25 / s)))
+        pk = max(1, int(round(0.40 / s)))
+        i0 = nx // 2 - pi // 2
+        j0 = (ny - pj) // 2 + 1
+        k0 = max(1, int(round(0.06 / s)))
+        pad = (_grid(i0, i0 + pi - 1, j0, j0 + pj - 1, k0, k0 + pk - 1).astype(np.float64) + (g - 1.0)) * s
+        fl = (fill_to_count(int(nf), (1, nx), (1, ny), s, set(), clearance(pad, OBSTACLE_CLEARANCE * s), gap=g)
+              .astype(np.float64) + (g - 1.0)) * s
+        c0 = pad.mean(0)
+        lo = (-0.5 * s, -0.5 * s, -0.5 * s)
+        hi = (Wx + 1.5 * s, Wy + 1.5 * s, (nz + 5) * s)
+        params = _params(h, dt, lo, hi, precision, nu=viscosity_for(h), flags=1)
+        r = SplitMix64(seed * 7919 + k, P_PHASE).uniform(12)
+        freqs = 0.2 + 2.8 * r[0:4]
+        w = r[4:8] + 0.05
+        amps = 0.075 * w / w.sum()
+        phases = 2.0 * math.pi * r[8:12]
+        poses = [[0, 0, 0, 1, 0, 0, 0], list(c0) + [1, 0, 0, 0]]
+        m = 1000.0 * s ** 3
+        out.append(_assemble(f"batch_{k}_{int(nf)}", precision, params, s,
+                             [(fl, FLUID, -1, m), (tank, BOUNDARY, 0, 0.0), (pad, BOUNDARY, 1, 0.0)],
+                             kin=[0, 1], poses=poses,
+                             info={"body": 1, "c0": c0, "freqs": freqs, "amps": amps, "phases": phases}))
+    return out
+
+
+def batch_pose(scene: Scene, t: float):
+    """Pose of a batch scene's paddle at time t: x = x0 + sum_m a_m
+    [sin(2 pi f_m t + phi_m) - sin phi_m], no rotation."""
+    f, a, ph = scene.info["freqs"], scene.info["amps"], scene.info["phases"]
+    c = np.asarray(scene.info["c0"], np.float64).copy()
+    c[0] += float(np.sum(a * (np.sin(2 * math.pi * f * t + ph) - np.sin(ph))))
+    v = np.zeros(3)
+    v[0] = float(np.sum(a * 2 * math.pi * f * np.cos(2 * math.pi * f * t + ph)))
+    return c, np.array([1.0, 0, 0, 0]), v, np.zeros(3)
+
+
 def small_scene(seed: int = 11, nf=(14, 9, 8), precision: str = "f32", with_soft=True,
                 with_body=True, perturb=True, n_tank=(24, 14, 16), spacing=0.02) -> Scene:
     """A small coupled scene for parity tests: a tank, a fluid block of
