@@ -91,7 +91,8 @@ typedef struct {
     double v_max;              /* |v| above this flags SPH_ERR_UNSTABLE; 0 = only non-finite */
     uint32_t max_probes;       /* capacity of density probe points (sph_set_probes), <= 2^20; 0 = none */
     uint32_t log_steps;        /* capacity of the per-step body log (sph_read_log), steps; 0 = none */
-    uint32_t reserved[6];      /* must be zero */
+    uint32_t track_steps;      /* capacity of each body's pose track (sph_set_body_track); 0 = none */
+    uint32_t reserved[5];      /* must be zero */
 } sph_params;
 
 typedef struct {               /* caller-owned host arrays, read only during sph_init */
@@ -208,6 +209,17 @@ sph_status sph_read_log(sph_ctx *ctx, double *out, size_t n_doubles, uint32_t *n
  * set or disabling drops the graph.  Profiling steps run without the graph.
  */
 sph_status sph_set_graph(sph_ctx *ctx, int enable);
+
+/*
+ * Pose track of a kinematic (or grabbed) body: poses[k] = c[3], q[4], v[3],
+ * w[3] for the k-th step from the next one on (n <= track_steps); the body
+ * takes them one per step on the device (no host work per step, e.g. under
+ * graph replay) and extrapolates from the last.  sph_set_body_pose ends a
+ * track.  SPH_ERR_ARG for a static body, a free (released) body, n above the
+ * capacity, a zero or non-finite entry.  The host array is copied; the call
+ * synchronises.
+ */
+sph_status sph_set_body_track(sph_ctx *ctx, uint32_t object, uint32_t n, const double *poses);
 
 /* Enqueue n_steps full steps on hip_stream (no host synchronisation). */
 sph_status sph_step(sph_ctx *ctx, uint32_t n_steps, void *hip_stream);

@@ -34,7 +34,7 @@ EXPORTED = ["sph_workspace_size", "sph_init", "sph_set_body_pose", "sph_step", "
             "sph_get_stats", "sph_get_info",
             "sph_synchronize", "sph_profile_begin", "sph_profile_read", "sph_profile_phase_name",
             "sph_set_probes", "sph_read_probes", "sph_grab_body", "sph_release_body", "sph_get_body_state",
-            "sph_batch_workspace_size", "sph_batch_init", "sph_read_log", "sph_set_graph",
+            "sph_batch_workspace_size", "sph_batch_init", "sph_read_log", "sph_set_graph", "sph_set_body_track",
             "sph_destroy", "sph_status_string", "sph_last_error"]
 
 
@@ -50,7 +50,7 @@ class SphParams(C.Structure):
                 ("k_pressure", C.c_double), ("nu", C.c_double), ("gravity", C.c_double * 3),
                 ("dt", C.c_double), ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
                 ("v_max", C.c_double), ("max_probes", C.c_uint32), ("log_steps", C.c_uint32),
-                ("reserved", C.c_uint32 * 6)]
+                ("track_steps", C.c_uint32), ("reserved", C.c_uint32 * 5)]
 
 
 class SphScene(C.Structure):
@@ -110,6 +110,7 @@ def load_library(path=None):
     L.sph_batch_init.argtypes = [C.POINTER(SphParams), C.POINTER(SphScene), C.c_uint32, vp, sz, vp, C.POINTER(vp)]
     L.sph_read_log.argtypes = [vp, d3, sz, C.POINTER(C.c_uint32)]
     L.sph_set_graph.argtypes = [vp, C.c_int]
+    L.sph_set_body_track.argtypes = [vp, C.c_uint32, C.c_uint32, d3]
     L.sph_release_body.argtypes = [vp, C.c_uint32]
     L.sph_get_body_state.argtypes = [vp, C.c_uint32, d3, d3, d3, d3]
     L.sph_destroy.argtypes = [vp]
@@ -130,7 +131,7 @@ def _dp(a):
 
 
 def make_params(params: dict, precision: str, v_max: float = 0.0, max_probes: int = 0,
-                log_steps: int = 0) -> SphParams:
+                log_steps: int = 0, track_steps: int = 0) -> SphParams:
     P = SphParams()
     P.abi_version = SPH_ABI_VERSION
     P.precision = SPH_FP64 if precision == "f64" else SPH_FP32
@@ -144,6 +145,7 @@ def make_params(params: dict, precision: str, v_max: float = 0.0, max_probes: in
     P.v_max = float(v_max)
     P.max_probes = int(max_probes)
     P.log_steps = int(log_steps)
+    P.track_steps = int(track_steps)
     return P
 
 
@@ -199,7 +201,7 @@ class Sim:
     """
 
     def __init__(self, scene, precision=None, device="cuda", stream=None, v_max=0.0, params=None, max_probes=0,
-                 log_steps=0):
+                 log_steps=0, track_steps=0):
         import torch
         self.torch = torch
         self.L = load_library()
@@ -215,7 +217,7 @@ class Sim:
             pr = dict(sc.params)
             if params:
                 pr.update(params)
-            self.P[k] = make_params(pr, self.precision, v_max, max_probes, log_steps)
+            self.P[k] = make_params(pr, self.precision, v_max, max_probes, log_steps, track_steps)
             S[k] = self._arrays[k].struct
         out = C.c_size_t(0)
         st = self.L.sph_batch_workspace_size(self.P, S, ns, C.byref(out))
@@ -263,6 +265,11 @@ class Sim:
         if check:
             self._check(st, "sph_get_body_wrench")
         return F, T
+
+    def set_body_track(self, obj, poses):
+        """poses: [n][13] (c, q, v, w) for the next n steps, taken on the device."""
+        p = np.ascontiguousarray(poses, np.float64).reshape(-1, 13)
+        self._check(self.L.sph_set_body_track(self.ctx, int(obj), p.shape[0], _dp(p)), "sph_set_body_track")
 
     def set_graph(self, enable=True):
         """Replay steps as a captured two-step HIP graph (non-default stream)."""

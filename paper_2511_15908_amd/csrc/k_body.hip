@@ -161,6 +161,14 @@ __global__ __launch_bounds__(64) void k_wrench_final(BodyArgs b)
                 pz[10 + a] = pz[10 + a] + dt * (Iwi[3 * a] * r0 + Iwi[3 * a + 1] * r1 + Iwi[3 * a + 2] * r2);
             }
         }
+        if (b.track && b.track_pos[2u * o] < b.track_pos[2u * o + 1u]) {
+            // next pose of the body's track
+            const uint32_t k = b.track_pos[2u * o];
+            const double *tp = b.track + ((size_t)o * b.track_cap + k) * 16u;
+            for (int a = 0; a < 13; ++a) pz[a] = tp[a];
+            b.track_pos[2u * o] = k + 1u;
+            return;
+        }
         // pose advance: c += v dt, q <- normalise(q + dt/2 (0, w) q)
         for (int a = 0; a < 3; ++a) pz[a] = pz[a] + pz[7 + a] * dt;
         const double qw = pz[3], qx = pz[4], qy = pz[5], qz = pz[6];
@@ -225,6 +233,19 @@ __global__ void k_set_double(double *__restrict__ slot, double v)
 void launch_set_double(hipStream_t s, double *slot, double v)
 {
     hipLaunchKernelGGL(k_set_double, dim3(1), dim3(64), 0, s, slot, v);
+}
+
+__global__ void k_set_u32x2(uint32_t *__restrict__ slot, uint32_t a, uint32_t b)
+{
+    if (threadIdx.x == 0) {
+        slot[0] = a;
+        slot[1] = b;
+    }
+}
+
+void launch_set_u32x2(hipStream_t s, uint32_t *slot, uint32_t a, uint32_t b)
+{
+    hipLaunchKernelGGL(k_set_u32x2, dim3(1), dim3(64), 0, s, slot, a, b);
 }
 
 // ------------------------------------------------------------------ density probes

@@ -55,6 +55,10 @@ struct sph_ctx {
     uint32_t log_cap = 0;
     double *log = nullptr;
     uint32_t *log_count = nullptr;
+    uint32_t track_cap = 0;
+    double *track = nullptr;
+    uint32_t *track_pos = nullptr;
+    std::vector<uint8_t> track_on;        // kinematic index -> a track may be active
     // graph replay of two steps
     bool graph_on = false;
     hipGraphExec_t graph_exec = nullptr;
@@ -190,7 +194,7 @@ bool body_mass_props(const sph_scene *s, uint32_t o, double *m_out, double com[3
 }
 
 struct Plan {
-    uint32_t n, nb, nk, rows, nsp2, nblk_w, nslots, K, nblk_sort, max_probes, nscenes, log_steps;
+    uint32_t n, nb, nk, rows, nsp2, nblk_w, nslots, K, nblk_sort, max_probes, nscenes, log_steps, track_steps;
     int prec;
 };
 
@@ -380,6 +384,7 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
     pl.max_probes = p->max_probes;
     pl.nscenes = 1;
     pl.log_steps = p->log_steps;
+    pl.track_steps = p->track_steps;
     return SPH_OK;
 }
 
@@ -462,6 +467,7 @@ sph_status validate_batch(const sph_params *p, const sph_scene *sc, uint32_t ns,
             const sph_params &a = p[0], &b = p[k];
             if (a.precision != b.precision || a.dt != b.dt || a.v_max != b.v_max ||
                 a.smoothing_window != b.smoothing_window || a.log_steps != b.log_steps ||
+                a.track_steps != b.track_steps ||
                 a.gravity[0] != b.gravity[0] || a.gravity[1] != b.gravity[1] || a.gravity[2] != b.gravity[2]) {
                 why = "the scenes of a batch share precision, dt, gravity, v_max, smoothing_window, log_steps";
                 return SPH_ERR_ARG;
@@ -494,6 +500,11 @@ sph_status validate_batch(const sph_params *p, const sph_scene *sc, uint32_t ns,
     tot.prec = p[0].precision;
     tot.nscenes = ns;
     tot.log_steps = p[0].log_steps;
+    tot.track_steps = p[0].track_steps;
+    if ((uint64_t)tot.track_steps * tot.nk * 128 > (1ull << 36)) {
+        why = "track_steps too large";
+        return SPH_ERR_ARG;
+    }
     pl = tot;
     if (merged) merge(sc, ns, *merged);
     return SPH_OK;
@@ -550,6 +561,8 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
     c->scene_tab = cv.take<void>((size_t)pl.nscenes * std::max(sizeof(SceneC<float>), sizeof(SceneC<double>)));
     c->log = cv.take<double>((size_t)pl.log_steps * pl.nk * 20 * 8);
     c->log_count = cv.take<uint32_t>((size_t)pl.nk * 4);
+    c->track = cv.take<double>((size_t)pl.track_steps * pl.nk * 16 * 8);
+    c->track_pos = cv.take<uint32_t>((size_t)pl.nk * 2 * 4);
     *total = cv.off + 256;
 }
 
@@ -584,6 +597,9 @@ BodyArgs body_args(sph_ctx *c)
     b.log = c->log;
     b.log_count = c->log_count;
     b.log_cap = c->log_cap;
+    b.track = c->track_cap ? c->track : nullptr;
+    b.track_pos = c->track_pos;
+    b.track_cap = c->track_cap;
     return b;
 }
 
@@ -832,6 +848,7 @@ sph_status upload(sph_ctx *c, const sph_scene *s)
         HIPCHK(c, H2D(c->scene_tab, tab.data(), tab.size() * sizeof(SceneC<T>)));
     }
     launch_clear_u32(st, c->log_count, c->nk);
+    launch_clear_u32(st, c->track_pos, 2 * (size_t)c->nk);
     // first neighbour search, then boundary volumes from the initial configuration
     c->cur = 0;
     if (n) {
@@ -970,6 +987,7 @@ sph_status sph_batch_init(const sph_params *params, const sph_scene *scenes, uin
     c->grid = grids[0];
     c->cell_size = csz[0];
     c->log_cap = pl.log_steps;
+    c->track_cap = pl.track_steps;
     c->stream = (hipStream_t)hip_stream;
     c->kin_of_object.assign(scene->n_objects, -1);
     for (uint32_t o = 0; o < scene->n_objects; ++o)
@@ -978,6 +996,7 @@ sph_status sph_batch_init(const sph_params *params, const sph_scene *scenes, uin
             c->kin_objects.push_back(o);
             c->dynamic.push_back(scene->object_kinematic[o] == 2 ? 1 : 0);
             c->free_now.push_back(scene->object_kinematic[o] == 2 ? 1 : 0);
+            c->track_on.push_back(0);
         }
     for (uint32_t i = 0; i < scene->n; ++i) {
         if (scene->type[i] == SPH_FLUID) ++c->n_fluid;
@@ -1016,8 +1035,45 @@ sph_status sph_set_body_pose(sph_ctx *ctx, uint32_t object, const double c[3], c
     if (!(qn > 0)) return SPH_ERR_ARG;
     double qq[4];
     quat_normalise(q, qq);
-    launch_set_pose(ctx->stream, ctx->poses + 16 * ctx->kin_of_object[object], c, qq, v, w);
+    const uint32_t k = (uint32_t)ctx->kin_of_object[object];
+    if (ctx->track_on[k]) {
+        launch_set_u32x2(ctx->stream, ctx->track_pos + 2 * k, 0u, 0u);
+        ctx->track_on[k] = 0;
+    }
+    launch_set_pose(ctx->stream, ctx->poses + 16 * k, c, qq, v, w);
     HIPCHK(ctx, hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status sph_set_body_track(sph_ctx *ctx, uint32_t object, uint32_t n, const double *poses)
+{
+    if (!ctx) return SPH_ERR_ARG;
+    if (ctx->dead) return SPH_ERR_STATE;
+    if (object >= ctx->n_objects || ctx->kin_of_object[object] < 0 || n < 1 || n > ctx->track_cap || !poses)
+        return SPH_ERR_ARG;
+    const uint32_t k = (uint32_t)ctx->kin_of_object[object];
+    if (ctx->dynamic[k] && ctx->free_now[k]) {
+        ctx->last_error = "a free body moves under its wrench; grab it first";
+        return SPH_ERR_ARG;
+    }
+    std::vector<double> t(16 * (size_t)n, 0.0);
+    for (uint32_t e = 0; e < n; ++e) {
+        const double *p = poses + 13 * (size_t)e;
+        for (int a = 0; a < 13; ++a)
+            if (!isfinite(p[a])) return SPH_ERR_ARG;
+        const double qn = p[3] * p[3] + p[4] * p[4] + p[5] * p[5] + p[6] * p[6];
+        if (!(qn > 0)) return SPH_ERR_ARG;
+        double *d = t.data() + 16 * (size_t)e;
+        for (int a = 0; a < 13; ++a) d[a] = p[a];
+        quat_normalise(p + 3, d + 3);
+    }
+    double *dst = ctx->track + (size_t)k * ctx->track_cap * 16;
+    HIPCHK(ctx, hipMemcpyAsync(dst, t.data(), t.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+    launch_set_pose(ctx->stream, ctx->poses + 16 * k, t.data(), t.data() + 3, t.data() + 7, t.data() + 10);
+    launch_set_u32x2(ctx->stream, ctx->track_pos + 2 * k, 1u, n);
+    ctx->track_on[k] = 1;
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return SPH_OK;
 }
 
@@ -1032,6 +1088,10 @@ static sph_status set_free(sph_ctx *ctx, uint32_t object, bool free_)
         return SPH_ERR_ARG;
     }
     ctx->free_now[k] = free_ ? 1 : 0;
+    if (free_ && ctx->track_on[k]) {
+        launch_set_u32x2(ctx->stream, ctx->track_pos + 2 * k, 0u, 0u);
+        ctx->track_on[k] = 0;
+    }
     launch_set_double(ctx->stream, ctx->props + 24 * k + kPropFree, free_ ? 1.0 : 0.0);
     launch_reset_ring(ctx->stream, ctx->ring_count + k);
     HIPCHK(ctx, hipGetLastError());

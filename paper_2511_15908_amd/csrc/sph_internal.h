@@ -296,6 +296,9 @@ struct BodyArgs {
     double *log;               // [log_cap][nk][20]: c, q, v, w, F, T, step (or null)
     uint32_t *log_count;       // [nk] rows written
     uint32_t log_cap;
+    const double *track;       // [nk][track_cap][16]: c, q, v, w per step (or null)
+    uint32_t *track_pos;       // [2 nk]: next entry, entries
+    uint32_t track_cap;
 };
 constexpr int kPropFree = 19;
 template <typename T>
@@ -305,6 +308,7 @@ void launch_set_pose(hipStream_t s, double *pose_slot, const double c[3], const 
                      const double v[3], const double w[3]);
 void launch_reset_ring(hipStream_t s, uint32_t *ring_count_slot);
 void launch_set_double(hipStream_t s, double *slot, double v);
+void launch_set_u32x2(hipStream_t s, uint32_t *slot, uint32_t a, uint32_t b);
 
 struct ProbeArgs {
     uint32_t n;

@@ -133,35 +133,68 @@ def test_body_log(gpu):
     assert sim.read_log().shape[0] == 0
 
 
+def _track(sc, n, dt):
+    from paper_2511_15908_amd import scenes
+    return np.array([np.concatenate(scenes.batch_pose(sc, k * dt)) for k in range(n)])
+
+
+def test_body_track_equals_per_step_poses(gpu):
+    """A pose track taken on the device equals the same poses set before
+    every step from the host, bitwise; after the track the pose
+    extrapolates."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.stirring_batch(seed=6, n_scenes=1, n_min=3000, n_max=3000)[0]
+    dt = sc.params["dt"]
+    tr = _track(sc, 6, dt)
+    a = gpu.Sim(sc)
+    b = gpu.Sim(sc, track_steps=8)
+    b.set_body_track(1, tr)
+    for k in range(6):
+        a.set_body_pose(1, tr[k, :3], tr[k, 3:7], tr[k, 7:10], tr[k, 10:13])
+        a.step(1)
+    b.step(6)
+    assert np.array_equal(a.read("x"), b.read("x")) and np.array_equal(a.read("f"), b.read("f"))
+    a.step(3)
+    b.step(3)
+    assert np.array_equal(a.read("x"), b.read("x"))
+    with pytest.raises(gpu.SphError):
+        b.set_body_track(1, np.zeros((9, 13)))       # above the capacity
+    with pytest.raises(gpu.SphError):
+        b.set_body_track(0, tr[:2])                  # static tank
+
+
 def test_stirring_batch_256(gpu):
     """The 256-scene batch (log-uniform 2k-30k fluid each, 3.4M particles):
-    graph replays with per-step paddle poses and the body log; two of its
-    scenes checked bitwise against their own contexts."""
+    paddle paths as device pose tracks, graph replays with no host work per
+    step, the body log; two of its scenes checked bitwise against their own
+    contexts."""
     import time
     import torch
     from paper_2511_15908_amd import scenes
     scs = scenes.stirring_batch(seed=4, n_scenes=256)
     st = torch.cuda.Stream()
-    sim = gpu.Sim(scs, stream=st, log_steps=64)
+    n = 64
+    sim = gpu.Sim(scs, stream=st, log_steps=n, track_steps=n)
     sim.set_graph(True)
-    pick = [3, 200]
-    singles = {i: gpu.Sim(scs[i], stream=st) for i in pick}
     dt = scs[0].params["dt"]
+    pick = [3, 200]
+    singles = {i: gpu.Sim(scs[i], stream=st, track_steps=n) for i in pick}
+    for i, sc in enumerate(scs):
+        sim.set_body_track(int(sim.obj0[i]) + 1, _track(sc, n, dt))
+    for i in pick:
+        singles[i].set_body_track(1, _track(scs[i], n, dt))
+        singles[i].step(n)
+    sim.step(2)
+    sim.synchronize()
     t0 = time.perf_counter()
-    for k in range(16):
-        for i, sc in enumerate(scs):
-            sim.set_body_pose(int(sim.obj0[i]) + 1, *scenes.batch_pose(sc, k * 2 * dt))
-        for i in pick:
-            singles[i].set_body_pose(1, *scenes.batch_pose(scs[i], k * 2 * dt))
-            singles[i].step(2)
-        sim.step(2)
+    sim.step(n - 2)
     sim.synchronize()
     el = time.perf_counter() - t0
-    n_upd = sum(sc.counts()["fluid"] for sc in scs) * 32
-    print(f"256 scenes, {sum(sc.n for sc in scs)} particles: 32 steps in {el:.2f} s "
-          f"({n_upd / el / 1e6:.0f} M fluid particle-updates/s, incl. 8192 pose calls)")
+    n_upd = sum(sc.counts()["fluid"] for sc in scs) * (n - 2)
+    print(f"256 scenes, {sum(sc.n for sc in scs)} particles: {n - 2} graph-replayed steps in {el:.3f} s "
+          f"({el / (n - 2) * 1e3:.2f} ms/step, {n_upd / el / 1e6:.0f} M fluid particle-updates/s)")
     log = sim.read_log()
-    assert log.shape == (32, 256, 20) and np.all(np.isfinite(log))
+    assert log.shape == (n, 256, 20) and np.all(np.isfinite(log))
     x = sim.read("x")
     for i in pick:
         assert np.array_equal(x[sim.part0[i]:sim.part0[i + 1]], singles[i].read("x"))
