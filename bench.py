@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--workload", default="coupled_1m")
     ap.add_argument("--n-fluid", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 256-scene batch leg (graph-replayed steps of independent stirring tanks)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the haptic-rate surrogate leg (100k haptic scene: logs, training, evaluation)")
     ap.add_argument("--quiet", action="store_true")
@@ -102,6 +104,36 @@ def profiled_traffic(kernel):
     if rec.get("source_sha256_k_sums") != sha or kernel not in rec.get("kernels", {}):
         return None
     return rec["kernels"][kernel]["bytes"]
+
+
+def batch_leg(dev, n_scenes=256, steps=64):
+    """The batched data-generation workload: independent stirring tanks in one
+    context (one launch per kernel for all scenes), paddles on device pose
+    tracks, two-step graph replays, per-step body log."""
+    import torch
+    import paper_2511_15908_amd as P
+    from paper_2511_15908_amd import scenes
+    scs = scenes.stirring_batch(seed=4, n_scenes=n_scenes)
+    st = torch.cuda.Stream(device=dev)
+    sim = P.Sim(scs, device=dev, stream=st, log_steps=steps + 2, track_steps=steps + 2)
+    sim.set_graph(True)
+    dt = scs[0].params["dt"]
+    for i, sc in enumerate(scs):
+        tr = np.array([np.concatenate(scenes.batch_pose(sc, k * dt)) for k in range(steps + 2)])
+        sim.set_body_track(int(sim.obj0[i]) + 1, tr)
+    sim.step(2)
+    sim.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    el = time.perf_counter() - t0
+    log = sim.read_log()
+    nf = sum(sc.counts()["fluid"] for sc in scs)
+    return {"workload": f"{n_scenes} independent stirring tanks, 2k-30k fluid each (log-uniform), "
+                        f"{sum(sc.n for sc in scs):,} particles, dt = 5e-4 s",
+            "steps": steps, "ms_per_step": 1e3 * el / steps, "fluid_updates_per_s": nf * steps / el,
+            "particle_updates_per_s": sum(sc.n for sc in scs) * steps / el,
+            "log_records": int(log.shape[0] * log.shape[1])}
 
 
 def main():
@@ -206,6 +238,9 @@ def main():
                     "over64": int((cnt > 64).sum()),
                     "passes_per_target": float(np.ceil(cnt / 64).sum() * 64 / cnt.sum())}
     del sim
+    if not a.no_batch:
+        log("batch leg: 256 stirring tanks (2k-30k fluid each), pose tracks, graph replay ...", a.quiet)
+        out["batch"] = batch_leg(dev)
     if not a.no_surrogate:
         from paper_2511_15908_amd import surrogate as S
         log("surrogate leg: plain-SPH haptic logs of the 100k haptic scene, training, evaluation ...", a.quiet)
