@@ -136,6 +136,59 @@ __device__ __forceinline__ uint32_t chunk_index(const Nbhd &nb, uint32_t s, uint
     return nb.start[k] + s + nb.stride * (v - nb.pre[k]);
 }
 
+// Bounding box of the home cell's particles (lanes stride over them; the
+// same box for every pass over the cell and in both passes of the step).
+template <typename T>
+__device__ __forceinline__ void cell_box(const V4<T> *__restrict__ pos, uint32_t s0, uint32_t e0, uint32_t lane,
+                                         T lo[3], T hi[3])
+{
+    const T inf = __builtin_huge_val();
+    T l0 = inf, l1 = inf, l2 = inf, h0 = -inf, h1 = -inf, h2 = -inf;
+    for (uint32_t j = s0 + lane; j < e0; j += kWave) {
+        const V4<T> c = pos[j];
+        l0 = fmin(l0, c.x);
+        l1 = fmin(l1, c.y);
+        l2 = fmin(l2, c.z);
+        h0 = fmax(h0, c.x);
+        h1 = fmax(h1, c.y);
+        h2 = fmax(h2, c.z);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        l0 = fmin(l0, __shfl_xor(l0, m, 64));
+        l1 = fmin(l1, __shfl_xor(l1, m, 64));
+        l2 = fmin(l2, __shfl_xor(l2, m, 64));
+        h0 = fmax(h0, __shfl_xor(h0, m, 64));
+        h1 = fmax(h1, __shfl_xor(h1, m, 64));
+        h2 = fmax(h2, __shfl_xor(h2, m, 64));
+    }
+    lo[0] = l0;
+    lo[1] = l1;
+    lo[2] = l2;
+    hi[0] = h0;
+    hi[1] = h1;
+    hi[2] = h2;
+}
+
+// A candidate farther than the support from every point of the box cannot
+// be a neighbour of any particle in it.  The test is conservative: squared
+// distance to the box in T against the squared support enlarged by 2^-8, so
+// rounding never drops a pair the canonical predicate accepts.
+template <typename T>
+__device__ __forceinline__ bool near_box(const V4<T> &c, const T lo[3], const T hi[3], T R2)
+{
+#pragma clang fp contract(off)
+    const T dx = fmax(fmax(lo[0] - c.x, c.x - hi[0]), (T)0);
+    const T dy = fmax(fmax(lo[1] - c.y, c.y - hi[1]), (T)0);
+    const T dz = fmax(fmax(lo[2] - c.z, c.z - hi[2]), (T)0);
+    return dx * dx + dy * dy + dz * dz < R2 * (T)1.00390625;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m, uint32_t lane)
+{
+    return (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
 // Hit bits of this lane's particle against nv (<= 32) staged candidates;
 // nv is uniform, so empty slots of a super-chunk are never tested.
 template <typename T>
@@ -221,6 +274,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
     const uint32_t S = nb.stride;
     const T R2 = grid_R2<T>(g);
     const T inf = __builtin_huge_val();
+    T blo[3], bhi[3];
+    cell_box<T>(st.pos, s0, e0, lane, blo, bhi);
     const uint32_t ncell = e0 - s0, rem = ncell % kWave;
     const bool use_left = ncell > (uint32_t)kWave && rem != 0u && rem <= kLeftD;
     const uint32_t nlane = use_left ? ncell / kWave : (ncell + kWave - 1) / kWave;
@@ -246,18 +301,24 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         uint32_t npair = 0, witer = 0, ncand = 0, nleftpair_d = 0, nleftpair_f = 0;
         for (uint32_t sc = 0; sc < S; ++sc) {
             begin_chunk(nb, sc, lane);
-            const uint32_t size = nb.size;
-            ncand += size;
+            // stage the super-chunk's candidates near the cell's box, compacted
+            uint32_t size = 0;
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) {
                 const uint32_t v = q * kWave + lane;
-                const bool in = v < size;
-                V4<T> c = st.pos[in ? chunk_index(nb, sc, v) : s0];
-                c.x = in ? c.x : inf;
-                c.y = in ? c.y : inf;
-                c.z = in ? c.z : inf;
-                cand[v] = c;
+                const bool in = v < nb.size;
+                const V4<T> c = st.pos[in ? chunk_index(nb, sc, v) : s0];
+                const bool keep = in && near_box<T>(c, blo, bhi, R2);
+                const uint64_t km = __ballot(keep);
+                if (keep) cand[size + lanes_below(km, lane)] = c;
+                size += (uint32_t)__popcll(km);
             }
+#pragma unroll
+            for (int q = 0; q < kScWords; ++q) {
+                const uint32_t v = q * kWave + lane;
+                if (v >= size) cand[v] = V4<T>{inf, inf, inf, (T)0};
+            }
+            ncand += size;
             __syncthreads();
             const uint32_t nws = nb.wbase[sc + 1] - nb.wbase[sc];
             const uint32_t w0 = nb.wbase[sc];
@@ -266,7 +327,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                 for (int q = 0; q < kScWords; ++q) {
                     uint64_t m = 0;
                     if ((uint32_t)q < nws) {
-                        const uint32_t nv = min(size - (uint32_t)q * kWave, (uint32_t)kWave);
+                        const uint32_t nv = size > (uint32_t)q * kWave ? min(size - (uint32_t)q * kWave, (uint32_t)kWave) : 0u;
                         m = hit_word<T>(me, cand + q * kWave, nv, R2);
                         if (act) masks[(size_t)(w0 + q) * n + p] = m;
                         npair += want ? (uint32_t)__popcll(m) : 0u;
@@ -456,6 +517,9 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
     const Phys<T> ph = scn.ph;
     if (!load_nbhd(slot - g.slot0, g, cstart, cend, nb, lane)) return;   // flagged by the density pass
     const uint32_t S = nb.stride;
+    const T R2 = grid_R2<T>(g);
+    T blo[3], bhi[3];
+    cell_box<T>(st.pos, s0, e0, lane, blo, bhi);
     const uint32_t ncell = e0 - s0, rem = ncell % kWave;
     const bool use_left = ncell > (uint32_t)kWave && rem != 0u && rem <= kLeftF;
     const uint32_t nlane = use_left ? ncell / kWave : (ncell + kWave - 1) / kWave;
@@ -482,15 +546,24 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
         uint32_t witer = 0;
         for (uint32_t sc = 0; sc < S; ++sc) {
             begin_chunk(nb, sc, lane);
-            const uint32_t size = nb.size;
+            // the density pass's compacted layout: candidates near the cell's
+            // box in chunk order (slots past it are never hit)
+            uint32_t size = 0;
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) {
-                // slots past the chunk are never hit (their mask bits are 0)
                 const uint32_t v = q * kWave + lane;
-                const uint32_t j = v < size ? chunk_index(nb, sc, v) : s0;
-                cp[v] = st.pos[j];
-                cvel[v] = st.vel[j];
-                cden[v] = dens[j];
+                const bool in = v < nb.size;
+                const uint32_t j = in ? chunk_index(nb, sc, v) : s0;
+                const V4<T> c = st.pos[j];
+                const bool keep = in && near_box<T>(c, blo, bhi, R2);
+                const uint64_t km = __ballot(keep);
+                if (keep) {
+                    const uint32_t o = size + lanes_below(km, lane);
+                    cp[o] = c;
+                    cvel[o] = st.vel[j];
+                    cden[o] = dens[j];
+                }
+                size += (uint32_t)__popcll(km);
             }
             const uint32_t nws = nb.wbase[sc + 1] - nb.wbase[sc];
             const uint32_t w0 = nb.wbase[sc];

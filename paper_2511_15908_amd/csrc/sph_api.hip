@@ -4,6 +4,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <limits>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -1404,7 +1406,13 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t nt, const uint32_t *targets, uint32
     hipStream_t s = c->stream;
     std::vector<uint32_t> ids(n), aux(n), keys(n), cs(c->nslots), ce(c->nslots);
     std::vector<uint64_t> masks((size_t)kMaxWords * n);
+    // positions the step's neighbour passes saw: the reorder's source buffer
+    // through the sort permutation (integration has moved the current one)
+    std::vector<V4<T>> pos(n), old(n);
+    std::vector<uint32_t> perm(n);
     if (n) {
+        HIPCHK(c, hipMemcpyAsync(old.data(), c->pos[1 - c->cur], (size_t)n * sizeof(V4<T>), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(perm.data(), c->sorted_vals, (size_t)n * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipMemcpyAsync(ids.data(), c->id[c->cur], (size_t)n * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipMemcpyAsync(aux.data(), c->aux[c->cur], (size_t)n * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipMemcpyAsync(keys.data(), c->sorted_keys, (size_t)n * 4, hipMemcpyDeviceToHost, s));
@@ -1414,6 +1422,7 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t nt, const uint32_t *targets, uint32
     }
     sph_status st = check_err(c);
     if (st == SPH_ERR_DEVICE) return st;
+    for (uint32_t p = 0; p < n; ++p) pos[p] = old[perm[p]];
     std::vector<std::vector<uint32_t>> lists(n);
     std::vector<uint8_t> want(n, targets ? 0 : 1);
     if (targets)
@@ -1426,6 +1435,27 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t nt, const uint32_t *targets, uint32
         while (sc + 1 < c->nscenes && c->grids[sc + 1].slot0 <= keys[p]) ++sc;
         const Grid &g = c->grids[sc];
         const uint32_t home = keys[p] - g.slot0;
+        // the kernels' candidate filter: within the support of the home cell's box
+        T lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::numeric_limits<T>::infinity();
+            hi[d] = -std::numeric_limits<T>::infinity();
+        }
+        for (uint32_t j = cs[keys[p]]; j < ce[keys[p]]; ++j) {
+            const T xyz[3] = {pos[j].x, pos[j].y, pos[j].z};
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::fmin(lo[d], xyz[d]);
+                hi[d] = std::fmax(hi[d], xyz[d]);
+            }
+        }
+        const T R2 = std::is_same<T, float>::value ? (T)g.R2_32 : (T)g.R2_64;
+        auto near = [&](const V4<T> &q) {
+#pragma clang fp contract(off)
+            const T dx = std::fmax(std::fmax(lo[0] - q.x, q.x - hi[0]), (T)0);
+            const T dy = std::fmax(std::fmax(lo[1] - q.y, q.y - hi[1]), (T)0);
+            const T dz = std::fmax(std::fmax(lo[2] - q.z, q.z - hi[2]), (T)0);
+            return dx * dx + dy * dy + dz * dz < R2 * (T)1.00390625;
+        };
         const int cx = (int)compact3(home), cy = (int)compact3(home >> 1), cz = (int)compact3(home >> 2);
         uint32_t start[27], cnt[27], L = 0;
         for (int k = 0; k < 27; ++k) {
@@ -1463,14 +1493,20 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t nt, const uint32_t *targets, uint32
                 over = true;
                 break;
             }
+            std::vector<uint32_t> kept;
+            for (uint32_t v = 0; v < size; ++v) {
+                int k = 0;
+                while (k < 26 && pre[k + 1] <= v) ++k;
+                const uint32_t j = start[k] + sc + S * (v - pre[k]);
+                if (near(pos[j])) kept.push_back(j);
+            }
             for (uint32_t q = 0; q < nws; ++q) {
                 const uint64_t m = masks[(size_t)(w0 + q) * n + p];
                 for (int b = 0; b < 64; ++b) {
                     if (!((m >> b) & 1ull)) continue;
                     const uint32_t v = q * kWave + (uint32_t)b;
-                    int k = 0;
-                    while (k < 26 && pre[k + 1] <= v) ++k;
-                    lst.push_back(ids[start[k] + sc + S * (v - pre[k])]);
+                    if (v < kept.size()) lst.push_back(ids[kept[v]]);
+                    else lst.push_back(0xffffffffu);      // a hit past the staged candidates: reported as is
                 }
             }
             w0 += nws;

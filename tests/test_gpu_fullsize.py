@@ -84,3 +84,33 @@ def test_stirring_250k_sampled(gpu, orc):
     from paper_2511_15908_amd import scenes
     sc = scenes.stirring_tank()
     _fullsize(gpu, orc, sc, scenes.stirring_pose(sc, 0.3), 2)
+
+
+def _all_particles(gpu, orc, sc, pose):
+    sim = gpu.Sim(sc)
+    sim.set_body_pose(1, *pose)
+    sim.step(1)
+    o = orc.Oracle(sc, "f32")
+    o.set_pose(1, *pose)
+    r = o.step()
+    fs = np.nonzero(sc.type != 2)[0]
+    rg, fg = sim.read("rho")[fs], sim.read("f")
+    e_rho = np.abs(rg - r["rho"][fs]) / r["rho"][fs]
+    mref = float(np.median(sc.mass[fs]))
+    floor = np.maximum(np.linalg.norm(r["f"], axis=1), mref * _cmp.G)
+    e_f = np.linalg.norm(fg - r["f"], axis=1) / floor
+    body = np.nonzero(sc.object == 1)[0]
+    print(f"{sc.name} all {fs.size} fluid/soft: density max {e_rho.max():.2e} p99.9 {np.percentile(e_rho, 99.9):.2e}; "
+          f"force (all {sc.n}) max {e_f.max():.2e} p99.9 {np.percentile(e_f, 99.9):.2e} median {np.median(e_f):.2e}; "
+          f"body particles max {e_f[body].max():.2e}")
+    assert e_rho.max() <= 1e-5
+    assert e_f.max() <= 1e-4
+
+
+def test_coupled_1m_every_particle(gpu, orc):
+    """Every particle of the 1M scene after one step (the oracle's full FP64
+    step on the host cores)."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.coupled_1m()
+    C, Q, V, W = scenes.random_walk(3, 40, sc.info["c0"])
+    _all_particles(gpu, orc, sc, (C[37], Q[37], V[37], W[37]))
