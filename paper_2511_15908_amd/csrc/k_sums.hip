@@ -209,18 +209,21 @@ __device__ __forceinline__ uint64_t hit_word(const V4<T> &me, const V4<T> *cand,
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Next set bit of this lane's staged masks (half-words in LDS); -1 when done.
-template <int W>
-__device__ __forceinline__ int next_hit(uint32_t (*mlds)[kWave], uint32_t lane, int &hw, uint32_t &cur)
+// Lowest set bit of this lane's hit words (held in registers, mw[0] first),
+// cleared on return; -1 when none is left.  When the current word empties
+// the later words move down one place (base counts the words consumed), so
+// every lane walks its own bits without branching on the others.
+__device__ __forceinline__ int next_hit(uint64_t (&mw)[kScWords], int &base)
 {
-    while (cur == 0u && hw < 2 * W - 1) {
-        ++hw;
-        cur = mlds[hw][lane];
-    }
-    if (cur == 0u) return -1;
-    const int b = __builtin_ctz(cur);
-    cur &= cur - 1u;
-    return hw * 32 + b;
+    const bool empty = mw[0] == 0ull;
+#pragma unroll
+    for (int w = 0; w + 1 < kScWords; ++w) mw[w] = empty ? mw[w + 1] : mw[w];
+    mw[kScWords - 1] = empty ? 0ull : mw[kScWords - 1];
+    base = empty ? base + kWave : base;
+    const uint64_t m = mw[0];
+    if (m == 0ull) return -1;
+    mw[0] = m & (m - 1ull);
+    return base + (int)__builtin_ctzll(m);
 }
 
 // ------------------------------------------------------------------ density
@@ -257,7 +260,6 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
 {
     __shared__ Nbhd nb;
     __shared__ V4<T> cand[kScWords * kWave];
-    __shared__ uint32_t mlds[2 * kScWords][kWave];
     __shared__ double accl[kLeftD > 0 ? kLeftD : 1];
     const uint32_t lane = threadIdx.x;
     const uint32_t slot = cell_of_block(blockIdx.x, b.nslots);
@@ -323,6 +325,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
             const uint32_t nws = nb.wbase[sc + 1] - nb.wbase[sc];
             const uint32_t w0 = nb.wbase[sc];
             if (lanes_any) {
+                uint64_t mw[kScWords];
 #pragma unroll
                 for (int q = 0; q < kScWords; ++q) {
                     uint64_t m = 0;
@@ -332,22 +335,20 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                         if (act) masks[(size_t)(w0 + q) * n + p] = m;
                         npair += want ? (uint32_t)__popcll(m) : 0u;
                     }
-                    mlds[2 * q][lane] = fs ? (uint32_t)m : 0u;
-                    mlds[2 * q + 1][lane] = fs ? (uint32_t)(m >> 32) : 0u;
+                    mw[q] = fs ? m : 0ull;
                 }
                 {
                     uint32_t mine = 0;
 #pragma unroll
-                    for (int h = 0; h < 2 * kScWords; ++h) mine += __popc(mlds[h][lane]);
+                    for (int q = 0; q < kScWords; ++q) mine += (uint32_t)__popcll(mw[q]);
 #pragma unroll
                     for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
                     witer += mine;
                 }
                 // kernel sum over this lane's neighbours among the staged candidates
-                int hw = 0;
-                uint32_t cur = mlds[0][lane];
+                int base = 0;
                 for (;;) {
-                    const int k = next_hit<kScWords>(mlds, lane, hw, cur);
+                    const int k = next_hit(mw, base);
                     if (k < 0) break;
                     const V4<T> c = cand[k];
                     acc = fma((double)fabs(c.w), kernel_w64<T>(c, me, ph), acc);
@@ -505,7 +506,6 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
     __shared__ V4<T> cp[kScWords * kWave];
     __shared__ V4<T> cvel[kScWords * kWave];
     __shared__ V2<T> cden[kScWords * kWave];
-    __shared__ uint32_t mlds[2 * kScWords][kWave];
     __shared__ double accf[kLeftF > 0 ? kLeftF : 1][3];
     const uint32_t lane = threadIdx.x;
     const uint32_t slot = cell_of_block(blockIdx.x, b.nslots);
@@ -567,29 +567,28 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
             }
             const uint32_t nws = nb.wbase[sc + 1] - nb.wbase[sc];
             const uint32_t w0 = nb.wbase[sc];
+            uint64_t mw[kScWords];
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) {
                 uint64_t m = 0;
                 if ((uint32_t)q < nws && tgt) m = masks[(size_t)(w0 + q) * n + p];
-                mlds[2 * q][lane] = (uint32_t)m;
-                mlds[2 * q + 1][lane] = (uint32_t)(m >> 32);
+                mw[q] = m;
             }
             __syncthreads();
             if (lanes_any) {
                 {
                     uint32_t mine = 0;
 #pragma unroll
-                    for (int h = 0; h < 2 * kScWords; ++h) mine += __popc(mlds[h][lane]);
+                    for (int q = 0; q < kScWords; ++q) mine += (uint32_t)__popcll(mw[q]);
 #pragma unroll
                     for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
                     witer += mine;
                 }
                 // a super-chunk holds ~1/S of the neighbours: sum it in T, then in FP64
                 T cx = (T)0, cy = (T)0, cz = (T)0;
-                int hw = 0;
-                uint32_t cur = mlds[0][lane];
+                int base = 0;
                 for (;;) {
-                    const int k = next_hit<kScWords>(mlds, lane, hw, cur);
+                    const int k = next_hit(mw, base);
                     if (k < 0) break;
                     pair_force<T>(me, mv, md.x, md.y, kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
                 }
