@@ -36,8 +36,9 @@ struct Nbhd {
     uint32_t stride;      // S: number of super-chunks
     uint32_t nw;          // candidate words of the neighbourhood
     uint32_t wbase[kMaxWords + 1];  // first word of each super-chunk (S <= kMaxWords)
-    uint32_t pre[32];     // current super-chunk: exclusive prefix of per-cell counts, padded
-    uint32_t size;        // current super-chunk: candidates
+    uint32_t pre[2][32];  // super-chunks being staged / prefetched (by parity): exclusive
+                          // prefix of the per-cell counts, padded
+    uint32_t size[2];     // their candidate counts
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD runs of 64
@@ -110,30 +111,65 @@ __device__ __forceinline__ bool load_nbhd(uint32_t cell, const Grid &g, const ui
     return NW <= (uint32_t)kMaxWords;
 }
 
-// Prefix of the per-cell shares of super-chunk s (all lanes participate).
-__device__ __forceinline__ void begin_chunk(Nbhd &nb, uint32_t s, uint32_t lane)
+// Inclusive prefix sum over lanes 0..31: within each 16-lane row by DPP row
+// shifts, then row 0's total broadcast into row 1 (all lanes active).
+__device__ __forceinline__ uint32_t scan32_incl(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);    // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);    // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);    // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);    // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    return x;
+}
+
+// Prefix of the per-cell shares of super-chunk s into pre[buf] (all lanes
+// participate).
+__device__ __forceinline__ void begin_chunk(Nbhd &nb, uint32_t s, uint32_t buf, uint32_t lane)
 {
     const uint32_t c = (lane < 27u) ? share(nb.cnt[lane], s, nb.stride) : 0u;
-    uint32_t inc = c;
-#pragma unroll
-    for (int d = 1; d < 32; d <<= 1) {
-        const uint32_t t = __shfl_up(inc, d, 64);
-        if (lane >= (uint32_t)d) inc += t;
-    }
-    if (lane < 32u) nb.pre[lane] = lane < 27u ? inc - c : 0xffffffffu;
-    if (lane == 26u) nb.size = inc;
+    const uint32_t inc = scan32_incl(c);
+    if (lane < 32u) nb.pre[buf][lane] = lane < 27u ? inc - c : 0xffffffffu;
+    if (lane == 26u) nb.size[buf] = inc;
     __syncthreads();
 }
 
-// Sorted index of candidate v (< size) of super-chunk s: cell k = largest
-// with pre[k] <= v, in-cell index s + S (v - pre[k]).
-__device__ __forceinline__ uint32_t chunk_index(const Nbhd &nb, uint32_t s, uint32_t v)
+// Sorted indices of the slots v = q*64 + lane of super-chunk s (prefix in
+// pre[buf]): cell k = largest with pre[k] <= v, in-cell index s + S (v -
+// pre[k]); slots past the super-chunk's size get dflt, and every index is
+// kept below n.  The searches of the words run interleaved, so their LDS
+// latencies overlap.
+__device__ __forceinline__ void chunk_slots(const Nbhd &nb, uint32_t s, uint32_t buf, uint32_t lane, uint32_t dflt,
+                                            uint32_t n, uint32_t (&j)[kScWords])
 {
-    uint32_t k = 0;
+    uint32_t k[kScWords];
 #pragma unroll
-    for (uint32_t step = 16; step >= 1; step >>= 1)
-        if (nb.pre[k + step] <= v) k += step;
-    return nb.start[k] + s + nb.stride * (v - nb.pre[k]);
+    for (int q = 0; q < kScWords; ++q) k[q] = 0;
+#pragma unroll
+    for (uint32_t step = 16; step >= 1; step >>= 1) {
+#pragma unroll
+        for (int q = 0; q < kScWords; ++q)
+            if (nb.pre[buf][k[q] + step] <= (uint32_t)q * kWave + lane) k[q] += step;
+    }
+    const uint32_t sz = nb.size[buf];
+#pragma unroll
+    for (int q = 0; q < kScWords; ++q) {
+        const uint32_t v = (uint32_t)q * kWave + lane;
+        j[q] = v < sz ? min(nb.start[k[q]] + s + nb.stride * (v - nb.pre[buf][k[q]]), n - 1u) : dflt;
+    }
+}
+
+// A value every lane holds alike, moved to scalar registers.
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // Bounding box of the home cell's particles (lanes stride over them; the
@@ -162,12 +198,12 @@ __device__ __forceinline__ void cell_box(const V4<T> *__restrict__ pos, uint32_t
         h1 = fmax(h1, __shfl_xor(h1, m, 64));
         h2 = fmax(h2, __shfl_xor(h2, m, 64));
     }
-    lo[0] = l0;
-    lo[1] = l1;
-    lo[2] = l2;
-    hi[0] = h0;
-    hi[1] = h1;
-    hi[2] = h2;
+    lo[0] = wave_uniform(l0);
+    lo[1] = wave_uniform(l1);
+    lo[2] = wave_uniform(l2);
+    hi[0] = wave_uniform(h0);
+    hi[1] = wave_uniform(h1);
+    hi[2] = wave_uniform(h2);
 }
 
 // A candidate farther than the support from every point of the box cannot
@@ -189,14 +225,32 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m, uint32_t lane)
     return (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
 }
 
+// Sign word of r2 - R2 in T for the pair (a, b): its top bit is set exactly
+// when the canonical predicate r2 < R2 holds (the difference of two floats
+// is zero only when they are equal, and equal values give +0).
+template <typename T>
+__device__ __forceinline__ uint32_t gap_sign(const V4<T> &a, const V4<T> &b, T R2)
+{
+#pragma clang fp contract(off)
+    const T dx = b.x - a.x;
+    const T dy = b.y - a.y;
+    const T dz = b.z - a.z;
+    const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const T d = r2 - R2;
+    if constexpr (sizeof(T) == 4) return __float_as_uint((float)d);
+    else return (uint32_t)((uint64_t)__double_as_longlong((double)d) >> 32);
+}
+
 // Hit bits of this lane's particle against nv (<= 32) staged candidates;
-// nv is uniform, so empty slots of a super-chunk are never tested.
+// nv is uniform, so empty slots of a super-chunk are never tested.  The
+// candidates go from the last to the first, each shifting its sign bit in
+// at the bottom (one funnel shift), so candidate b ends at bit b.
 template <typename T>
 __device__ __forceinline__ uint32_t hit_bits(const V4<T> &me, const V4<T> *cand, uint32_t nv, T R2)
 {
     uint32_t bits = 0;
 #pragma unroll 8
-    for (uint32_t b = 0; b < nv; ++b) bits |= (uint32_t)within_support<T>(me, cand[b], R2) << b;
+    for (uint32_t b = nv; b-- > 0u;) bits = __builtin_amdgcn_alignbit(bits, gap_sign<T>(me, cand[b], R2), 31u);
     return bits;
 }
 
@@ -209,22 +263,36 @@ __device__ __forceinline__ uint64_t hit_word(const V4<T> &me, const V4<T> *cand,
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Lowest set bit of this lane's hit words (held in registers, mw[0] first),
-// cleared on return; -1 when none is left.  When the current word empties
-// the later words move down one place (base counts the words consumed), so
-// every lane walks its own bits without branching on the others.
-__device__ __forceinline__ int next_hit(uint64_t (&mw)[kScWords], int &base)
+// This lane's hit words are held in registers, mw[0] first, and walked
+// lowest bit first: the loop over a lane's hits is
+//     for (;;) { skip_empty_word(mw, base); if (mw[0] == 0) break;
+//                k = base + ctz(mw[0]); clear that bit; ... }
+// When the current word is empty the later words move down one place (base
+// counts the candidates of the words consumed), so every lane walks its own
+// bits without branching on the others.  One move per iteration suffices
+// for at most two words: a word only empties by the clearing of its last bit.
+static_assert(kScWords >= 1 && kScWords <= 2, "skip_empty_word moves one word per iteration");
+__device__ __forceinline__ void skip_empty_word(uint64_t (&mw)[kScWords], int &base)
 {
     const bool empty = mw[0] == 0ull;
 #pragma unroll
     for (int w = 0; w + 1 < kScWords; ++w) mw[w] = empty ? mw[w + 1] : mw[w];
     mw[kScWords - 1] = empty ? 0ull : mw[kScWords - 1];
     base = empty ? base + kWave : base;
+}
+
+// Index of the lowest hit (mw[0] != 0), which is cleared.
+__device__ __forceinline__ int take_hit(uint64_t (&mw)[kScWords], int base)
+{
     const uint64_t m = mw[0];
-    if (m == 0ull) return -1;
     mw[0] = m & (m - 1ull);
     return base + (int)__builtin_ctzll(m);
 }
+
+// A staged candidate for the FP64 density terms: position and mass.
+struct Cand64 {
+    double x, y, z, m;
+};
 
 // ------------------------------------------------------------------ density
 
@@ -259,7 +327,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                                                 unsigned long long *__restrict__ stats)
 {
     __shared__ Nbhd nb;
-    __shared__ V4<T> cand[kScWords * kWave];
+    __shared__ V4<T> cand[kScWords * kWave];         // tests: T positions, inf past the end
+    __shared__ Cand64 cand64[kScWords * kWave];     // terms: FP64 positions and masses
     __shared__ double accl[kLeftD > 0 ? kLeftD : 1];
     const uint32_t lane = threadIdx.x;
     const uint32_t slot = cell_of_block(blockIdx.x, b.nslots);
@@ -283,6 +352,10 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
     const uint32_t nlane = use_left ? ncell / kWave : (ncell + kWave - 1) / kWave;
     const uint32_t nleft = use_left ? rem : 0u;
     const uint32_t left0 = s0 + kWave * nlane;
+    // work counters of the cell (uniform), added to the slot's own record
+    // (kept in LDS by lane 0 rather than in registers)
+    __shared__ unsigned long long cstat[5];
+    if (lane < 5u) cstat[lane] = 0ull;
     for (uint32_t ch = 0; ch < nlane; ++ch) {
         const uint32_t t0 = s0 + kWave * ch;
         const bool with_left = (ch + 1 == nlane) && nleft;
@@ -294,6 +367,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         me.x = act ? me.x : inf;
         me.y = act ? me.y : inf;
         me.z = act ? me.z : inf;
+        const double mx = (double)me.x, my = (double)me.y, mz = (double)me.z;
         const bool fs = act && aux_type(aux) != TY_BOUNDARY;
         const bool want = act && (fs || aux_kin(aux));
         const bool lanes_any = __ballot(want) != 0ull;
@@ -301,18 +375,42 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         if (with_left && lane < nleft) accl[lane] = 0.0;
         double acc = 0.0;
         uint32_t npair = 0, witer = 0, ncand = 0, nleftpair_d = 0, nleftpair_f = 0;
+        // the candidates of super-chunk sc + 1 are loaded while sc is summed
+        V4<T> nxt[kScWords];
+        {
+            uint32_t j[kScWords];
+            begin_chunk(nb, 0u, 0u, lane);
+            chunk_slots(nb, 0u, 0u, lane, s0, n, j);
+#pragma unroll
+            for (int q = 0; q < kScWords; ++q) nxt[q] = st.pos[j[q]];
+        }
         for (uint32_t sc = 0; sc < S; ++sc) {
-            begin_chunk(nb, sc, lane);
+            const uint32_t buf = sc & 1u;
+            const uint32_t csize = nb.size[buf];
+            V4<T> cur[kScWords];
+#pragma unroll
+            for (int q = 0; q < kScWords; ++q) cur[q] = nxt[q];
+            if (sc + 1u < S) {
+                uint32_t j[kScWords];
+                begin_chunk(nb, sc + 1u, buf ^ 1u, lane);
+                chunk_slots(nb, sc + 1u, buf ^ 1u, lane, s0, n, j);
+#pragma unroll
+                for (int q = 0; q < kScWords; ++q) nxt[q] = st.pos[j[q]];
+            }
             // stage the super-chunk's candidates near the cell's box, compacted
             uint32_t size = 0;
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) {
                 const uint32_t v = q * kWave + lane;
-                const bool in = v < nb.size;
-                const V4<T> c = st.pos[in ? chunk_index(nb, sc, v) : s0];
+                const bool in = v < csize;
+                const V4<T> c = cur[q];
                 const bool keep = in && near_box<T>(c, blo, bhi, R2);
                 const uint64_t km = __ballot(keep);
-                if (keep) cand[size + lanes_below(km, lane)] = c;
+                if (keep) {
+                    const uint32_t slot_c = size + lanes_below(km, lane);
+                    cand[slot_c] = c;
+                    cand64[slot_c] = Cand64{(double)c.x, (double)c.y, (double)c.z, (double)fabs(c.w)};
+                }
                 size += (uint32_t)__popcll(km);
             }
 #pragma unroll
@@ -345,13 +443,15 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                     for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
                     witer += mine;
                 }
-                // kernel sum over this lane's neighbours among the staged candidates
+                // kernel sum over this lane's neighbours among the staged
+                // candidates, in units of alpha/6
                 int base = 0;
                 for (;;) {
-                    const int k = next_hit(mw, base);
-                    if (k < 0) break;
-                    const V4<T> c = cand[k];
-                    acc = fma((double)fabs(c.w), kernel_w64<T>(c, me, ph), acc);
+                    skip_empty_word(mw, base);
+                    if (mw[0] == 0ull) break;
+                    const int k = take_hit(mw, base);
+                    const Cand64 c = cand64[k];
+                    acc = fma(c.m, spline_shape64(c.x - mx, c.y - my, c.z - mz, ph.inv_h64), acc);
                 }
             }
             if (with_left) {
@@ -362,6 +462,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                     const bool fs_t = aux_type(at) != TY_BOUNDARY;
                     if (!fs_t && !aux_kin(at)) continue;    // uniform: static boundary
                     const V4<T> mt = st.pos[pt];
+                    const double tx = (double)mt.x, ty = (double)mt.y, tz = (double)mt.z;
                     double part = 0.0;
 #pragma unroll
                     for (int q = 0; q < kScWords; ++q) {
@@ -373,7 +474,11 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                             const uint32_t cnt = (uint32_t)__popcll(m);
                             nleftpair_f += cnt;
                             nleftpair_d += fs_t ? cnt : 0u;
-                            if (fs_t && hit) part = fma((double)fabs(c.w), kernel_w64<T>(c, mt, ph), part);
+                            if (fs_t && hit) {
+                                const Cand64 c64 = cand64[q * kWave + lane];
+                                part = fma(c64.m, spline_shape64(c64.x - tx, c64.y - ty, c64.z - tz, ph.inv_h64),
+                                           part);
+                            }
                         }
                     }
                     part = wave_sum_f64(part);
@@ -389,20 +494,21 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
             nd = wave_sum_u32(nd);
             nf = wave_sum_u32(nf);
             if (lane == 0) {
-                atomicAdd(stats + 0, (unsigned long long)(nd + nleftpair_d));
-                atomicAdd(stats + 1, (unsigned long long)(nf + nleftpair_f));
-                atomicAdd(stats + 2, (unsigned long long)ncand * (kWave + nleft));
-                atomicAdd(stats + 3, 1ull);
-                atomicAdd(stats + 4, (unsigned long long)witer);
+                cstat[0] += nd + nleftpair_d;
+                cstat[1] += nf + nleftpair_f;
+                cstat[2] += (unsigned long long)ncand * (kWave + nleft);
+                cstat[3] += 1u;
+                cstat[4] += witer;
             }
         }
         if (act) {
             V2<T> d{(T)0, (T)0};
             if (fs) {
-                double pr = ph.kp * (acc - ph.rho0);
+                const double rho = ph.alpha6_64 * acc;
+                double pr = ph.kp * (rho - ph.rho0);
                 if ((ph.flags & 1u) && pr < 0.0) pr = 0.0;
-                d.x = (T)acc;
-                d.y = (T)(pr / (acc * acc));
+                d.x = (T)rho;
+                d.y = (T)(pr / (rho * rho));
             }
             dens[p] = d;
         }
@@ -411,7 +517,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
             const bool fs_t = aux_type(st.aux[pt]) != TY_BOUNDARY;
             V2<T> d{(T)0, (T)0};
             if (fs_t) {
-                const double rho = accl[lane];
+                const double rho = ph.alpha6_64 * accl[lane];
                 double pr = ph.kp * (rho - ph.rho0);
                 if ((ph.flags & 1u) && pr < 0.0) pr = 0.0;
                 d.x = (T)rho;
@@ -420,6 +526,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
             dens[pt] = d;
         }
     }
+    __syncthreads();
+    if (lane < 5u) stats[(size_t)slot * kStatWords + lane] += cstat[lane];
 }
 
 // ------------------------------------------------------------------ forces
@@ -525,6 +633,8 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
     const uint32_t nlane = use_left ? ncell / kWave : (ncell + kWave - 1) / kWave;
     const uint32_t nleft = use_left ? rem : 0u;
     const uint32_t left0 = s0 + kWave * nlane;
+    __shared__ unsigned long long cstat;   // neighbour-loop iterations of the cell
+    if (lane == 0) cstat = 0ull;
     for (uint32_t ch = 0; ch < nlane; ++ch) {
         const uint32_t t0 = s0 + kWave * ch;
         const bool with_left = (ch + 1 == nlane) && nleft;
@@ -544,17 +654,38 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
         const T ma = fabs(me.w);
         double fx = 0.0, fy = 0.0, fz = 0.0;
         uint32_t witer = 0;
+        // the positions of super-chunk sc + 1 are loaded while sc is summed
+        V4<T> nxt[kScWords];
+        uint32_t nj[kScWords];
+        begin_chunk(nb, 0u, 0u, lane);
+        chunk_slots(nb, 0u, 0u, lane, s0, n, nj);
+#pragma unroll
+        for (int q = 0; q < kScWords; ++q) nxt[q] = st.pos[nj[q]];
         for (uint32_t sc = 0; sc < S; ++sc) {
-            begin_chunk(nb, sc, lane);
+            const uint32_t buf = sc & 1u;
+            const uint32_t csize = nb.size[buf];
+            V4<T> cur[kScWords];
+            uint32_t cj[kScWords];
+#pragma unroll
+            for (int q = 0; q < kScWords; ++q) {
+                cur[q] = nxt[q];
+                cj[q] = nj[q];
+            }
+            if (sc + 1u < S) {
+                begin_chunk(nb, sc + 1u, buf ^ 1u, lane);
+                chunk_slots(nb, sc + 1u, buf ^ 1u, lane, s0, n, nj);
+#pragma unroll
+                for (int q = 0; q < kScWords; ++q) nxt[q] = st.pos[nj[q]];
+            }
             // the density pass's compacted layout: candidates near the cell's
             // box in chunk order (slots past it are never hit)
             uint32_t size = 0;
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) {
                 const uint32_t v = q * kWave + lane;
-                const bool in = v < nb.size;
-                const uint32_t j = in ? chunk_index(nb, sc, v) : s0;
-                const V4<T> c = st.pos[j];
+                const bool in = v < csize;
+                const uint32_t j = cj[q];
+                const V4<T> c = cur[q];
                 const bool keep = in && near_box<T>(c, blo, bhi, R2);
                 const uint64_t km = __ballot(keep);
                 if (keep) {
@@ -588,8 +719,9 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
                 T cx = (T)0, cy = (T)0, cz = (T)0;
                 int base = 0;
                 for (;;) {
-                    const int k = next_hit(mw, base);
-                    if (k < 0) break;
+                    skip_empty_word(mw, base);
+                    if (mw[0] == 0ull) break;
+                    const int k = take_hit(mw, base);
                     pair_force<T>(me, mv, md.x, md.y, kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
                 }
                 fx += (double)cx;
@@ -632,7 +764,7 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
             }
             __syncthreads();
         }
-        if (lane == 0) atomicAdd(stats + 5, (unsigned long long)witer);
+        if (lane == 0) cstat += witer;
         if (tgt) store_force<T>(p, aux, ma, fx, fy, fz, ph, fspring, force, fbody);
         if (with_left && lane < nleft) {
             const uint32_t pt = left0 + lane;
@@ -642,6 +774,31 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
                                force, fbody);
         }
     }
+    if (lane == 0) stats[(size_t)slot * kStatWords + 5] += cstat;
+}
+
+// Work counters: each cell slot's record is only touched by the one
+// workgroup that serves the slot in a launch, so the sums need no atomics;
+// this reduction (one block per counter, fixed order) adds them up on demand.
+__global__ __launch_bounds__(256) void k_stats_sum(uint32_t nslots, const unsigned long long *__restrict__ rec,
+                                                   unsigned long long *__restrict__ out)
+{
+    __shared__ unsigned long long part[256];
+    const uint32_t k = blockIdx.x, t = threadIdx.x;
+    unsigned long long v = 0;
+    for (uint32_t i = t; i < nslots; i += 256u) v += rec[(size_t)i * kStatWords + k];
+    part[t] = v;
+    __syncthreads();
+    for (uint32_t h = 128; h >= 1; h >>= 1) {
+        if (t < h) part[t] += part[t + h];
+        __syncthreads();
+    }
+    if (t == 0) out[k] = part[0];
+}
+
+void launch_stats_sum(hipStream_t s, uint32_t nslots, const unsigned long long *rec, unsigned long long *out)
+{
+    hipLaunchKernelGGL(k_stats_sum, dim3(kStats), dim3(256), 0, s, nslots, rec, out);
 }
 
 template <typename T>

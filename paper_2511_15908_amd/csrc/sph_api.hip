@@ -83,7 +83,8 @@ struct sph_ctx {
     double *ring = nullptr;
     uint32_t *ring_count = nullptr;
     uint32_t *err = nullptr;
-    unsigned long long *stats = nullptr;
+    unsigned long long *stats = nullptr;        // [kStats] sums, filled on request
+    unsigned long long *stat_rec = nullptr;     // [nslots][kStatWords] per-slot counters
     int32_t *obj_of_id = nullptr;
     uint32_t max_probes = 0, n_probes = 0;
     double *probe_pts = nullptr, *probe_out = nullptr;
@@ -556,6 +557,7 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
     c->ring_count = cv.take<uint32_t>((size_t)pl.nk * 4);
     c->err = cv.take<uint32_t>(16);
     c->stats = cv.take<unsigned long long>(8 * 8);
+    c->stat_rec = cv.take<unsigned long long>((size_t)pl.nslots * kStatWords * 8);
     c->obj_of_id = cv.take<int32_t>(n * 4);
     c->probe_pts = cv.take<double>((size_t)pl.max_probes * 3 * 8);
     c->probe_frame = cv.take<int32_t>((size_t)pl.max_probes * 4);
@@ -669,11 +671,11 @@ void one_step(sph_ctx *c)
     launch_springs<T>(s, sa, c->inv_perm, st, (V4<T> *)c->fspring);
     prof_mark(c, 4, false);
     prof_mark(c, 5, true);
-    launch_density<T>(s, c->n, st, batch<T>(c), c->cstart, c->cend, (V2<T> *)c->dens, c->masks, c->err, c->stats);
+    launch_density<T>(s, c->n, st, batch<T>(c), c->cstart, c->cend, (V2<T> *)c->dens, c->masks, c->err, c->stat_rec);
     prof_mark(c, 5, false);
     prof_mark(c, 6, true);
     launch_forces<T>(s, c->n, st, batch<T>(c), c->cstart, c->cend, (const V2<T> *)c->dens, c->masks,
-                     (const V4<T> *)c->fspring, (V4<T> *)c->force, c->fbody, c->err, c->stats);
+                     (const V4<T> *)c->fspring, (V4<T> *)c->force, c->fbody, c->err, c->stat_rec);
     prof_mark(c, 6, false);
     prof_mark(c, 9, true);
     if (c->n_probes) {
@@ -836,6 +838,7 @@ sph_status upload(sph_ctx *c, const sph_scene *s)
     launch_clear_u32(st, c->ring_count, c->nk);
     launch_clear_u32(st, c->err, 4);
     launch_clear_u32(st, (uint32_t *)c->stats, 16);
+    launch_clear_u32(st, (uint32_t *)c->stat_rec, (size_t)c->nslots * kStatWords * 2);
     launch_clear_u32(st, (uint32_t *)c->dens, (size_t)n * 2 * sizeof(T) / 4);
     launch_clear_u32(st, (uint32_t *)c->force, (size_t)n * 4 * sizeof(T) / 4);
     launch_clear_u32(st, (uint32_t *)c->fspring, (size_t)c->rows * 4 * sizeof(T) / 4);
@@ -1569,6 +1572,9 @@ sph_status sph_get_stats(sph_ctx *ctx, uint64_t out[6])
     if (!ctx || !out) return SPH_ERR_ARG;
     if (ctx->dead) return SPH_ERR_STATE;
     unsigned long long v[6] = {0, 0, 0, 0, 0, 0};
+    static_assert(kStats == 6, "sph_get_stats reports six counters");
+    launch_stats_sum(ctx->stream, ctx->nslots, ctx->stat_rec, ctx->stats);
+    HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipMemcpyAsync(v, ctx->stats, sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     for (int k = 0; k < 6; ++k) out[k] = (uint64_t)v[k];

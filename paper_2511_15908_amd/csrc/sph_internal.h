@@ -38,6 +38,8 @@ constexpr int kWave = 64;
 // 64-candidate mask words per super-chunk staged in LDS
 constexpr int kScWords = SPH_SC_WORDS;
 constexpr int kMaxWords = 64;               // capacity: candidate words per neighbourhood
+constexpr int kStats = 6;                   // work counters of a step (see sph_get_stats)
+constexpr int kStatWords = 8;               // per-cell-slot counter record, one 64-byte line
 
 // The 27 cells around a home cell: the home cell, then 13 pairs of opposite
 // cells, so that a staged super-chunk of candidates holds cells from both
@@ -188,23 +190,30 @@ template <>
 __device__ __forceinline__ double grid_R2<double>(const Grid &g) { return g.R2_64; }
 
 
-// Kernel value W(|c - me|) evaluated in FP64 from the exact T-precision
-// coordinate differences: p = k (rho - rho0) turns a relative density error e
+// Shape of the cubic spline, (2-q)+^3 - 4 (1-q)+^3 with q = r/h, in FP64 from
+// FP64 coordinate differences (exact for FP32 positions).  The density sum
+// carries FP64 terms: p = k (rho - rho0) turns a relative density error e
 // into e rho / (rho - rho0) (~1e4 e near rest) in the pressure, whose pair
-// terms nearly cancel, so the density sum carries FP64 terms.
-template <typename T>
-__device__ __forceinline__ double kernel_w64(const V4<T> &c, const V4<T> &me, const Phys<T> &ph)
+// terms nearly cancel.  The constant alpha/6 multiplies finished sums.
+__device__ __forceinline__ double spline_shape64(double dx, double dy, double dz, double inv_h)
 {
-    const double dx = (double)(c.x - me.x), dy = (double)(c.y - me.y), dz = (double)(c.z - me.z);
     const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     // r from an FP32 rsqrt seed and one Newton step in FP64 (~1e-14)
     const double y = (double)frsqrt((float)fmax(r2, 1e-30));
     double r = r2 * y;
     r = fma(0.5 * y, fma(-r, r, r2), r);
-    const double q = r * ph.inv_h64;
+    const double q = r * inv_h;
     const double t2 = fmax(2.0 - q, 0.0);
     const double t1 = fmax(1.0 - q, 0.0);
-    return ph.alpha6_64 * (t2 * t2 * t2 - 4.0 * (t1 * t1 * t1));
+    return fma(t2 * t2, t2, -4.0 * (t1 * (t1 * t1)));
+}
+
+// Kernel value W(|c - me|) in FP64.
+template <typename T>
+__device__ __forceinline__ double kernel_w64(const V4<T> &c, const V4<T> &me, const Phys<T> &ph)
+{
+    return ph.alpha6_64 * spline_shape64((double)c.x - (double)me.x, (double)c.y - (double)me.y,
+                                         (double)c.z - (double)me.z, ph.inv_h64);
 }
 
 // --- batches of independent scenes ---
@@ -272,6 +281,8 @@ void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b,
                    const uint32_t *cstart, const uint32_t *cend, const V2<T> *dens,
                    const uint64_t *masks, const V4<T> *fspring, V4<T> *force, double *fbody,
                    uint32_t *err, unsigned long long *stats);
+// Sum of the per-slot counter records [nslots][kStatWords] into out[kStats].
+void launch_stats_sum(hipStream_t s, uint32_t nslots, const unsigned long long *rec, unsigned long long *out);
 
 // --- launchers (k_body.hip) ---
 struct BodyArgs {
