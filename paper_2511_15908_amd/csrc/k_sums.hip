@@ -50,12 +50,85 @@ __device__ __forceinline__ uint32_t cell_of_block(uint32_t b, uint32_t nslots)
     return grp * 512u + (r & 7u) * 64u + (r >> 3);
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+// --- cross-lane moves by DPP (gfx9): row_shr:n reads lane i - n of the same
+// 16-lane row, row_bcast:15 / :31 read lane 15 / 31 of the row(s) before
+// into the rows enabled by the row mask; a lane with no source keeps `old`.
+// Every reduction and scan below needs all 64 lanes active.
+constexpr int kShr1 = 0x111, kShr2 = 0x112, kShr4 = 0x114, kShr8 = 0x118, kBc15 = 0x142, kBc31 = 0x143;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t old, uint32_t x)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, ROWS, 0xf, false);
 }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_mov(float old, float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_mov(double old, double x)
+{
+    const uint64_t o = (uint64_t)__double_as_longlong(old), v = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)v, CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(v >> 32), CTRL,
+                                                              ROWS, 0xf, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ uint32_t lane63(uint32_t x) { return (uint32_t)__builtin_amdgcn_readlane((int)x, 63); }
+__device__ __forceinline__ float lane63(float x) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63)); }
+__device__ __forceinline__ double lane63(double x)
+{
+    const uint64_t v = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Reduction over the 64 lanes, returned to every lane: after the row shifts
+// lane 15 of each row holds its row's result; the broadcasts fold rows 0-1
+// into lane 31 and then all rows into lane 63.  `id` is op's identity.
+template <typename V, typename Op>
+__device__ __forceinline__ V wave_reduce(V x, V id, Op op)
+{
+    x = op(x, dpp_mov<kShr1, 0xf>(id, x));
+    x = op(x, dpp_mov<kShr2, 0xf>(id, x));
+    x = op(x, dpp_mov<kShr4, 0xf>(id, x));
+    x = op(x, dpp_mov<kShr8, 0xf>(id, x));
+    x = op(x, dpp_mov<kBc15, 0xa>(id, x));
+    x = op(x, dpp_mov<kBc31, 0xc>(id, x));
+    return lane63(x);
+}
+
+// Inclusive prefix sum over the 64 lanes: row scans, then row 0's total into
+// row 1 and row 2's into row 3, then lane 31's total into rows 2-3.
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x)
+{
+    x += dpp_mov<kShr1, 0xf>(0u, x);
+    x += dpp_mov<kShr2, 0xf>(0u, x);
+    x += dpp_mov<kShr4, 0xf>(0u, x);
+    x += dpp_mov<kShr8, 0xf>(0u, x);
+    x += dpp_mov<kBc15, 0xa>(0u, x);
+    x += dpp_mov<kBc31, 0xc>(0u, x);
+    return x;
+}
+
+struct OpAdd {
+    template <typename V>
+    __device__ V operator()(V a, V b) const { return a + b; }
+};
+struct OpMax {
+    __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return max(a, b); }
+    __device__ float operator()(float a, float b) const { return fmaxf(a, b); }
+    __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+struct OpMin {
+    __device__ float operator()(float a, float b) const { return fminf(a, b); }
+    __device__ double operator()(double a, double b) const { return fmin(a, b); }
+};
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) { return wave_reduce(v, 0u, OpAdd{}); }
 
 // Particles of cell k (count c) in super-chunk s of S.
 __device__ __forceinline__ uint32_t share(uint32_t c, uint32_t s, uint32_t S)
@@ -90,18 +163,13 @@ __device__ __forceinline__ bool load_nbhd(uint32_t cell, const Grid &g, const ui
     // words of each super-chunk: lane s < S computes its own size
     uint32_t words = 0;
     for (uint32_t k = 0; k < 27u; ++k) {
-        const uint32_t ck = __shfl(cnt, (int)k, 64);
+        const uint32_t ck = (uint32_t)__builtin_amdgcn_readlane((int)cnt, (int)k);
         words += (lane < S) ? share(ck, lane, S) : 0u;
     }
     words = (words + (uint32_t)kWave - 1u) / (uint32_t)kWave;
-    uint32_t inc = words;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(inc, d, 64);
-        if (lane >= (uint32_t)d) inc += t;
-    }
+    const uint32_t inc = wave_scan_incl(words);
     if (lane < S) nb.wbase[lane] = inc - words;
-    const uint32_t NW = __shfl(inc, 63, 64);
+    const uint32_t NW = lane63(inc);
     if (lane == 0) {
         nb.stride = S;
         nb.nw = NW;
@@ -111,24 +179,12 @@ __device__ __forceinline__ bool load_nbhd(uint32_t cell, const Grid &g, const ui
     return NW <= (uint32_t)kMaxWords;
 }
 
-// Inclusive prefix sum over lanes 0..31: within each 16-lane row by DPP row
-// shifts, then row 0's total broadcast into row 1 (all lanes active).
-__device__ __forceinline__ uint32_t scan32_incl(uint32_t x)
-{
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);    // row_shr:1
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);    // row_shr:2
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);    // row_shr:4
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);    // row_shr:8
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);   // row_bcast:15
-    return x;
-}
-
 // Prefix of the per-cell shares of super-chunk s into pre[buf] (all lanes
 // participate).
 __device__ __forceinline__ void begin_chunk(Nbhd &nb, uint32_t s, uint32_t buf, uint32_t lane)
 {
     const uint32_t c = (lane < 27u) ? share(nb.cnt[lane], s, nb.stride) : 0u;
-    const uint32_t inc = scan32_incl(c);
+    const uint32_t inc = wave_scan_incl(c);
     if (lane < 32u) nb.pre[buf][lane] = lane < 27u ? inc - c : 0xffffffffu;
     if (lane == 26u) nb.size[buf] = inc;
     __syncthreads();
@@ -159,19 +215,6 @@ __device__ __forceinline__ void chunk_slots(const Nbhd &nb, uint32_t s, uint32_t
     }
 }
 
-// A value every lane holds alike, moved to scalar registers.
-__device__ __forceinline__ float wave_uniform(float v)
-{
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-__device__ __forceinline__ double wave_uniform(double v)
-{
-    const uint64_t u = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
 // Bounding box of the home cell's particles (lanes stride over them; the
 // same box for every pass over the cell and in both passes of the step).
 template <typename T>
@@ -189,21 +232,12 @@ __device__ __forceinline__ void cell_box(const V4<T> *__restrict__ pos, uint32_t
         h1 = fmax(h1, c.y);
         h2 = fmax(h2, c.z);
     }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        l0 = fmin(l0, __shfl_xor(l0, m, 64));
-        l1 = fmin(l1, __shfl_xor(l1, m, 64));
-        l2 = fmin(l2, __shfl_xor(l2, m, 64));
-        h0 = fmax(h0, __shfl_xor(h0, m, 64));
-        h1 = fmax(h1, __shfl_xor(h1, m, 64));
-        h2 = fmax(h2, __shfl_xor(h2, m, 64));
-    }
-    lo[0] = wave_uniform(l0);
-    lo[1] = wave_uniform(l1);
-    lo[2] = wave_uniform(l2);
-    hi[0] = wave_uniform(h0);
-    hi[1] = wave_uniform(h1);
-    hi[2] = wave_uniform(h2);
+    lo[0] = wave_reduce(l0, inf, OpMin{});
+    lo[1] = wave_reduce(l1, inf, OpMin{});
+    lo[2] = wave_reduce(l2, inf, OpMin{});
+    hi[0] = wave_reduce(h0, -inf, OpMax{});
+    hi[1] = wave_reduce(h1, -inf, OpMax{});
+    hi[2] = wave_reduce(h2, -inf, OpMax{});
 }
 
 // A candidate farther than the support from every point of the box cannot
@@ -296,12 +330,7 @@ struct Cand64 {
 
 // ------------------------------------------------------------------ density
 
-__device__ __forceinline__ double wave_sum_f64(double v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
+__device__ __forceinline__ double wave_sum_f64(double v) { return wave_reduce(v, 0.0, OpAdd{}); }
 
 // A cell's particles are served 64 per wavefront pass ("lane mode": lane =
 // target).  When a cell holds a little more than a multiple of 64 (common at
@@ -439,9 +468,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                     uint32_t mine = 0;
 #pragma unroll
                     for (int q = 0; q < kScWords; ++q) mine += (uint32_t)__popcll(mw[q]);
-#pragma unroll
-                    for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
-                    witer += mine;
+                    witer += wave_reduce(mine, 0u, OpMax{});
                 }
                 // kernel sum over this lane's neighbours among the staged
                 // candidates, in units of alpha/6
@@ -576,6 +603,23 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
     fz = fma(sp, dz, fma(sv, mv.z - cv.z, fz));
 }
 
+// Pair forces of one lane's hits among the staged candidates (walking its
+// hit words).  KIN = false when no lane of the wavefront serves a kinematic
+// boundary particle: the target-side pressure mirroring then drops out.
+template <typename T, bool KIN>
+__device__ __forceinline__ void walk_forces(uint64_t (&mw)[kScWords], const V4<T> &me, const V4<T> &mv,
+                                            const V2<T> &md, bool kin, T ma, const V4<T> *cp, const V4<T> *cvel,
+                                            const V2<T> *cden, const Phys<T> &ph, T &cx, T &cy, T &cz)
+{
+    int base = 0;
+    for (;;) {
+        skip_empty_word(mw, base);
+        if (mw[0] == 0ull) break;
+        const int k = take_hit(mw, base);
+        pair_force<T>(me, mv, md.x, md.y, KIN && kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
+    }
+}
+
 // Force on a lane-mode or transposed-mode target from its accumulated pair
 // sum: fluid/soft add gravity and springs; kinematic boundary particles keep
 // the reaction for the body wrench.
@@ -649,6 +693,7 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
         const bool kin = act && aux_kin(aux);
         const bool tgt = fs || kin;
         const bool lanes_any = __ballot(tgt) != 0ull;
+        const bool wave_kin = __ballot(kin) != 0ull;
         if (!lanes_any && !with_left) continue;
         if (with_left && lane < 3u * nleft) accf[lane / 3u][lane % 3u] = 0.0;
         const T ma = fabs(me.w);
@@ -711,19 +756,14 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
                     uint32_t mine = 0;
 #pragma unroll
                     for (int q = 0; q < kScWords; ++q) mine += (uint32_t)__popcll(mw[q]);
-#pragma unroll
-                    for (int m = 32; m >= 1; m >>= 1) mine = max(mine, (uint32_t)__shfl_xor(mine, m, 64));
-                    witer += mine;
+                    witer += wave_reduce(mine, 0u, OpMax{});
                 }
                 // a super-chunk holds ~1/S of the neighbours: sum it in T, then in FP64
                 T cx = (T)0, cy = (T)0, cz = (T)0;
-                int base = 0;
-                for (;;) {
-                    skip_empty_word(mw, base);
-                    if (mw[0] == 0ull) break;
-                    const int k = take_hit(mw, base);
-                    pair_force<T>(me, mv, md.x, md.y, kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
-                }
+                if (wave_kin)
+                    walk_forces<T, true>(mw, me, mv, md, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
+                else
+                    walk_forces<T, false>(mw, me, mv, md, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
                 fx += (double)cx;
                 fy += (double)cy;
                 fz += (double)cz;
@@ -749,12 +789,9 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
                                               cx, cy, cz);
                         }
                     }
-#pragma unroll
-                    for (int m = 32; m >= 1; m >>= 1) {
-                        cx += __shfl_xor(cx, m, 64);
-                        cy += __shfl_xor(cy, m, 64);
-                        cz += __shfl_xor(cz, m, 64);
-                    }
+                    cx = wave_reduce(cx, (T)0, OpAdd{});
+                    cy = wave_reduce(cy, (T)0, OpAdd{});
+                    cz = wave_reduce(cz, (T)0, OpAdd{});
                     if (lane == 0) {
                         accf[t][0] += (double)cx;
                         accf[t][1] += (double)cy;
