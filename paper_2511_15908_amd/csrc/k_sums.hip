@@ -340,10 +340,10 @@ __device__ __forceinline__ double wave_sum_f64(double v) { return wave_reduce(v,
 // "transposed mode" (lane = candidate, one target at a time, ballot = the
 // target's hit word), which costs about 1/20 of a pass per target.
 #ifndef SPH_LEFT_DENSITY
-#define SPH_LEFT_DENSITY 24
+#define SPH_LEFT_DENSITY 8
 #endif
 #ifndef SPH_LEFT_FORCE
-#define SPH_LEFT_FORCE 12
+#define SPH_LEFT_FORCE 6
 #endif
 constexpr uint32_t kLeftD = SPH_LEFT_DENSITY;   // most leftover targets of the density pass
 constexpr uint32_t kLeftF = SPH_LEFT_FORCE;     // of the force pass
@@ -568,10 +568,13 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
 // particles exert nothing.  Every factor is symmetric in (a, c) and the
 // vector factors are antisymmetric, so the force c computes on itself from a
 // is the exact IEEE negation.
-template <typename T>
-__device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T rho_a, T P_a, bool isBa, T ma,
-                                           const V4<T> &c, const V4<T> &cv, const V2<T> &cd, const Phys<T> &ph,
-                                           T &fx, T &fy, T &fz)
+// P_mir is the pressure a boundary partner takes from this particle: P_a,
+// or 0 with the single-boundary-term flag.  KIN = false: particle a is not a
+// boundary particle; PLAIN: neither boundary flag (2, 4) is set.
+template <typename T, bool KIN, bool PLAIN>
+__device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T rho_a, T P_a, T P_mir, bool isBa,
+                                           T ma, const V4<T> &c, const V4<T> &cv, const V2<T> &cd,
+                                           const Phys<T> &ph, T &fx, T &fy, T &fz)
 {
     const T dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
     const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
@@ -582,22 +585,27 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
     const T g = ((ph.gch * fma((T)2, t1, -t2)) * fma((T)2, t1, t2)) * rs;
     const bool isBc = c.w < (T)0;
     const T mc = fabs(c.w);
-    T Pa = isBa ? cd.y : P_a;
-    T Pc = isBc ? P_a : cd.y;
-    const T ra = isBa ? cd.x : rho_a;
+    const T Pc = isBc ? P_mir : cd.y;
     const T rc = isBc ? rho_a : cd.x;
-    if (ph.flags & 2u) {   // single boundary pressure term
-        Pa = isBa ? (T)0 : Pa;
-        Pc = isBc ? (T)0 : Pc;
+    T Pa = P_a, ra = rho_a;
+    if (KIN) {
+        const T Pb = (!PLAIN && (ph.flags & 2u)) ? (T)0 : cd.y;
+        Pa = isBa ? Pb : P_a;
+        ra = isBa ? cd.x : rho_a;
     }
     const T mm = ma * mc;
     T sp = -(mm * (Pa + Pc)) * g;
     // 2 nu m_a m_c [2/(rho_a+rho_c)] g r^2/(r^2+eps), one reciprocal
     T sv = ((ph.two_nu * mm) * g) * (((T)2 * r2) * frcp((ra + rc) * (r2 + ph.eps)));
-    const bool bb = isBa && isBc;
-    const bool novisc = bb || ((ph.flags & 4u) && (isBa || isBc));
-    sp = bb ? (T)0 : sp;
-    sv = novisc ? (T)0 : sv;
+    if (KIN) {
+        const bool bb = isBa && isBc;
+        sp = bb ? (T)0 : sp;
+        sv = bb ? (T)0 : sv;
+    }
+    if (!PLAIN) {
+        const bool novisc = (ph.flags & 4u) && (isBa || isBc);
+        sv = novisc ? (T)0 : sv;
+    }
     fx = fma(sp, dx, fma(sv, mv.x - cv.x, fx));
     fy = fma(sp, dy, fma(sv, mv.y - cv.y, fy));
     fz = fma(sp, dz, fma(sv, mv.z - cv.z, fz));
@@ -606,17 +614,18 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
 // Pair forces of one lane's hits among the staged candidates (walking its
 // hit words).  KIN = false when no lane of the wavefront serves a kinematic
 // boundary particle: the target-side pressure mirroring then drops out.
-template <typename T, bool KIN>
+template <typename T, bool KIN, bool PLAIN>
 __device__ __forceinline__ void walk_forces(uint64_t (&mw)[kScWords], const V4<T> &me, const V4<T> &mv,
-                                            const V2<T> &md, bool kin, T ma, const V4<T> *cp, const V4<T> *cvel,
-                                            const V2<T> *cden, const Phys<T> &ph, T &cx, T &cy, T &cz)
+                                            const V2<T> &md, T P_mir, bool kin, T ma, const V4<T> *cp,
+                                            const V4<T> *cvel, const V2<T> *cden, const Phys<T> &ph, T &cx, T &cy,
+                                            T &cz)
 {
     int base = 0;
     for (;;) {
         skip_empty_word(mw, base);
         if (mw[0] == 0ull) break;
         const int k = take_hit(mw, base);
-        pair_force<T>(me, mv, md.x, md.y, KIN && kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
+        pair_force<T, KIN, PLAIN>(me, mv, md.x, md.y, P_mir, kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
     }
 }
 
@@ -760,10 +769,11 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
                 }
                 // a super-chunk holds ~1/S of the neighbours: sum it in T, then in FP64
                 T cx = (T)0, cy = (T)0, cz = (T)0;
-                if (wave_kin)
-                    walk_forces<T, true>(mw, me, mv, md, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
+                const T P_mir = (ph.flags & 2u) ? (T)0 : md.y;
+                if (wave_kin || (ph.flags & 6u))
+                    walk_forces<T, true, false>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
                 else
-                    walk_forces<T, false>(mw, me, mv, md, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
+                    walk_forces<T, false, true>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
                 fx += (double)cx;
                 fy += (double)cy;
                 fz += (double)cz;
@@ -785,8 +795,9 @@ __global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T>
                             const uint64_t m = masks[(size_t)(w0 + q) * n + pt];
                             const uint32_t v = q * kWave + lane;
                             if ((m >> lane) & 1ull)
-                                pair_force<T>(mt, mvt, mdt.x, mdt.y, kin_t, fabs(mt.w), cp[v], cvel[v], cden[v], ph,
-                                              cx, cy, cz);
+                                pair_force<T, true, false>(mt, mvt, mdt.x, mdt.y, (ph.flags & 2u) ? (T)0 : mdt.y,
+                                                           kin_t, fabs(mt.w), cp[v], cvel[v], cden[v], ph, cx, cy,
+                                                           cz);
                         }
                     }
                     cx = wave_reduce(cx, (T)0, OpAdd{});

@@ -192,15 +192,22 @@ def train(net, X, Y, steps, batch=4096, lr0=1e-3, lr1=1e-5, seed=1, holdout=None
     return hist
 
 
-def evaluate(net, log, scene):
+def evaluate(net, logs, scene):
     """Errors of the surrogate and of the two baselines on the ticks between
-    SPH updates (d > 0), against the plain-SPH haptic wrench at every tick."""
-    t, d, (X, Y) = eval_rows(log)
-    truth = Y.astype(np.float64)
-    zoh, avg = baselines(log, t, d)
+    SPH updates (d > 0), against the plain-SPH haptic wrench at every tick;
+    `logs` is one log or a list, whose ticks are pooled."""
+    if isinstance(logs, dict):
+        logs = [logs]
+    errs = {"surrogate": [], "zero_order_hold": [], "hold_rolling_mean": []}
+    for log in logs:
+        t, d, (X, Y) = eval_rows(log)
+        truth = Y.astype(np.float64)
+        zoh, avg = baselines(log, t, d)
+        for name, p in (("surrogate", predict(net, X)), ("zero_order_hold", zoh), ("hold_rolling_mean", avg)):
+            errs[name].append(wrench_errors(p, truth, scene)[d > 0])
     out = {}
-    for name, p in (("surrogate", predict(net, X)), ("zero_order_hold", zoh), ("hold_rolling_mean", avg)):
-        e = wrench_errors(p, truth, scene)[d > 0]
+    for name, parts in errs.items():
+        e = np.concatenate(parts)
         out[name] = {"mean": float(e.mean()), "p50": float(np.median(e)), "p95": float(np.percentile(e, 95)),
                      "max": float(e.max())}
     return out
@@ -230,10 +237,12 @@ def haptic_rate(net, X, n=500):
 
 
 def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=1500, steps=1500, seed=1,
-                   warmup_ticks=300, log=print):
+                   warmup_ticks=300, eval_segments=3, log=print):
     """Collect plain-SPH haptic logs (a 1 kHz smooth walk per segment, 4 SPH
     steps per tick), train on the first segments with early stopping on a
-    held-out segment, evaluate on a last one.  Returns a summary dict."""
+    held-out segment, evaluate on the last `eval_segments` (pooled: a single
+    walk's smoothness swings the hold baseline's error several-fold).
+    Returns a summary dict."""
     import time
     import torch
     sc = scenes.haptic_scene(n_fluid=n_fluid)
@@ -242,7 +251,7 @@ def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=150
     c = sc.info["c0"]
     logs = []
     segs = [(warmup_ticks, 11)] + [(ticks, 101 + i) for i in range(train_segments)] + \
-        [(eval_ticks, 901), (eval_ticks, 902)]
+        [(eval_ticks, 801)] + [(eval_ticks, 901 + i) for i in range(eval_segments)]
     t0 = time.perf_counter()
     for n, sd in segs:
         walk = scenes.smooth_walk(sd, n, c, lo, hi)
@@ -255,10 +264,11 @@ def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=150
     Y = torch.from_numpy(np.concatenate([r[1] for r in rows])).to("cuda")
     net = make_net(seed=seed)
     t0 = time.perf_counter()
-    hist = train(net, X, Y, steps, seed=seed, holdout=(logs[-2], sc))
+    hold = logs[1 + train_segments]
+    hist = train(net, X, Y, steps, seed=seed, holdout=(hold, sc))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    errs = evaluate(net, logs[-1], sc)
+    errs = evaluate(net, logs[2 + train_segments:], sc)
     rate = haptic_rate(net, eval_rows(logs[-1])[2][0])
     return {"scene": sc.name, "n_particles": int(sc.n), "training_rows": int(X.shape[0]),
             "ticks_collected": int(sum(n for n, _ in segs)), "collect_s": t_collect, "train_s": t_train,
