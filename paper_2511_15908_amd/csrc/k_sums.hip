@@ -334,6 +334,40 @@ struct Cand64 {
     double x, y, z, m;
 };
 
+// A pass whose cell part holds at most 32 targets (fluid, soft or kinematic
+// particles) is served with two lanes per target: lanes r and r + 32 take the
+// r-th target, each walking alternate bits of its hit words (even slots for
+// the lower half, odd for the upper), and the two partial sums are added at
+// the end of the pass; only the lower lane stores.  Halves the neighbour
+// loop of cells at walls and at the free surface.
+struct SplitPass {
+    bool split;      // uniform
+    bool lead;       // this lane stores (lower half, or every lane when not split)
+    uint64_t bits;   // hit bits this lane walks
+};
+
+__device__ __forceinline__ SplitPass split_pass(bool target, bool with_left, uint32_t lane, uint32_t t0, uint32_t e0,
+                                               uint32_t s0, const uint32_t *__restrict__ auxv, uint8_t *tmap,
+                                               uint32_t &p, bool &act, uint32_t &pc, uint32_t &aux)
+{
+    const uint64_t tb = __ballot(target);
+    const uint32_t nt = (uint32_t)__popcll(tb);
+    SplitPass sp{false, true, ~0ull};
+    if (with_left || nt == 0u || nt > 32u) return sp;
+    __syncthreads();                      // the previous pass's readers of tmap are done
+    if (target) tmap[lanes_below(tb, lane)] = (uint8_t)lane;
+    __syncthreads();
+    const uint32_t r = lane & 31u;
+    act = r < nt;
+    p = act ? t0 + tmap[r] : e0;
+    pc = act ? p : s0;
+    aux = act ? auxv[pc] : 0u;
+    sp.split = true;
+    sp.lead = lane < 32u;
+    sp.bits = sp.lead ? 0x5555555555555555ull : 0xAAAAAAAAAAAAAAAAull;
+    return sp;
+}
+
 // ------------------------------------------------------------------ density
 
 __device__ __forceinline__ double wave_sum_f64(double v) { return wave_reduce(v, 0.0, OpAdd{}); }
@@ -391,14 +425,18 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
     // (kept in LDS by lane 0 rather than in registers)
     __shared__ unsigned long long cstat[5];
     if (lane < 5u) cstat[lane] = 0ull;
+    __shared__ uint8_t tmap[kWave];
     for (uint32_t ch = 0; ch < nlane; ++ch) {
         const uint32_t t0 = s0 + kWave * ch;
         const bool with_left = (ch + 1 == nlane) && nleft;
-        const uint32_t p = t0 + lane;
-        const bool act = p < e0;
-        const uint32_t pc = act ? p : s0;
+        uint32_t p = t0 + lane;
+        bool act = p < e0;
+        uint32_t pc = act ? p : s0;
+        uint32_t aux = act ? st.aux[pc] : 0u;
+        // a pass with at most 32 targets is split: two lanes per target
+        const SplitPass sp = split_pass(act && (aux_type(aux) != TY_BOUNDARY || aux_kin(aux)), with_left, lane,
+                                        t0, e0, s0, st.aux, tmap, p, act, pc, aux);
         V4<T> me = st.pos[pc];
-        const uint32_t aux = act ? st.aux[pc] : 0u;
         me.x = act ? me.x : inf;
         me.y = act ? me.y : inf;
         me.z = act ? me.z : inf;
@@ -465,10 +503,10 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                     if ((uint32_t)q < nws) {
                         const uint32_t nv = size > (uint32_t)q * kWave ? min(size - (uint32_t)q * kWave, (uint32_t)kWave) : 0u;
                         m = hit_word<T>(me, cand + q * kWave, nv, R2);
-                        if (act) masks[(size_t)(w0 + q) * n + p] = m;
-                        npair += want ? (uint32_t)__popcll(m) : 0u;
+                        if (act && sp.lead) masks[(size_t)(w0 + q) * n + p] = m;
+                        npair += (want && sp.lead) ? (uint32_t)__popcll(m) : 0u;
                     }
-                    mw[q] = fs ? m : 0ull;
+                    mw[q] = fs ? (m & sp.bits) : 0ull;
                 }
                 {
                     uint32_t mine = 0;
@@ -534,7 +572,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                 cstat[4] += witer;
             }
         }
-        if (act) {
+        if (sp.split) acc += __shfl_xor(acc, 32, 64);
+        if (act && sp.lead) {
             V2<T> d{(T)0, (T)0};
             if (fs) {
                 const double rho = ph.alpha6_64 * acc;
@@ -694,16 +733,19 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
     const uint32_t left0 = s0 + kWave * nlane;
     __shared__ unsigned long long cstat;   // neighbour-loop iterations of the cell
     if (lane == 0) cstat = 0ull;
+    __shared__ uint8_t tmap[kWave];
     for (uint32_t ch = 0; ch < nlane; ++ch) {
         const uint32_t t0 = s0 + kWave * ch;
         const bool with_left = (ch + 1 == nlane) && nleft;
-        const uint32_t p = t0 + lane;
-        const bool act = p < e0;
-        const uint32_t pc = act ? p : s0;
+        uint32_t p = t0 + lane;
+        bool act = p < e0;
+        uint32_t pc = act ? p : s0;
+        uint32_t aux = act ? st.aux[pc] : 0u;
+        const SplitPass sp = split_pass(act && (aux_type(aux) != TY_BOUNDARY || aux_kin(aux)), with_left, lane,
+                                        t0, e0, s0, st.aux, tmap, p, act, pc, aux);
         const V4<T> me = st.pos[pc];
         const V4<T> mv = st.vel[pc];
         const V2<T> md = dens[pc];
-        const uint32_t aux = act ? st.aux[pc] : 0u;
         const bool fs = act && aux_type(aux) != TY_BOUNDARY;
         const bool kin = act && aux_kin(aux);
         const bool tgt = fs || kin;
@@ -763,7 +805,7 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
             for (int q = 0; q < kScWords; ++q) {
                 uint64_t m = 0;
                 if ((uint32_t)q < nws && tgt) m = masks[(size_t)(w0 + q) * n + p];
-                mw[q] = m;
+                mw[q] = m & sp.bits;
             }
             __syncthreads();
             if (lanes_any) {
@@ -819,7 +861,12 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
             __syncthreads();
         }
         if (lane == 0) cstat += witer;
-        if (tgt) store_force<T>(p, aux, ma, fx, fy, fz, ph, fspring, force, fbody);
+        if (sp.split) {
+            fx += __shfl_xor(fx, 32, 64);
+            fy += __shfl_xor(fy, 32, 64);
+            fz += __shfl_xor(fz, 32, 64);
+        }
+        if (tgt && sp.lead) store_force<T>(p, aux, ma, fx, fy, fz, ph, fspring, force, fbody);
         if (with_left && lane < nleft) {
             const uint32_t pt = left0 + lane;
             const uint32_t at = st.aux[pt];
