@@ -516,13 +516,24 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                 }
                 // kernel sum over this lane's neighbours among the staged
                 // candidates, in units of alpha/6
-                int base = 0;
-                for (;;) {
-                    skip_empty_word(mw, base);
-                    if (mw[0] == 0ull) break;
-                    const int k = take_hit(mw, base);
-                    const Cand64 c = cand64[k];
-                    acc = fma(c.m, spline_shape64(c.x - mx, c.y - my, c.z - mz, ph.inv_h64), acc);
+                if (size <= (uint32_t)kWave) {
+                    // one word holds the whole (culled) super-chunk: no word moves
+                    uint64_t m = mw[0];
+                    while (m) {
+                        const int k = (int)__builtin_ctzll(m);
+                        m &= m - 1ull;
+                        const Cand64 c = cand64[k];
+                        acc = fma(c.m, spline_shape64(c.x - mx, c.y - my, c.z - mz, ph.inv_h64), acc);
+                    }
+                } else {
+                    int base = 0;
+                    for (;;) {
+                        skip_empty_word(mw, base);
+                        if (mw[0] == 0ull) break;
+                        const int k = take_hit(mw, base);
+                        const Cand64 c = cand64[k];
+                        acc = fma(c.m, spline_shape64(c.x - mx, c.y - my, c.z - mz, ph.inv_h64), acc);
+                    }
                 }
             }
             if (with_left) {
@@ -659,12 +670,22 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
 // Pair forces of one lane's hits among the staged candidates (walking its
 // hit words).  KIN = false when no lane of the wavefront serves a kinematic
 // boundary particle: the target-side pressure mirroring then drops out.
-template <typename T, bool KIN, bool PLAIN>
+// ONE: the staged super-chunk fits one word (no word moves).
+template <typename T, bool KIN, bool PLAIN, bool ONE>
 __device__ __forceinline__ void walk_forces(uint64_t (&mw)[kScWords], const V4<T> &me, const V4<T> &mv,
                                             const V2<T> &md, T P_mir, bool kin, T ma, const V4<T> *cp,
                                             const V4<T> *cvel, const V2<T> *cden, const Phys<T> &ph, T &cx, T &cy,
                                             T &cz)
 {
+    if (ONE) {
+        uint64_t m = mw[0];
+        while (m) {
+            const int k = (int)__builtin_ctzll(m);
+            m &= m - 1ull;
+            pair_force<T, KIN, PLAIN>(me, mv, md.x, md.y, P_mir, kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
+        }
+        return;
+    }
     int base = 0;
     for (;;) {
         skip_empty_word(mw, base);
@@ -818,10 +839,20 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                 // a super-chunk holds ~1/S of the neighbours: sum it in T, then in FP64
                 T cx = (T)0, cy = (T)0, cz = (T)0;
                 const T P_mir = (ph.flags & 2u) ? (T)0 : md.y;
-                if (wave_kin || (ph.flags & 6u))
-                    walk_forces<T, true, false>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
-                else
-                    walk_forces<T, false, true>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
+                const bool one = size <= (uint32_t)kWave;
+                if (wave_kin || (ph.flags & 6u)) {
+                    if (one)
+                        walk_forces<T, true, false, true>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
+                    else
+                        walk_forces<T, true, false, false>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy,
+                                                           cz);
+                } else {
+                    if (one)
+                        walk_forces<T, false, true, true>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
+                    else
+                        walk_forces<T, false, true, false>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy,
+                                                           cz);
+                }
                 fx += (double)cx;
                 fy += (double)cy;
                 fz += (double)cz;
