@@ -214,10 +214,13 @@ void launch_clear_u32(hipStream_t s, uint32_t *p, size_t count)
 // ---------------------------------------------------------------- reorder + cell table
 
 template <typename T>
+// Static boundary particles get density and force 0 in their new slot here:
+// the neighbour passes never write them (a slot's previous particle may have).
 __global__ __launch_bounds__(256) void k_reorder(uint32_t n, const uint32_t *__restrict__ perm,
                                                  const uint32_t *__restrict__ keys, State<T> in, State<T> out,
                                                  uint32_t *__restrict__ inv_perm, uint32_t *__restrict__ cstart,
-                                                 uint32_t *__restrict__ cend)
+                                                 uint32_t *__restrict__ cend, V2<T> *__restrict__ dens,
+                                                 V4<T> *__restrict__ force)
 {
     uint32_t p = blockIdx.x * 256u + threadIdx.x;
     if (p >= n) return;
@@ -226,7 +229,12 @@ __global__ __launch_bounds__(256) void k_reorder(uint32_t n, const uint32_t *__r
     out.vel[p] = in.vel[j];
     const uint32_t id = in.id[j];
     out.id[p] = id;
-    out.aux[p] = in.aux[j];
+    const uint32_t aux = in.aux[j];
+    out.aux[p] = aux;
+    if (aux_type(aux) == TY_BOUNDARY && !aux_kin(aux)) {
+        dens[p] = V2<T>{(T)0, (T)0};
+        force[p] = V4<T>{(T)0, (T)0, (T)0, (T)0};
+    }
     inv_perm[id] = p;
     const uint32_t k = keys[p];
     if (p == 0 || keys[p - 1] != k) cstart[k] = p;
@@ -235,16 +243,16 @@ __global__ __launch_bounds__(256) void k_reorder(uint32_t n, const uint32_t *__r
 
 template <typename T>
 void launch_reorder(hipStream_t s, uint32_t n, const uint32_t *perm, const uint32_t *keys, State<T> in,
-                    State<T> out, uint32_t *inv_perm, uint32_t *cstart, uint32_t *cend)
+                    State<T> out, uint32_t *inv_perm, uint32_t *cstart, uint32_t *cend, V2<T> *dens, V4<T> *force)
 {
     if (!n) return;
     hipLaunchKernelGGL(k_reorder<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, keys, in, out, inv_perm,
-                       cstart, cend);
+                       cstart, cend, dens, force);
 }
 template void launch_reorder<float>(hipStream_t, uint32_t, const uint32_t *, const uint32_t *, State<float>,
-                                    State<float>, uint32_t *, uint32_t *, uint32_t *);
+                                    State<float>, uint32_t *, uint32_t *, uint32_t *, V2<float> *, V4<float> *);
 template void launch_reorder<double>(hipStream_t, uint32_t, const uint32_t *, const uint32_t *, State<double>,
-                                     State<double>, uint32_t *, uint32_t *, uint32_t *);
+                                     State<double>, uint32_t *, uint32_t *, uint32_t *, V2<double> *, V4<double> *);
 
 // ---------------------------------------------------------------- boundary volumes (init only)
 

@@ -433,7 +433,9 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         bool act = p < e0;
         uint32_t pc = act ? p : s0;
         uint32_t aux = act ? st.aux[pc] : 0u;
-        // a pass with at most 32 targets is split: two lanes per target
+        // a pass with at most 32 targets is split: two lanes per target (no
+        // lane then serves the cell's static boundary particles, whose density
+        // and force the reorder has already set to 0)
         const SplitPass sp = split_pass(act && (aux_type(aux) != TY_BOUNDARY || aux_kin(aux)), with_left, lane,
                                         t0, e0, s0, st.aux, tmap, p, act, pc, aux);
         V4<T> me = st.pos[pc];

@@ -644,7 +644,7 @@ void neighbour_search(sph_ctx *c)
     launch_clear_u32(c->stream, c->cstart, c->nslots);
     launch_clear_u32(c->stream, c->cend, c->nslots);
     launch_reorder<T>(c->stream, n, c->sorted_vals, c->sorted_keys, state<T>(c, c->cur), state<T>(c, 1 - c->cur),
-                      c->inv_perm, c->cstart, c->cend);
+                      c->inv_perm, c->cstart, c->cend, (V2<T> *)c->dens, (V4<T> *)c->force);
     c->cur = 1 - c->cur;
     prof_mark(c, 3, false);
 }

@@ -266,7 +266,8 @@ void launch_radix_sort(hipStream_t s, uint32_t n, int key_bits, Sort &st, uint32
 void launch_clear_u32(hipStream_t s, uint32_t *p, size_t count);
 template <typename T>
 void launch_reorder(hipStream_t s, uint32_t n, const uint32_t *perm, const uint32_t *keys,
-                    State<T> in, State<T> out, uint32_t *inv_perm, uint32_t *cstart, uint32_t *cend);
+                    State<T> in, State<T> out, uint32_t *inv_perm, uint32_t *cstart, uint32_t *cend,
+                    V2<T> *dens, V4<T> *force);
 template <typename T>
 void launch_psi_obj(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, const uint32_t *cstart,
                     const uint32_t *cend, const int32_t *obj_of_id);

@@ -198,3 +198,19 @@ def test_fluid_only_no_boundary(gpu, orc):
     sc.object_kinematic = np.zeros(0, np.uint8)
     sc.object_pose0 = np.zeros((0, 7))
     _compare_one_step(gpu, orc, sc, "f32", 1e-5, 1e-4)
+
+
+def test_static_boundary_fields_stay_zero(gpu):
+    """Each step's sort moves sorted slots between particles, and a pass with
+    at most 32 targets serves none of the cell's static boundary particles;
+    these must still read rho = 0 and force = 0 (the field contract) after
+    many steps of a collapsing column."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.dam_break(precision="f32")
+    sim = gpu.Sim(sc)
+    sim.step(60)
+    kin = np.nonzero(sc.object_kinematic)[0]
+    static = np.nonzero((sc.type == 2) & ~np.isin(sc.object, kin))[0]
+    assert static.size
+    assert np.all(sim.read("rho")[static] == 0)
+    assert np.all(sim.read("f")[static] == 0)
