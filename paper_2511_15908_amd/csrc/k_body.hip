@@ -315,11 +315,13 @@ template void launch_probe<double>(hipStream_t, const ProbeArgs &, State<double>
 
 // ------------------------------------------------------------------ springs
 
+// One thread per spring row; 64-thread blocks spread the few thousand rows
+// over many CUs (the loop is a chain of dependent gathers).
 template <typename T>
-__global__ __launch_bounds__(256) void k_springs(SpringArgs a, const uint32_t *__restrict__ inv_perm, State<T> st,
-                                                 V4<T> *__restrict__ fspring)
+__global__ __launch_bounds__(64) void k_springs(SpringArgs a, const uint32_t *__restrict__ inv_perm, State<T> st,
+                                                V4<T> *__restrict__ fspring)
 {
-    const uint32_t r = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t r = blockIdx.x * 64u + threadIdx.x;
     if (r >= a.rows) return;
     const uint32_t i = inv_perm[a.row_id[r]];
     const V4<T> xi = st.pos[i], vi = st.vel[i];
@@ -331,7 +333,8 @@ __global__ __launch_bounds__(256) void k_springs(SpringArgs a, const uint32_t *_
         const double d1 = (double)xi.y - (double)xj.y;
         const double d2 = (double)xi.z - (double)xj.z;
         const double len = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double e0 = d0 / len, e1 = d1 / len, e2 = d2 / len;
+        const double il = 1.0 / len;
+        const double e0 = d0 * il, e1 = d1 * il, e2 = d2 * il;
         const double vr = ((double)vi.x - (double)vj.x) * e0 + ((double)vi.y - (double)vj.y) * e1 +
                           ((double)vi.z - (double)vj.z) * e2;
         const double *pr = a.prm + 3u * e;
@@ -347,7 +350,7 @@ template <typename T>
 void launch_springs(hipStream_t s, const SpringArgs &a, const uint32_t *inv_perm, State<T> st, V4<T> *fspring)
 {
     if (!a.rows) return;
-    hipLaunchKernelGGL(k_springs<T>, dim3((a.rows + 255) / 256), dim3(256), 0, s, a, inv_perm, st, fspring);
+    hipLaunchKernelGGL(k_springs<T>, dim3((a.rows + 63) / 64), dim3(64), 0, s, a, inv_perm, st, fspring);
 }
 template void launch_springs<float>(hipStream_t, const SpringArgs &, const uint32_t *, State<float>, V4<float> *);
 template void launch_springs<double>(hipStream_t, const SpringArgs &, const uint32_t *, State<double>,

@@ -641,10 +641,12 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
     const T t1 = max((T)1 - q, (T)0);
     const T t2 = max((T)2 - q, (T)0);
     const T g = ((ph.gch * fma((T)2, t1, -t2)) * fma((T)2, t1, t2)) * rs;
-    const bool isBc = c.w < (T)0;
+    // cv.w is 1 for a boundary candidate (0 otherwise), whose staged density
+    // and pressure term are 0: the mirrored values enter by one FMA each
+    const bool isBc = cv.w != (T)0;
     const T mc = fabs(c.w);
-    const T Pc = isBc ? P_mir : cd.y;
-    const T rc = isBc ? rho_a : cd.x;
+    const T Pc = fma(cv.w, P_mir, cd.y);
+    const T rc = fma(cv.w, rho_a, cd.x);
     T Pa = P_a, ra = rho_a;
     if (KIN) {
         const T Pb = (!PLAIN && (ph.flags & 2u)) ? (T)0 : cd.y;
@@ -653,8 +655,9 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
     }
     const T mm = ma * mc;
     T sp = -(mm * (Pa + Pc)) * g;
-    // 2 nu m_a m_c [2/(rho_a+rho_c)] g r^2/(r^2+eps), one reciprocal
-    T sv = ((ph.two_nu * mm) * g) * (((T)2 * r2) * frcp((ra + rc) * (r2 + ph.eps)));
+    // 2 nu m_a m_c [2/(rho_a+rho_c)] g r^2/(r^2+eps), one reciprocal (the
+    // factor 2 of 2 r^2 rides on the uniform 2 nu: scaling by 2 is exact)
+    T sv = (((ph.two_nu * (T)2) * mm) * g) * (r2 * frcp((ra + rc) * (r2 + ph.eps)));
     if (KIN) {
         const bool bb = isBa && isBc;
         sp = bb ? (T)0 : sp;
@@ -816,7 +819,9 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                 if (keep) {
                     const uint32_t o = size + lanes_below(km, lane);
                     cp[o] = c;
-                    cvel[o] = st.vel[j];
+                    V4<T> cv = st.vel[j];
+                    cv.w = c.w < (T)0 ? (T)1 : (T)0;    // boundary flag for the pair loop
+                    cvel[o] = cv;
                     cden[o] = dens[j];
                 }
                 size += (uint32_t)__popcll(km);
