@@ -315,42 +315,52 @@ template void launch_probe<double>(hipStream_t, const ProbeArgs &, State<double>
 
 // ------------------------------------------------------------------ springs
 
-// One thread per spring row; 64-thread blocks spread the few thousand rows
-// over many CUs (the loop is a chain of dependent gathers).
+// Half a wavefront (32 lanes) per spring row, one spring per lane (rows
+// longer than 32 loop), the row's sum by a fixed butterfly: the gathers of a
+// row are in flight together instead of one after another.
 template <typename T>
 __global__ __launch_bounds__(64) void k_springs(SpringArgs a, const uint32_t *__restrict__ inv_perm, State<T> st,
                                                 V4<T> *__restrict__ fspring)
 {
-    const uint32_t r = blockIdx.x * 64u + threadIdx.x;
-    if (r >= a.rows) return;
-    const uint32_t i = inv_perm[a.row_id[r]];
-    const V4<T> xi = st.pos[i], vi = st.vel[i];
+    const uint32_t r = blockIdx.x * 2u + (threadIdx.x >> 5);
+    const uint32_t l = threadIdx.x & 31u;
+    const bool row = r < a.rows;
     double f[3] = {0.0, 0.0, 0.0};
-    for (uint32_t e = a.row_ptr[r]; e < a.row_ptr[r + 1]; ++e) {
-        const uint32_t j = inv_perm[a.partner[e]];
-        const V4<T> xj = st.pos[j], vj = st.vel[j];
-        const double d0 = (double)xi.x - (double)xj.x;
-        const double d1 = (double)xi.y - (double)xj.y;
-        const double d2 = (double)xi.z - (double)xj.z;
-        const double len = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double il = 1.0 / len;
-        const double e0 = d0 * il, e1 = d1 * il, e2 = d2 * il;
-        const double vr = ((double)vi.x - (double)vj.x) * e0 + ((double)vi.y - (double)vj.y) * e1 +
-                          ((double)vi.z - (double)vj.z) * e2;
-        const double *pr = a.prm + 3u * e;
-        const double mag = pr[1] * (len - pr[0]) + pr[2] * vr;
-        f[0] -= mag * e0;
-        f[1] -= mag * e1;
-        f[2] -= mag * e2;
+    if (row) {
+        const uint32_t i = inv_perm[a.row_id[r]];
+        const V4<T> xi = st.pos[i], vi = st.vel[i];
+        for (uint32_t e = a.row_ptr[r] + l; e < a.row_ptr[r + 1]; e += 32u) {
+            const uint32_t j = inv_perm[a.partner[e]];
+            const V4<T> xj = st.pos[j], vj = st.vel[j];
+            const double d0 = (double)xi.x - (double)xj.x;
+            const double d1 = (double)xi.y - (double)xj.y;
+            const double d2 = (double)xi.z - (double)xj.z;
+            const double len = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double il = 1.0 / len;
+            const double e0 = d0 * il, e1 = d1 * il, e2 = d2 * il;
+            const double vr = ((double)vi.x - (double)vj.x) * e0 + ((double)vi.y - (double)vj.y) * e1 +
+                              ((double)vi.z - (double)vj.z) * e2;
+            const double *pr = a.prm + 3u * e;
+            const double mag = pr[1] * (len - pr[0]) + pr[2] * vr;
+            f[0] -= mag * e0;
+            f[1] -= mag * e1;
+            f[2] -= mag * e2;
+        }
     }
-    fspring[r] = V4<T>{(T)f[0], (T)f[1], (T)f[2], (T)0};
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) {
+        f[0] += __shfl_xor(f[0], m, 32);
+        f[1] += __shfl_xor(f[1], m, 32);
+        f[2] += __shfl_xor(f[2], m, 32);
+    }
+    if (row && l == 0) fspring[r] = V4<T>{(T)f[0], (T)f[1], (T)f[2], (T)0};
 }
 
 template <typename T>
 void launch_springs(hipStream_t s, const SpringArgs &a, const uint32_t *inv_perm, State<T> st, V4<T> *fspring)
 {
     if (!a.rows) return;
-    hipLaunchKernelGGL(k_springs<T>, dim3((a.rows + 63) / 64), dim3(64), 0, s, a, inv_perm, st, fspring);
+    hipLaunchKernelGGL(k_springs<T>, dim3((a.rows + 1) / 2), dim3(64), 0, s, a, inv_perm, st, fspring);
 }
 template void launch_springs<float>(hipStream_t, const SpringArgs &, const uint32_t *, State<float>, V4<float> *);
 template void launch_springs<double>(hipStream_t, const SpringArgs &, const uint32_t *, State<double>,

@@ -38,8 +38,9 @@ template void launch_keys<double>(hipStream_t, uint32_t, const V4<double> *, con
 
 // ---------------------------------------------------------------- radix sort
 // Tile of 2048 keys per block (256 threads x 8 rounds).  hist is digit-major:
-// hist[d * nblk + b] = count of digit d in block b; after the scans
-// dbase[d] + hist[d * nblk + b] is the global output offset of (d, b).
+// hist[d * nblk + b] = count of digit d in block b; the per-digit scan turns
+// it into the offset of block b within digit d and puts the digit's total in
+// dbase[d]; the scatter adds the exclusive scan of the totals.
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_ROUNDS = 8;
@@ -95,36 +96,34 @@ __global__ __launch_bounds__(256) void k_radix_scan_digit(uint32_t *__restrict__
     if (tid == 0) tot[blockIdx.x] = carry;
 }
 
-// Exclusive scan of the 256 digit totals (one block).
-__global__ __launch_bounds__(256) void k_radix_scan_tot(uint32_t *__restrict__ tot)
-{
-    __shared__ uint32_t wsum[4];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    const uint32_t v = tot[tid];
-    uint32_t inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(inc, d, 64);
-        if (lane >= (uint32_t)d) inc += t;
-    }
-    if (lane == 63u) wsum[wv] = inc;
-    __syncthreads();
-    uint32_t before = 0;
-    for (uint32_t w = 0; w < wv; ++w) before += wsum[w];
-    tot[tid] = before + inc - v;
-}
-
 // Stable scatter: elements are ranked in index order (round, wave, lane).
+// Each block first turns the 256 digit totals into digit offsets (an
+// exclusive scan, the same in every block).
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, uint32_t n, uint32_t shift, const uint32_t *__restrict__ hist, uint32_t nblk,
-    const uint32_t *__restrict__ dbase)
+    const uint32_t *__restrict__ tot)
 {
+    static_assert(RS_THREADS == 256, "one thread per digit");
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[RS_THREADS / 64][256];
+    __shared__ uint32_t wsum[RS_THREADS / 64];
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, wv = tid >> 6;
-    base[tid] = dbase[tid] + hist[tid * nblk + blockIdx.x];
+    {
+        const uint32_t v = tot[tid];
+        uint32_t inc = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d, 64);
+            if (lane >= (uint32_t)d) inc += t;
+        }
+        if (lane == 63u) wsum[wv] = inc;
+        __syncthreads();
+        uint32_t before = 0;
+        for (uint32_t w = 0; w < wv; ++w) before += wsum[w];
+        base[tid] = before + inc - v + hist[tid * nblk + blockIdx.x];
+    }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
     const uint32_t tile = blockIdx.x * RS_TILE;
     for (int r = 0; r < RS_ROUNDS; ++r) {
@@ -179,7 +178,6 @@ void launch_radix_sort(hipStream_t s, uint32_t n, int key_bits, Sort &st, uint32
         const uint32_t shift = 8u * (uint32_t)p;
         hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(RS_THREADS), 0, s, kin, n, shift, st.hist, nblk);
         hipLaunchKernelGGL(k_radix_scan_digit, dim3(256), dim3(256), 0, s, st.hist, nblk, st.dbase);
-        hipLaunchKernelGGL(k_radix_scan_tot, dim3(1), dim3(256), 0, s, st.dbase);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(RS_THREADS), 0, s, kin, vin, kout, vout, n,
                            shift, st.hist, nblk, st.dbase);
         // next pass reads what this one wrote

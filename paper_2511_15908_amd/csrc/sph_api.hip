@@ -532,8 +532,8 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
     c->sort.dbase = cv.take<uint32_t>(256 * 4);
     c->sort.nblk = pl.nblk_sort;
     c->inv_perm = cv.take<uint32_t>(n * 4);
-    c->cstart = cv.take<uint32_t>((size_t)pl.nslots * 4);
-    c->cend = cv.take<uint32_t>((size_t)pl.nslots * 4);
+    c->cstart = cv.take<uint32_t>((size_t)pl.nslots * 8);   // cstart and cend back to back: one clear
+    c->cend = c->cstart ? c->cstart + pl.nslots : nullptr;
     c->dens = cv.take<void>(n * 2 * tsz);
     c->force = cv.take<void>(n * 4 * tsz);
     c->masks = cv.take<uint64_t>((size_t)kMaxWords * n * 8);
@@ -641,8 +641,7 @@ void neighbour_search(sph_ctx *c)
     launch_radix_sort(c->stream, n, key_bits(c->nslots), c->sort, &c->sorted_keys, &c->sorted_vals);
     prof_mark(c, 2, false);
     prof_mark(c, 3, true);
-    launch_clear_u32(c->stream, c->cstart, c->nslots);
-    launch_clear_u32(c->stream, c->cend, c->nslots);
+    launch_clear_u32(c->stream, c->cstart, (size_t)c->nslots * 2);   // cstart and cend
     launch_reorder<T>(c->stream, n, c->sorted_vals, c->sorted_keys, state<T>(c, c->cur), state<T>(c, 1 - c->cur),
                       c->inv_perm, c->cstart, c->cend, (V2<T> *)c->dens, (V4<T> *)c->force);
     c->cur = 1 - c->cur;

@@ -125,7 +125,7 @@ struct State {
 struct Sort {
     uint32_t *keys_a, *keys_b, *vals_a, *vals_b;
     uint32_t *hist;
-    uint32_t *dbase;   // 256 digit bases
+    uint32_t *dbase;   // 256 digit totals
     uint32_t nblk;
 };
 
