@@ -495,14 +495,16 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
             }
             ncand += size;
             __syncthreads();
-            const uint32_t nws = nb.wbase[sc + 1] - nb.wbase[sc];
+            // the super-chunk owns words [w0, w0 + its pre-culling words); only the
+            // first nwc hold candidates after culling and are written and read
+            const uint32_t nwc = (size + (uint32_t)kWave - 1u) / (uint32_t)kWave;
             const uint32_t w0 = nb.wbase[sc];
             if (lanes_any) {
                 uint64_t mw[kScWords];
 #pragma unroll
                 for (int q = 0; q < kScWords; ++q) {
                     uint64_t m = 0;
-                    if ((uint32_t)q < nws) {
+                    if ((uint32_t)q < nwc) {
                         const uint32_t nv = size > (uint32_t)q * kWave ? min(size - (uint32_t)q * kWave, (uint32_t)kWave) : 0u;
                         m = hit_word<T>(me, cand + q * kWave, nv, R2);
                         if (act && sp.lead) masks[(size_t)(w0 + q) * n + p] = m;
@@ -550,7 +552,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                     double part = 0.0;
 #pragma unroll
                     for (int q = 0; q < kScWords; ++q) {
-                        if ((uint32_t)q < nws) {
+                        if ((uint32_t)q < nwc) {
                             const V4<T> c = cand[q * kWave + lane];   // far past the chunk end
                             const bool hit = within_support<T>(mt, c, R2);
                             const uint64_t m = __ballot(hit);
@@ -826,13 +828,15 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                 }
                 size += (uint32_t)__popcll(km);
             }
-            const uint32_t nws = nb.wbase[sc + 1] - nb.wbase[sc];
+            // the super-chunk owns words [w0, w0 + its pre-culling words); only the
+            // first nwc hold candidates after culling and are written and read
+            const uint32_t nwc = (size + (uint32_t)kWave - 1u) / (uint32_t)kWave;
             const uint32_t w0 = nb.wbase[sc];
             uint64_t mw[kScWords];
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) {
                 uint64_t m = 0;
-                if ((uint32_t)q < nws && tgt) m = masks[(size_t)(w0 + q) * n + p];
+                if ((uint32_t)q < nwc && tgt) m = masks[(size_t)(w0 + q) * n + p];
                 mw[q] = m & sp.bits;
             }
             __syncthreads();
@@ -877,7 +881,7 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                     T cx = (T)0, cy = (T)0, cz = (T)0;
 #pragma unroll
                     for (int q = 0; q < kScWords; ++q) {
-                        if ((uint32_t)q < nws) {
+                        if ((uint32_t)q < nwc) {
                             const uint64_t m = masks[(size_t)(w0 + q) * n + pt];
                             const uint32_t v = q * kWave + lane;
                             if ((m >> lane) & 1ull)

@@ -1502,7 +1502,9 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t nt, const uint32_t *targets, uint32
                 const uint32_t j = start[k] + sc + S * (v - pre[k]);
                 if (near(pos[j])) kept.push_back(j);
             }
-            for (uint32_t q = 0; q < nws; ++q) {
+            // only the words holding culled candidates are written
+            const uint32_t nwc = (uint32_t)((kept.size() + kWave - 1) / kWave);
+            for (uint32_t q = 0; q < nwc; ++q) {
                 const uint64_t m = masks[(size_t)(w0 + q) * n + p];
                 for (int b = 0; b < 64; ++b) {
                     if (!((m >> b) & 1ull)) continue;
