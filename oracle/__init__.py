@@ -333,7 +333,10 @@ class Oracle:
         self.n = scene.n
         self.x = round_to(scene.x, self.prec).copy()
         self.v = round_to(scene.v, self.prec).copy()
-        self.mass = _f64(scene.mass)
+        # the particle state holds masses (and, below, boundary volumes) at the
+        # run's precision too; rigid-body mass properties use the scene's FP64
+        # masses
+        self.mass = round_to(scene.mass, self.prec).copy()
         self.type = np.ascontiguousarray(scene.type, np.uint8)
         self.obj = np.ascontiguousarray(scene.object, np.int32)
         self.kin = [o for o in range(len(scene.object_kinematic)) if scene.object_kinematic[o]]
@@ -352,7 +355,7 @@ class Oracle:
                                  _p(p0, C.c_double), _p(self.r_loc, C.c_double))
             q = p0[3:] / np.linalg.norm(p0[3:])
             self.pose[o] = [p0[:3].copy(), q, np.zeros(3), np.zeros(3)]
-        self.psi = self._psi()
+        self.psi = round_to(self._psi(), self.prec).copy()
         self.K = int(self.params.get("smoothing_window", 20))
         self.samples = {o: [] for o in self.kin}
         self.nsteps = 0
@@ -360,16 +363,6 @@ class Oracle:
     # boundary volumes from the initial configuration
     def _psi(self):
         return boundary_psi(self.params, self.prec, self.x, self.type, self.obj)
-        counts, offs, ids = neighbors(self.params, self.prec, self.x, bids)
-        fc = np.zeros(self.n, np.int64)
-        fo = np.zeros(self.n, np.int64)
-        fc[bids] = counts
-        fo[bids] = offs
-        lib().orc_boundary_psi(C.byref(self.P), self.n, _p(self.x, C.c_double),
-                               _p(self.type, C.c_uint8), _p(self.obj, C.c_int32),
-                               _p(fc, C.c_int64), _p(fo, C.c_int64), _p(ids, C.c_int64),
-                               _p(psi, C.c_double))
-        return psi
 
     def grab(self, o):
         """A dynamic object follows set_pose from now on (smoothing restarts)."""
