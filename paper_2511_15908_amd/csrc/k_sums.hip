@@ -6,20 +6,21 @@
 //
 // Work decomposition (gfx950, wave64): one workgroup = one wavefront per
 // occupied grid cell (cell size 2h, so all neighbours of a particle lie in the
-// 27 cells around its own).  Each lane owns one particle of the home cell.
-// The candidates (particles of the 27 cells) are visited in S super-chunks of
-// at most kScWords*64: super-chunk s holds every S-th particle of every cell
-// (in-cell index = s mod S).  Each super-chunk is staged through LDS with
-// coalesced loads of the sorted SoA arrays and spreads each lane's neighbours
-// evenly, so the per-lane hit counts of a super-chunk are close to their mean
-// and the compacted per-lane loop below keeps most lanes busy.
+// 27 cells around its own).  Each lane owns one target particle of the home
+// cell (two lanes per target when a pass has at most 32 targets).  The
+// candidates (particles of the 27 cells) are visited in S super-chunks of at
+// most kScWords*64: super-chunk s holds every S-th particle of every cell
+// (in-cell index = s mod S), which spreads each lane's neighbours evenly over
+// the super-chunks.  Candidates farther than the support from the home cell's
+// bounding box are culled, the rest staged compacted in LDS; the next
+// super-chunk's positions are loaded while the current one is summed.
 //  - Density pass: every lane tests every staged candidate (LDS broadcast
-//    reads) and keeps one 64-bit hit mask per word; the kernel sum runs over
-//    the set bits only.  The masks go to HBM.
+//    reads) and keeps one 64-bit hit mask per word in registers; the kernel
+//    sum runs over the set bits only, with FP64 terms.  The masks go to HBM.
 //  - Force pass: restages the same super-chunks (position, velocity,
-//    density) and walks the stored masks, so no pair is tested twice.
-// All sums accumulate FP32 terms in FP64 registers; no atomics, so results are
-// bitwise reproducible.
+//    density) and walks the stored masks, so no pair is tested twice; FP32
+//    terms summed per super-chunk, then in FP64.
+// No atomics in the sums, so results are bitwise reproducible.
 #include "sph_internal.h"
 
 namespace sphk {
