@@ -201,6 +201,19 @@ sph_status sph_batch_init(const sph_params *params, const sph_scene *scenes, uin
 sph_status sph_read_log(sph_ctx *ctx, double *out, size_t n_doubles, uint32_t *n_steps);
 
 /*
+ * Per-step probe log (params.log_steps > 0, params.max_probes > 0, at least
+ * one kinematic or free body): every step also keeps the densities of the
+ * current probe set (sph_set_probes) beside its body-log record.
+ * sph_read_probe_log copies, for the steps sph_read_log would return (oldest
+ * first), [steps][n_probes] densities into out (n_doubles must hold them) and
+ * writes their number to n_steps; it does not empty the log, so call it
+ * before sph_read_log, which empties both.  Steps taken under an earlier
+ * probe set report that set's values.  Synchronises.  With no body, no
+ * probes or no log it reports 0 steps.
+ */
+sph_status sph_read_probe_log(sph_ctx *ctx, double *out, size_t n_doubles, uint32_t *n_steps);
+
+/*
  * Graph replay (enable != 0): sph_step launches a HIP graph of two captured
  * steps (captured at the first use, on that call's stream) instead of their
  * kernels one by one; an odd remainder runs as a plain step.  Needs a

@@ -34,8 +34,8 @@ EXPORTED = ["sph_workspace_size", "sph_init", "sph_set_body_pose", "sph_step", "
             "sph_get_stats", "sph_get_info",
             "sph_synchronize", "sph_profile_begin", "sph_profile_read", "sph_profile_phase_name",
             "sph_set_probes", "sph_read_probes", "sph_grab_body", "sph_release_body", "sph_get_body_state",
-            "sph_batch_workspace_size", "sph_batch_init", "sph_read_log", "sph_set_graph", "sph_set_body_track",
-            "sph_destroy", "sph_status_string", "sph_last_error"]
+            "sph_batch_workspace_size", "sph_batch_init", "sph_read_log", "sph_read_probe_log", "sph_set_graph",
+            "sph_set_body_track", "sph_destroy", "sph_status_string", "sph_last_error"]
 
 
 class SphError(RuntimeError):
@@ -109,6 +109,7 @@ def load_library(path=None):
     L.sph_batch_workspace_size.argtypes = [C.POINTER(SphParams), C.POINTER(SphScene), C.c_uint32, C.POINTER(sz)]
     L.sph_batch_init.argtypes = [C.POINTER(SphParams), C.POINTER(SphScene), C.c_uint32, vp, sz, vp, C.POINTER(vp)]
     L.sph_read_log.argtypes = [vp, d3, sz, C.POINTER(C.c_uint32)]
+    L.sph_read_probe_log.argtypes = [vp, d3, sz, C.POINTER(C.c_uint32)]
     L.sph_set_graph.argtypes = [vp, C.c_int]
     L.sph_set_body_track.argtypes = [vp, C.c_uint32, C.c_uint32, d3]
     L.sph_release_body.argtypes = [vp, C.c_uint32]
@@ -283,6 +284,15 @@ class Sim:
         m = C.c_uint32(0)
         self._check(self.L.sph_read_log(self.ctx, _dp(out), out.size, C.byref(m)), "sph_read_log")
         return out[:m.value * nb * 20].reshape(m.value, nb, 20)
+
+    def read_probe_log(self):
+        """Per-step probe densities [steps][n_probes] of the steps read_log
+        would return (oldest first); does not empty the log."""
+        npr = getattr(self, "n_probes", 0)
+        out = np.zeros(max(self.log_steps, 1) * max(npr, 1))
+        m = C.c_uint32(0)
+        self._check(self.L.sph_read_probe_log(self.ctx, _dp(out), out.size, C.byref(m)), "sph_read_probe_log")
+        return out[:m.value * npr].reshape(m.value, npr)
 
     def grab(self, obj):
         """A free rigid body follows set_body_pose until release()."""

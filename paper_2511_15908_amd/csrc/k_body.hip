@@ -298,7 +298,11 @@ __global__ __launch_bounds__(64) void k_probe(ProbeArgs a, State<T> st, Batch<T>
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-    if (lane == 0) a.out[i] = acc;
+    if (lane == 0) {
+        a.out[i] = acc;
+        // the body log's wrench pass of this step runs later and advances the row
+        if (a.log) a.log[(size_t)(*a.log_row % a.log_cap) * a.stride + i] = acc;
+    }
 }
 
 template <typename T>

@@ -88,6 +88,7 @@ struct sph_ctx {
     int32_t *obj_of_id = nullptr;
     uint32_t max_probes = 0, n_probes = 0;
     double *probe_pts = nullptr, *probe_out = nullptr;
+    double *probe_log = nullptr;                 // [log_cap][max_probes] (log and probes both on)
     int32_t *probe_frame = nullptr;
     std::vector<double> probe_host_pts;
     std::vector<int32_t> probe_host_frame;
@@ -562,6 +563,9 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
     c->probe_pts = cv.take<double>((size_t)pl.max_probes * 3 * 8);
     c->probe_frame = cv.take<int32_t>((size_t)pl.max_probes * 4);
     c->probe_out = cv.take<double>((size_t)pl.max_probes * 8);
+    c->probe_log = (pl.log_steps && pl.max_probes && pl.nk)
+                       ? cv.take<double>((size_t)pl.log_steps * pl.max_probes * 8)
+                       : nullptr;
     c->scene_tab = cv.take<void>((size_t)pl.nscenes * std::max(sizeof(SceneC<float>), sizeof(SceneC<double>)));
     c->log = cv.take<double>((size_t)pl.log_steps * pl.nk * 20 * 8);
     c->log_count = cv.take<uint32_t>((size_t)pl.nk * 4);
@@ -678,7 +682,8 @@ void one_step(sph_ctx *c)
     prof_mark(c, 6, false);
     prof_mark(c, 9, true);
     if (c->n_probes) {
-        ProbeArgs pa{c->n_probes, c->probe_pts, c->probe_frame, c->poses, c->probe_out};
+        ProbeArgs pa{c->n_probes, c->probe_pts,  c->probe_frame, c->poses,
+                     c->probe_out, c->probe_log, c->log_count, c->log_cap, c->max_probes};
         launch_probe<T>(s, pa, st, batch<T>(c), c->cstart, c->cend);
     }
     prof_mark(c, 9, false);
@@ -1143,6 +1148,31 @@ sph_status sph_read_log(sph_ctx *ctx, double *out, size_t n_doubles, uint32_t *n
     if (m > a) HIPCHK(ctx, hipMemcpyAsync(out + a * row, ctx->log, (m - a) * row * 8, hipMemcpyDeviceToHost, ctx->stream));
     launch_clear_u32(ctx->stream, ctx->log_count, ctx->nk);
     HIPCHK(ctx, hipGetLastError());
+    *n_steps = m;
+    return check_err(ctx);
+}
+
+sph_status sph_read_probe_log(sph_ctx *ctx, double *out, size_t n_doubles, uint32_t *n_steps)
+{
+    if (!ctx || !n_steps) return SPH_ERR_ARG;
+    if (ctx->dead) return SPH_ERR_STATE;
+    *n_steps = 0;
+    if (!ctx->probe_log || !ctx->n_probes) return SPH_OK;
+    uint32_t cnt = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&cnt, ctx->log_count, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const uint32_t m = std::min(cnt, ctx->log_cap);
+    const size_t np = ctx->n_probes, pitch = (size_t)ctx->max_probes * 8;
+    if (m && (!out || n_doubles < m * np)) return SPH_ERR_ARG;
+    const uint32_t first = (cnt - m) % ctx->log_cap;
+    const uint32_t a = std::min(m, ctx->log_cap - first);
+    if (a)
+        HIPCHK(ctx, hipMemcpy2DAsync(out, np * 8, ctx->probe_log + (size_t)first * ctx->max_probes, pitch, np * 8, a,
+                                     hipMemcpyDeviceToHost, ctx->stream));
+    if (m > a)
+        HIPCHK(ctx, hipMemcpy2DAsync(out + (size_t)a * np, np * 8, ctx->probe_log, pitch, np * 8, m - a,
+                                     hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     *n_steps = m;
     return check_err(ctx);
 }

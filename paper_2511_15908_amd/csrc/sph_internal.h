@@ -328,6 +328,9 @@ struct ProbeArgs {
     const int32_t *frame;    // [n] kinematic index of the body frame, or -1
     const double *poses;     // [16 nk]
     double *out;             // [n]
+    double *log;             // [log_cap][stride] per-step copies of out, or null
+    const uint32_t *log_row; // the body log's row counter (row of this step)
+    uint32_t log_cap, stride;
 };
 template <typename T>
 void launch_probe(hipStream_t s, const ProbeArgs &a, State<T> st, const Batch<T> &b,

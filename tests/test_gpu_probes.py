@@ -96,3 +96,36 @@ def test_probe_argument_errors(gpu):
     sim.set_probes(np.zeros((0, 3)))
     sim.step(1)
     assert sim.read_probes().shape == (0,)
+
+
+def test_probe_log_matches_per_step_reads(gpu):
+    """The per-step probe log holds, bitwise, what read_probes returns after
+    each step, for the steps the body log returns, oldest first (ring
+    wrap-around included); read_log empties both logs; graph replays log as
+    eager steps do."""
+    import torch
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=94, precision="f32")
+    pts, frame = _probe_points(sc, 94)
+    st = torch.cuda.Stream()
+    for graph in (False, True):
+        sim = gpu.Sim(sc, max_probes=256, log_steps=5, stream=st)
+        sim.set_probes(pts, frame)
+        if graph:
+            sim.set_graph(True)
+        per = []
+        for k in range(8):
+            sim.set_body_pose(1, *scenes.random_pose_velocity(94 + k, sc.object_pose0[1, :3]))
+            sim.step(1)
+            per.append(sim.read_probes())
+        lg = sim.read_probe_log()
+        assert lg.shape == (5, pts.shape[0])
+        assert np.array_equal(lg, np.array(per[-5:]))
+        body = sim.read_log()
+        assert body.shape[0] == 5
+        assert sim.read_probe_log().shape[0] == 0
+        # two more steps (one graph replay when enabled), read without per-step reads
+        sim.step(2)
+        lg2 = sim.read_probe_log()
+        assert lg2.shape == (2, pts.shape[0])
+        assert np.array_equal(lg2[-1], sim.read_probes())
