@@ -55,10 +55,14 @@ def probe_points(scene):
     return scenes.fibonacci_sphere(N_PROBES, scene.info["probe_radius"], (0.0, 0.0, 0.0))
 
 
-def make_sim(scene, device="cuda"):
+def make_sim(scene, device="cuda", max_ticks=4000, per_tick=4):
+    """The haptic scene's context with the body-frame probes set and a
+    per-step body and probe log long enough for a walk of max_ticks ticks."""
     from ._binding import Sim
-    sim = Sim(scene, device=device, max_probes=N_PROBES)
+    sim = Sim(scene, device=device, max_probes=N_PROBES, log_steps=per_tick * max_ticks)
     sim.set_probes(probe_points(scene), np.full(N_PROBES, scene.info["body"], np.int32))
+    sim.per_tick = per_tick
+    sim.wrench_tail = np.zeros((0, 6))      # last per-step wrenches, for the rolling mean
     return sim
 
 
@@ -69,22 +73,36 @@ def make_net(max_batch=4096, device="cuda", seed=1, hidden=256, layers=3):
     return net
 
 
-def collect(sim, scene, walk, per_tick=4):
-    """Drive the grabbed body with `walk` (c, q, v, w per tick), `per_tick`
+def collect(sim, scene, walk):
+    """Drive the grabbed body with `walk` (c, q, v, w per tick), sim.per_tick
     SPH steps per tick; log per tick the pose, the haptic wrench (the rolling
-    mean of the per-step wrenches over the scene's smoothing window) and the
-    probe densities."""
+    mean of the per-step wrenches over the scene's smoothing window, as
+    sph_get_body_wrench returns it at the end of the tick) and the probe
+    densities.  The device logs every step, so the loop only enqueues work
+    and the host reads the logs once per walk."""
     C, Q, V, W = walk
     n = C.shape[0]
+    per_tick = sim.per_tick
     body = scene.info["body"]
-    wr = np.zeros((n, 6))
-    pr = np.zeros((n, N_PROBES))
+    K = int(scene.params["smoothing_window"])
+    if n * per_tick > sim.log_steps:
+        raise ValueError(f"walk of {n} ticks exceeds the log ({sim.log_steps} steps)")
+    sim.read_log()                                   # start from an empty log
     for t in range(n):
         sim.set_body_pose(body, C[t], Q[t], V[t], W[t])
         sim.step(per_tick)
-        F, T = sim.wrench(body, smoothed=True)
-        wr[t, :3], wr[t, 3:] = F, T
-        pr[t] = sim.read_probes()
+    probes = sim.read_probe_log()                    # [steps][N_PROBES]
+    rec = sim.read_log()                             # [steps][bodies][20]
+    if rec.shape[0] != n * per_tick or probes.shape[0] != n * per_tick:
+        raise RuntimeError("step log shorter than the walk")
+    kb = sim.kinematic.index(body)
+    allw = np.concatenate([sim.wrench_tail, rec[:, kb, 13:19]])
+    cs = np.concatenate([np.zeros((1, 6)), np.cumsum(allw, 0)])
+    end = sim.wrench_tail.shape[0] + per_tick * np.arange(1, n + 1)     # samples up to each tick's end
+    start = np.maximum(end - K, 0)
+    wr = (cs[end] - cs[start]) / (end - start)[:, None]
+    sim.wrench_tail = allw[-(K - 1):] if K > 1 else allw[:0]
+    pr = probes[per_tick * np.arange(1, n + 1) - 1]
     q = np.where(Q[:, :1] < 0, -Q, Q)
     return {"c": C.copy(), "q": q, "v": V.copy(), "w": W.copy(), "wrench": wr, "probes": pr}
 
@@ -246,7 +264,7 @@ def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=150
     import time
     import torch
     sc = scenes.haptic_scene(n_fluid=n_fluid)
-    sim = make_sim(sc)
+    sim = make_sim(sc, max_ticks=max(warmup_ticks, ticks, eval_ticks))
     lo, hi = sc.info["walk_lo"], sc.info["walk_hi"]
     c = sc.info["c0"]
     logs = []
