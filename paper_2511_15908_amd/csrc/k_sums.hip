@@ -282,6 +282,10 @@ __device__ __forceinline__ uint32_t gap_sign(const V4<T> &a, const V4<T> &b, T R
     else return (uint32_t)((uint64_t)__double_as_longlong((double)d) >> 32);
 }
 
+#ifndef SPH_TEST_UNROLL
+#define SPH_TEST_UNROLL 8
+#endif
+
 // Hit bits of this lane's particle against nv (<= 32) staged candidates;
 // nv is uniform, so empty slots of a super-chunk are never tested.  The
 // candidates go from the last to the first, each shifting its sign bit in
@@ -290,7 +294,7 @@ template <typename T>
 __device__ __forceinline__ uint32_t hit_bits(const V4<T> &me, const V4<T> *cand, uint32_t nv, T R2)
 {
     uint32_t bits = 0;
-#pragma unroll 8
+#pragma unroll SPH_TEST_UNROLL
     for (uint32_t b = nv; b-- > 0u;) bits = __builtin_amdgcn_alignbit(bits, gap_sign<T>(me, cand[b], R2), 31u);
     return bits;
 }
