@@ -137,10 +137,14 @@ struct OpMin {
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) { return wave_reduce(v, 0u, OpAdd{}); }
 
-// Particles of cell k (count c) in super-chunk s of S.
-__device__ __forceinline__ uint32_t share(uint32_t c, uint32_t s, uint32_t S)
+// Particles of cell k (count c) in super-chunk s of S: ceil((c - s) / S) for
+// c > s, taken as floor((c - s - 1 + 1/2) / S) + 1 with invS = 1/S in float.
+// A neighbourhood that fits (S <= kMaxWords) has c < 2^13, so (x + 1/2) / S
+// lies at least 1/(2 S) >= 1/128 from an integer while the float product is
+// off by less than 1e-3: the floor is exact.
+__device__ __forceinline__ uint32_t share(uint32_t c, uint32_t s, float invS)
 {
-    return c > s ? (c - s + S - 1u) / S : 0u;
+    return c > s ? (uint32_t)(((float)(c - s - 1u) + 0.5f) * invS) + 1u : 0u;
 }
 
 // Load the 27 cells around `cell` (index in its scene's grid), choose S so every super-chunk fits
@@ -168,10 +172,11 @@ __device__ __forceinline__ bool load_nbhd(uint32_t cell, const Grid &g, const ui
     const uint32_t S = (L + cap - 1u) / cap;     // >= 1: the home cell is occupied
     if (S > (uint32_t)kMaxWords) return false;
     // words of each super-chunk: lane s < S computes its own size
+    const float invS = 1.0f / (float)S;
     uint32_t words = 0;
     for (uint32_t k = 0; k < 27u; ++k) {
         const uint32_t ck = (uint32_t)__builtin_amdgcn_readlane((int)cnt, (int)k);
-        words += (lane < S) ? share(ck, lane, S) : 0u;
+        words += (lane < S) ? share(ck, lane, invS) : 0u;
     }
     words = (words + (uint32_t)kWave - 1u) / (uint32_t)kWave;
     const uint32_t inc = wave_scan_incl(words);
@@ -188,9 +193,9 @@ __device__ __forceinline__ bool load_nbhd(uint32_t cell, const Grid &g, const ui
 
 // Prefix of the per-cell shares of super-chunk s into pre[buf] (all lanes
 // participate).
-__device__ __forceinline__ void begin_chunk(Nbhd &nb, uint32_t s, uint32_t buf, uint32_t lane)
+__device__ __forceinline__ void begin_chunk(Nbhd &nb, uint32_t s, uint32_t buf, uint32_t lane, float invS)
 {
-    const uint32_t c = (lane < 27u) ? share(nb.cnt[lane], s, nb.stride) : 0u;
+    const uint32_t c = (lane < 27u) ? share(nb.cnt[lane], s, invS) : 0u;
     const uint32_t inc = wave_scan_incl(c);
     if (lane < 32u) nb.pre[buf][lane] = lane < 27u ? inc - c : 0xffffffffu;
     if (lane == 26u) nb.size[buf] = inc;
@@ -417,6 +422,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         return;
     }
     const uint32_t S = nb.stride;
+    const float invS = 1.0f / (float)S;
     const T R2 = grid_R2<T>(g);
     const T inf = __builtin_huge_val();
     T blo[3], bhi[3];
@@ -459,7 +465,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         V4<T> nxt[kScWords];
         {
             uint32_t j[kScWords];
-            begin_chunk(nb, 0u, 0u, lane);
+            begin_chunk(nb, 0u, 0u, lane, invS);
             chunk_slots(nb, 0u, 0u, lane, s0, n, j);
 #pragma unroll
             for (int q = 0; q < kScWords; ++q) nxt[q] = st.pos[j[q]];
@@ -472,7 +478,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
             for (int q = 0; q < kScWords; ++q) cur[q] = nxt[q];
             if (sc + 1u < S) {
                 uint32_t j[kScWords];
-                begin_chunk(nb, sc + 1u, buf ^ 1u, lane);
+                begin_chunk(nb, sc + 1u, buf ^ 1u, lane, invS);
                 chunk_slots(nb, sc + 1u, buf ^ 1u, lane, s0, n, j);
 #pragma unroll
                 for (int q = 0; q < kScWords; ++q) nxt[q] = st.pos[j[q]];
@@ -756,6 +762,7 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
     const Phys<T> ph = scn.ph;
     if (!load_nbhd(slot - g.slot0, g, cstart, cend, nb, lane)) return;   // flagged by the density pass
     const uint32_t S = nb.stride;
+    const float invS = 1.0f / (float)S;
     const T R2 = grid_R2<T>(g);
     T blo[3], bhi[3];
     cell_box<T>(st.pos, s0, e0, lane, blo, bhi);
@@ -792,7 +799,7 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
         // the positions of super-chunk sc + 1 are loaded while sc is summed
         V4<T> nxt[kScWords];
         uint32_t nj[kScWords];
-        begin_chunk(nb, 0u, 0u, lane);
+        begin_chunk(nb, 0u, 0u, lane, invS);
         chunk_slots(nb, 0u, 0u, lane, s0, n, nj);
 #pragma unroll
         for (int q = 0; q < kScWords; ++q) nxt[q] = st.pos[nj[q]];
@@ -807,7 +814,7 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                 cj[q] = nj[q];
             }
             if (sc + 1u < S) {
-                begin_chunk(nb, sc + 1u, buf ^ 1u, lane);
+                begin_chunk(nb, sc + 1u, buf ^ 1u, lane, invS);
                 chunk_slots(nb, sc + 1u, buf ^ 1u, lane, s0, n, nj);
 #pragma unroll
                 for (int q = 0; q < kScWords; ++q) nxt[q] = st.pos[nj[q]];
