@@ -43,6 +43,13 @@ LANE_OPS_FORCE_PAIR = 45
 # The same in FLOPs (FMA = 2) as written in the oracle, for reference.
 FLOP_DENSITY_PAIR = 17
 FLOP_FORCE_PAIR = 49
+# Compulsory HBM bytes per particle of the memory-bound phases (FP32 SoA,
+# unfused): keys 12 + 4; two 8-bit radix passes 2 x (8 + 8) + histograms;
+# reorder perm 4 + 32 + 32 + inverse 4 + cell bounds 6; integrate 40 + 24.
+# The whole step, neighbour sums included (their compulsory traffic: 24 and
+# 48), is 264 bytes per particle.
+HBM_BYTES_PER_PARTICLE = {"keys": 16, "sort": 34, "reorder": 78, "integrate": 64}
+HBM_BYTES_STEP_PER_PARTICLE = 264
 
 
 def parse():
@@ -229,7 +236,29 @@ def main():
                            "lane_efficiency_force": pairs_f / max(64 * (s1["iter_force"] - s0["iter_force"]) / a.steps, 1)},
         "phase_ms": {k: round(v, 4) for k, v in ms.items()},
         "roofline": roof,
+        # the memory-bound phases against HBM (algorithmic bytes / HIP-event phase time)
+        "hbm": {"peak_gbs": PEAK_HBM_GBS,
+                "whole_step": {"bytes_per_particle": HBM_BYTES_STEP_PER_PARTICLE,
+                               "achieved_gbs": round(HBM_BYTES_STEP_PER_PARTICLE * info["n"] / (ms_step * 1e-3) / 1e9, 1),
+                               "frac": round(HBM_BYTES_STEP_PER_PARTICLE * info["n"] / (ms_step * 1e-3) / 1e9
+                                             / PEAK_HBM_GBS, 4)},
+                "phases": {k: {"bytes_per_particle": b_, "ms": round(ms[k], 4),
+                               "achieved_gbs": round(b_ * info["n"] / (ms[k] * 1e-3) / 1e9, 1),
+                               "frac": round(b_ * info["n"] / (ms[k] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+                           for k, b_ in HBM_BYTES_PER_PARTICLE.items() if ms.get(k, 0) > 0}},
     }
+    # measured device copy bandwidth (read + write bytes of a 1 GiB torch copy)
+    src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    out["hbm"]["copy_gbs"] = round(5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del src, dst
     # cell occupancy of the last step (targets beyond 64 need a second wavefront pass)
     keys = sim.read("key")
     cnt = np.bincount(keys)
