@@ -176,7 +176,7 @@ sph_status sph_get_body_state(sph_ctx *ctx, uint32_t object, double c[3], double
  * Batches: independent scenes stepped together (one context, one launch per
  * kernel for all scenes).  params[k] and scenes[k] describe scene k exactly
  * as for sph_init; the scenes share precision, dt, gravity, v_max,
- * smoothing_window and log_steps, and take no density probes.  Each scene
+ * smoothing_window, log_steps, track_steps and max_probes.  Each scene
  * keeps its own h, grid, constants and flags.  In the context, particle ids,
  * object ids and spring ends of scene k follow those of scenes 0..k-1 (a
  * scene's particle i is id part0_k + i, part0_k = sum of the previous scenes'
@@ -311,6 +311,8 @@ const char *sph_profile_phase_name(uint32_t phase);
  * the caller's [n] doubles, n equal to the count last set, and synchronises;
  * it reports pending step errors like sph_synchronize.  The probe points are
  * rounded to the run precision; the support test is the particle-pair one.
+ * In a batch a body-frame point samples its body's scene and a world point
+ * scene 0.
  */
 sph_status sph_set_probes(sph_ctx *ctx, uint32_t n, const double *points, const int32_t *frame);
 sph_status sph_read_probes(sph_ctx *ctx, double *rho, uint32_t n);

@@ -262,8 +262,9 @@ __global__ __launch_bounds__(64) void k_probe(ProbeArgs a, State<T> st, Batch<T>
 #pragma clang fp contract(off)
     const uint32_t i = blockIdx.x, lane = threadIdx.x;
     if (i >= a.n) return;
-    const Grid g = b.sc[0].g;          // probes are offered for single-scene contexts
-    const Phys<T> ph = b.sc[0].ph;
+    const uint32_t si = a.scene[i];    // the probe's scene: its grid, constants and cells
+    const Grid g = b.sc[si].g;
+    const Phys<T> ph = b.sc[si].ph;
     double p[3] = {a.pts[3 * i], a.pts[3 * i + 1], a.pts[3 * i + 2]};
     const int32_t f = a.frame[i];
     if (f >= 0) {

@@ -42,6 +42,7 @@ struct sph_ctx {
     uint32_t n = 0, n_fluid = 0, n_soft = 0, n_bnd = 0;
     uint32_t nb = 0, nk = 0, n_objects = 0, rows = 0, nsprings = 0, nblk_w = 0, K = 1;
     std::vector<int32_t> kin_of_object;   // object -> kinematic index or -1
+    std::vector<uint32_t> obj_scene;      // object -> scene of the batch
     std::vector<uint32_t> kin_objects;    // kinematic index -> object
     std::vector<uint8_t> dynamic;         // kinematic index -> free rigid body type (object_kinematic 2)
     std::vector<uint8_t> free_now;        // kinematic index -> currently integrated (not grabbed)
@@ -89,9 +90,11 @@ struct sph_ctx {
     uint32_t max_probes = 0, n_probes = 0;
     double *probe_pts = nullptr, *probe_out = nullptr;
     double *probe_log = nullptr;                 // [log_cap][max_probes] (log and probes both on)
+    uint32_t *probe_scene = nullptr;             // [max_probes] scene each probe samples
     int32_t *probe_frame = nullptr;
     std::vector<double> probe_host_pts;
     std::vector<int32_t> probe_host_frame;
+    std::vector<uint32_t> probe_host_scene;
     uint64_t steps = 0;
     bool dead = false;
     std::string last_error;
@@ -471,15 +474,12 @@ sph_status validate_batch(const sph_params *p, const sph_scene *sc, uint32_t ns,
             const sph_params &a = p[0], &b = p[k];
             if (a.precision != b.precision || a.dt != b.dt || a.v_max != b.v_max ||
                 a.smoothing_window != b.smoothing_window || a.log_steps != b.log_steps ||
-                a.track_steps != b.track_steps ||
+                a.track_steps != b.track_steps || a.max_probes != b.max_probes ||
                 a.gravity[0] != b.gravity[0] || a.gravity[1] != b.gravity[1] || a.gravity[2] != b.gravity[2]) {
-                why = "the scenes of a batch share precision, dt, gravity, v_max, smoothing_window, log_steps";
+                why = "the scenes of a batch share precision, dt, gravity, v_max, smoothing_window, log_steps, "
+                      "track_steps, max_probes";
                 return SPH_ERR_ARG;
             }
-        }
-        if (ns > 1 && p[k].max_probes) {
-            why = "density probes are offered for single-scene contexts";
-            return SPH_ERR_UNSUPPORTED;
         }
         g.slot0 = (uint32_t)slots;
         slots += g.nslots;
@@ -563,6 +563,7 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
     c->probe_pts = cv.take<double>((size_t)pl.max_probes * 3 * 8);
     c->probe_frame = cv.take<int32_t>((size_t)pl.max_probes * 4);
     c->probe_out = cv.take<double>((size_t)pl.max_probes * 8);
+    c->probe_scene = cv.take<uint32_t>((size_t)pl.max_probes * 4);
     c->probe_log = (pl.log_steps && pl.max_probes && pl.nk)
                        ? cv.take<double>((size_t)pl.log_steps * pl.max_probes * 8)
                        : nullptr;
@@ -682,8 +683,8 @@ void one_step(sph_ctx *c)
     prof_mark(c, 6, false);
     prof_mark(c, 9, true);
     if (c->n_probes) {
-        ProbeArgs pa{c->n_probes, c->probe_pts,  c->probe_frame, c->poses,
-                     c->probe_out, c->probe_log, c->log_count, c->log_cap, c->max_probes};
+        ProbeArgs pa{c->n_probes,  c->probe_pts, c->probe_frame, c->probe_scene, c->poses,
+                     c->probe_out, c->probe_log, c->log_count,   c->log_cap,     c->max_probes};
         launch_probe<T>(s, pa, st, batch<T>(c), c->cstart, c->cend);
     }
     prof_mark(c, 9, false);
@@ -999,6 +1000,7 @@ sph_status sph_batch_init(const sph_params *params, const sph_scene *scenes, uin
     c->track_cap = pl.track_steps;
     c->stream = (hipStream_t)hip_stream;
     c->kin_of_object.assign(scene->n_objects, -1);
+    for (uint32_t k = 0; k < n_scenes; ++k) c->obj_scene.insert(c->obj_scene.end(), scenes[k].n_objects, k);
     for (uint32_t o = 0; o < scene->n_objects; ++o)
         if (scene->object_kinematic[o]) {
             c->kin_of_object[o] = (int32_t)c->kin_objects.size();
@@ -1276,6 +1278,7 @@ sph_status sph_set_probes(sph_ctx *ctx, uint32_t n, const double *points, const 
     if (n > ctx->max_probes || (n && (!points || !frame))) return SPH_ERR_ARG;
     std::vector<double> pts(points, points + 3 * (size_t)n);
     std::vector<int32_t> fr(n);
+    std::vector<uint32_t> scn(n, 0u);       // world points sample scene 0, body points their body's scene
     for (uint32_t i = 0; i < n; ++i) {
         if (!finite3(points + 3 * i)) return SPH_ERR_ARG;
         if (frame[i] < 0) {
@@ -1283,6 +1286,7 @@ sph_status sph_set_probes(sph_ctx *ctx, uint32_t n, const double *points, const 
         } else {
             if ((uint32_t)frame[i] >= ctx->n_objects || ctx->kin_of_object[frame[i]] < 0) return SPH_ERR_ARG;
             fr[i] = ctx->kin_of_object[frame[i]];
+            scn[i] = ctx->obj_scene[frame[i]];
         }
     }
     // the previous upload may still read the host copies
@@ -1293,10 +1297,13 @@ sph_status sph_set_probes(sph_ctx *ctx, uint32_t n, const double *points, const 
     }
     ctx->probe_host_pts.swap(pts);
     ctx->probe_host_frame.swap(fr);
+    ctx->probe_host_scene.swap(scn);
     if (n) {
         HIPCHK(ctx, hipMemcpyAsync(ctx->probe_pts, ctx->probe_host_pts.data(), 24 * (size_t)n,
                                    hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(ctx->probe_frame, ctx->probe_host_frame.data(), 4 * (size_t)n,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->probe_scene, ctx->probe_host_scene.data(), 4 * (size_t)n,
                                    hipMemcpyHostToDevice, ctx->stream));
         launch_clear_u32(ctx->stream, (uint32_t *)ctx->probe_out, 2 * (size_t)n);
     }

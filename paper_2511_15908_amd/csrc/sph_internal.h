@@ -326,6 +326,7 @@ struct ProbeArgs {
     uint32_t n;
     const double *pts;       // [3n] world or body-frame coordinates
     const int32_t *frame;    // [n] kinematic index of the body frame, or -1
+    const uint32_t *scene;   // [n] scene of the batch the probe samples
     const double *poses;     // [16 nk]
     double *out;             // [n]
     double *log;             // [log_cap][stride] per-step copies of out, or null

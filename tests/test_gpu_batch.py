@@ -198,3 +198,40 @@ def test_stirring_batch_256(gpu):
     x = sim.read("x")
     for i in pick:
         assert np.array_equal(x[sim.part0[i]:sim.part0[i + 1]], singles[i].read("x"))
+
+
+def test_batch_probes_equal_one_context_per_scene(gpu):
+    """Density probes in a batch: points in a body's frame sample that body's
+    scene, world points scene 0; every value (and the per-step probe log)
+    bitwise equal to one context per scene."""
+    from paper_2511_15908_amd import scenes
+    scs = _mixed("f32")[:3]
+    rng = scenes.SplitMix64(5, 33)
+    body_pts = (rng.uniform(48).reshape(-1, 3) - 0.5) * 0.12
+    world_pts = np.asarray(scs[0].params["domain_lo"]) + 0.05 + rng.uniform(12).reshape(-1, 3) * 0.1
+    batch = gpu.Sim(scs, max_probes=64, log_steps=4)
+    pts = np.concatenate([body_pts] * 3 + [world_pts])
+    frame = np.concatenate([np.full(16, int(batch.obj0[i]) + 1) for i in range(3)] + [np.full(4, -1)])
+    batch.set_probes(pts, frame.astype(np.int32))
+    singles = []
+    for i, sc in enumerate(scs):
+        s = gpu.Sim(sc, max_probes=64, log_steps=4)
+        p, f = (np.concatenate([body_pts, world_pts]), np.r_[np.full(16, 1), np.full(4, -1)]) if i == 0 \
+            else (body_pts, np.full(16, 1))
+        s.set_probes(p, f.astype(np.int32))
+        singles.append(s)
+    for k in range(3):
+        for i, p in enumerate(_poses(scs, k)):
+            batch.set_body_pose(int(batch.obj0[i]) + 1, *p)
+            singles[i].set_body_pose(1, *p)
+        batch.step(1)
+        for s in singles:
+            s.step(1)
+    g = batch.read_probes()
+    ref = [s.read_probes() for s in singles]
+    for i in range(3):
+        assert np.array_equal(g[16 * i:16 * i + 16], ref[i][:16]), i
+    assert np.array_equal(g[48:], ref[0][16:])
+    assert np.count_nonzero(g[:48]) > 10
+    lg = batch.read_probe_log()
+    assert lg.shape == (3, 52) and np.array_equal(lg[-1], g)
