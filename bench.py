@@ -63,7 +63,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 256-scene batch leg (graph-replayed steps of independent stirring tanks)")
     ap.add_argument("--no-surrogate", action="store_true",
-                    help="skip the haptic-rate surrogate leg (100k haptic scene: logs, training, evaluation)")
+                    help="skip the haptic-rate surrogate leg (16 copies of the 100k haptic scene: logs, training, "
+                         "evaluation; about 2 minutes)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
@@ -272,8 +273,10 @@ def main():
         out["batch"] = batch_leg(dev)
     if not a.no_surrogate:
         from paper_2511_15908_amd import surrogate as S
-        log("surrogate leg: plain-SPH haptic logs of the 100k haptic scene, training, evaluation ...", a.quiet)
-        r = S.run_experiment(log=lambda m: log(m, a.quiet))
+        log("surrogate leg: plain-SPH haptic logs of 16 copies of the 100k haptic scene (one walk each), "
+            "training, evaluation ...", a.quiet)
+        r = S.run_experiment(batch=16, train_segments=32, ticks=3000, eval_ticks=1500, eval_segments=15,
+                             steps=3000, log=lambda m: log(m, a.quiet))
         e = r["errors"]
         out["surrogate"] = {
             "scene": r["scene"], "n_particles": r["n_particles"], "sph_update_hz": 100, "haptic_hz": 1000,
@@ -281,7 +284,9 @@ def main():
             "error_p95": {k: round(v["p95"], 4) for k, v in e.items()},
             "tick_rate_hz": {"host_round_trip": round(r["host_round_trip_hz"], 1),
                              "device_chain": round(r["device_chain_hz"], 1)},
-            "training": {"rows": r["training_rows"], "steps": r["train_steps"], "seconds": round(r["train_s"], 2),
+            "eval_walks": r["eval_walks"],
+            "training": {"walks": r["training_walks"], "rows": r["training_rows"], "steps": r["train_steps"],
+                         "seconds": round(r["train_s"], 2), "scene_copies_stepped_together": r["batch"],
                          "ticks_simulated": r["ticks_collected"], "collect_seconds": round(r["collect_s"], 1)}}
     log(json.dumps(out, indent=1), a.quiet)
     if not a.no_cpu_baseline:

@@ -55,14 +55,19 @@ def probe_points(scene):
     return scenes.fibonacci_sphere(N_PROBES, scene.info["probe_radius"], (0.0, 0.0, 0.0))
 
 
-def make_sim(scene, device="cuda", max_ticks=4000, per_tick=4):
-    """The haptic scene's context with the body-frame probes set and a
-    per-step body and probe log long enough for a walk of max_ticks ticks."""
+def make_sim(scene, device="cuda", max_ticks=4000, per_tick=4, batch=1):
+    """`batch` copies of the haptic scene stepped together in one context (one
+    walk each), each with the body-frame probes on its own grabbed sphere and
+    a per-step body and probe log long enough for a walk of max_ticks ticks."""
     from ._binding import Sim
-    sim = Sim(scene, device=device, max_probes=N_PROBES, log_steps=per_tick * max_ticks)
-    sim.set_probes(probe_points(scene), np.full(N_PROBES, scene.info["body"], np.int32))
+    k = int(batch)
+    if k < 1:
+        raise ValueError("batch must be >= 1")
+    sim = Sim([scene] * k, device=device, max_probes=N_PROBES * k, log_steps=per_tick * max_ticks)
+    sim.bodies = [int(sim.obj0[i]) + scene.info["body"] for i in range(k)]
+    sim.set_probes(np.tile(probe_points(scene), (k, 1)), np.repeat(np.asarray(sim.bodies, np.int32), N_PROBES))
     sim.per_tick = per_tick
-    sim.wrench_tail = np.zeros((0, 6))      # last per-step wrenches, for the rolling mean
+    sim.wrench_tail = [np.zeros((0, 6)) for _ in range(k)]   # last per-step wrenches, for the rolling mean
     return sim
 
 
@@ -73,38 +78,52 @@ def make_net(max_batch=4096, device="cuda", seed=1, hidden=256, layers=3):
     return net
 
 
-def collect(sim, scene, walk):
-    """Drive the grabbed body with `walk` (c, q, v, w per tick), sim.per_tick
-    SPH steps per tick; log per tick the pose, the haptic wrench (the rolling
-    mean of the per-step wrenches over the scene's smoothing window, as
-    sph_get_body_wrench returns it at the end of the tick) and the probe
-    densities.  The device logs every step, so the loop only enqueues work
-    and the host reads the logs once per walk."""
-    C, Q, V, W = walk
-    n = C.shape[0]
+def collect(sim, scene, walks):
+    """Drive the grabbed sphere of each scene copy with its walk (c, q, v, w
+    per tick; `walks` holds one walk per copy, or is one walk for a context
+    of one), sim.per_tick SPH steps per tick; log per tick the pose, the
+    haptic wrench (the rolling mean of the per-step wrenches over the scene's
+    smoothing window, as sph_get_body_wrench returns it at the end of the
+    tick) and the probe densities.  The device logs every step, so the loop
+    only enqueues work and the host reads the logs once per walk.  Returns
+    one log per walk (a single log for a single walk)."""
+    single = isinstance(walks[0], np.ndarray)
+    if single:
+        walks = [walks]
+    k = len(sim.bodies)
+    if len(walks) != k:
+        raise ValueError(f"{len(walks)} walks for {k} scene copies")
+    n = walks[0][0].shape[0]
+    if any(w[0].shape[0] != n for w in walks):
+        raise ValueError("the walks of one batch must have the same length")
     per_tick = sim.per_tick
-    body = scene.info["body"]
     K = int(scene.params["smoothing_window"])
     if n * per_tick > sim.log_steps:
         raise ValueError(f"walk of {n} ticks exceeds the log ({sim.log_steps} steps)")
     sim.read_log()                                   # start from an empty log
     for t in range(n):
-        sim.set_body_pose(body, C[t], Q[t], V[t], W[t])
+        for b, (C, Q, V, W) in zip(sim.bodies, walks):
+            sim.set_body_pose(b, C[t], Q[t], V[t], W[t])
         sim.step(per_tick)
-    probes = sim.read_probe_log()                    # [steps][N_PROBES]
+    probes = sim.read_probe_log()                    # [steps][copies * N_PROBES]
     rec = sim.read_log()                             # [steps][bodies][20]
     if rec.shape[0] != n * per_tick or probes.shape[0] != n * per_tick:
         raise RuntimeError("step log shorter than the walk")
-    kb = sim.kinematic.index(body)
-    allw = np.concatenate([sim.wrench_tail, rec[:, kb, 13:19]])
-    cs = np.concatenate([np.zeros((1, 6)), np.cumsum(allw, 0)])
-    end = sim.wrench_tail.shape[0] + per_tick * np.arange(1, n + 1)     # samples up to each tick's end
-    start = np.maximum(end - K, 0)
-    wr = (cs[end] - cs[start]) / (end - start)[:, None]
-    sim.wrench_tail = allw[-(K - 1):] if K > 1 else allw[:0]
-    pr = probes[per_tick * np.arange(1, n + 1) - 1]
-    q = np.where(Q[:, :1] < 0, -Q, Q)
-    return {"c": C.copy(), "q": q, "v": V.copy(), "w": W.copy(), "wrench": wr, "probes": pr}
+    end_rows = per_tick * np.arange(1, n + 1) - 1
+    logs = []
+    for i, (b, (C, Q, V, W)) in enumerate(zip(sim.bodies, walks)):
+        kb = sim.kinematic.index(b)
+        tail = sim.wrench_tail[i]
+        allw = np.concatenate([tail, rec[:, kb, 13:19]])
+        cs = np.concatenate([np.zeros((1, 6)), np.cumsum(allw, 0)])
+        end = tail.shape[0] + per_tick * np.arange(1, n + 1)     # samples up to each tick's end
+        start = np.maximum(end - K, 0)
+        wr = (cs[end] - cs[start]) / (end - start)[:, None]
+        sim.wrench_tail[i] = allw[-(K - 1):] if K > 1 else allw[:0]
+        pr = probes[end_rows, i * N_PROBES:(i + 1) * N_PROBES]
+        q = np.where(Q[:, :1] < 0, -Q, Q)
+        logs.append({"c": C.copy(), "q": q, "v": V.copy(), "w": W.copy(), "wrench": wr, "probes": pr})
+    return logs[0] if single else logs
 
 
 def feature_rows(log, ticks, lags):
@@ -227,7 +246,7 @@ def evaluate(net, logs, scene):
     for name, parts in errs.items():
         e = np.concatenate(parts)
         out[name] = {"mean": float(e.mean()), "p50": float(np.median(e)), "p95": float(np.percentile(e, 95)),
-                     "max": float(e.max())}
+                     "max": float(e.max()), "walk_means": [float(x.mean()) for x in parts]}
     return out
 
 
@@ -255,42 +274,56 @@ def haptic_rate(net, X, n=500):
 
 
 def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=1500, steps=1500, seed=1,
-                   warmup_ticks=300, eval_segments=3, log=print):
+                   warmup_ticks=300, eval_segments=3, batch=1, log=print):
     """Collect plain-SPH haptic logs (a 1 kHz smooth walk per segment, 4 SPH
     steps per tick), train on the first segments with early stopping on a
-    held-out segment, evaluate on the last `eval_segments` (pooled: a single
-    walk's smoothness swings the hold baseline's error several-fold).
-    Returns a summary dict."""
+    held-out segment, evaluate on the last ones (pooled: a single walk's
+    smoothness swings the hold baseline's error several-fold).
+
+    `batch` copies of the scene are stepped together, one walk each: every
+    copy first takes a warm-up walk, then the copies walk in rounds; the
+    training walks are train_segments rounded up to a multiple of the batch,
+    the first walk after them is the held-out one and the rest, at least
+    eval_segments, are evaluated.  A copy's walk starts where its previous one
+    ended.  Returns a summary dict."""
     import time
     import torch
+    k = int(batch)
     sc = scenes.haptic_scene(n_fluid=n_fluid)
-    sim = make_sim(sc, max_ticks=max(warmup_ticks, ticks, eval_ticks))
+    sim = make_sim(sc, max_ticks=max(warmup_ticks, ticks, eval_ticks), batch=k)
     lo, hi = sc.info["walk_lo"], sc.info["walk_hi"]
-    c = sc.info["c0"]
+    cs = [sc.info["c0"]] * k
+    n_train = -(-train_segments // k) * k
+    n_eval = -(-(1 + eval_segments) // k) * k
+    rounds = [(warmup_ticks, [11 + i for i in range(k)])]
+    rounds += [(ticks, [101 + j for j in range(r, r + k)]) for r in range(0, n_train, k)]
+    ev = [801] + [901 + j for j in range(n_eval - 1)]
+    rounds += [(eval_ticks, ev[r:r + k]) for r in range(0, n_eval, k)]
     logs = []
-    segs = [(warmup_ticks, 11)] + [(ticks, 101 + i) for i in range(train_segments)] + \
-        [(eval_ticks, 801)] + [(eval_ticks, 901 + i) for i in range(eval_segments)]
     t0 = time.perf_counter()
-    for n, sd in segs:
-        walk = scenes.smooth_walk(sd, n, c, lo, hi)
-        logs.append(collect(sim, sc, walk))
-        c = walk[0][-1] + 1e-3 * walk[2][-1]
-        log(f"  collected {n} ticks (walk seed {sd})")
+    for n, seeds in rounds:
+        walks = [scenes.smooth_walk(sd, n, c, lo, hi) for sd, c in zip(seeds, cs)]
+        logs += collect(sim, sc, walks)
+        cs = [w[0][-1] + 1e-3 * w[2][-1] for w in walks]
+        log(f"  collected {n} ticks x {k} (walk seeds {seeds[0]}..{seeds[-1]})")
     t_collect = time.perf_counter() - t0
-    rows = [training_rows(lg) for lg in logs[1:1 + train_segments]]
+    logs = logs[k:]                                  # warm-up walks
+    rows = [training_rows(lg) for lg in logs[:n_train]]
     X = torch.from_numpy(np.concatenate([r[0] for r in rows])).to("cuda")
     Y = torch.from_numpy(np.concatenate([r[1] for r in rows])).to("cuda")
+    del rows
     net = make_net(seed=seed)
     t0 = time.perf_counter()
-    hold = logs[1 + train_segments]
-    hist = train(net, X, Y, steps, seed=seed, holdout=(hold, sc))
+    hist = train(net, X, Y, steps, seed=seed, holdout=(logs[n_train], sc))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    errs = evaluate(net, logs[2 + train_segments:], sc)
+    errs = evaluate(net, logs[n_train + 1:], sc)
     rate = haptic_rate(net, eval_rows(logs[-1])[2][0])
-    return {"scene": sc.name, "n_particles": int(sc.n), "training_rows": int(X.shape[0]),
-            "ticks_collected": int(sum(n for n, _ in segs)), "collect_s": t_collect, "train_s": t_train,
-            "train_steps": steps, "best_holdout_error": min(h[2] for h in hist), "errors": errs, **rate}
+    return {"scene": sc.name, "n_particles": int(sc.n), "batch": k, "training_walks": n_train,
+            "eval_walks": n_eval - 1, "training_rows": int(X.shape[0]),
+            "ticks_collected": int(sum(n * len(sd) for n, sd in rounds)), "collect_s": t_collect,
+            "train_s": t_train, "train_steps": steps, "best_holdout_error": min(h[2] for h in hist),
+            "errors": errs, **rate}
 
 
 if __name__ == "__main__":
@@ -302,7 +335,9 @@ if __name__ == "__main__":
     ap.add_argument("--ticks", type=int, default=3000)
     ap.add_argument("--eval-ticks", type=int, default=1500)
     ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--eval-segments", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=1, help="scene copies stepped together, one walk each")
     a = ap.parse_args()
-    r = run_experiment(a.n_fluid, a.segments, a.ticks, a.eval_ticks, a.steps,
-                       log=lambda m: print(m, flush=True))
+    r = run_experiment(a.n_fluid, a.segments, a.ticks, a.eval_ticks, a.steps, eval_segments=a.eval_segments,
+                       batch=a.batch, log=lambda m: print(m, flush=True))
     print(json.dumps(r), flush=True)

@@ -3,26 +3,60 @@ of the 100k-particle haptic scene (a 1 kHz hand-like walk of the grabbed
 sphere, 4 SPH steps per tick, 40 ms haptic rolling mean), training by the
 library's own forward/backward/Adam kernels, and the gain over the haptic
 loop without the network (zero-order hold of the 100 Hz SPH wrench, and the
-hold followed by a rolling mean) on three walks it never saw, judged against
-plain SPH at every tick."""
+hold followed by a rolling mean) on fifteen walks it never saw, judged
+against plain SPH at every tick.  The logs come from sixteen copies of the
+scene stepped together, one walk each."""
+import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
+
+
+def test_batched_collection_equals_one_context_per_walk():
+    """Logs collected on a batch of scene copies (one walk each, two walks in
+    a row so the rolling-mean tail carries over) bitwise equal to one context
+    per walk."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2511_15908_amd import scenes
+    from paper_2511_15908_amd import surrogate as S
+    sc = scenes.haptic_scene(n_fluid=100_000)     # footprint wide enough for the walk box
+    lo, hi = sc.info["walk_lo"], sc.info["walk_hi"]
+    seeds = [(5, 7), (6, 8), (9, 10)]
+    n = (40, 25)
+    batch = S.make_sim(sc, max_ticks=max(n), batch=len(seeds))
+    singles = [S.make_sim(sc, max_ticks=max(n)) for _ in seeds]
+    cs = [sc.info["c0"]] * len(seeds)
+    for r in range(2):
+        walks = [scenes.smooth_walk(sd[r], n[r], c, lo, hi) for sd, c in zip(seeds, cs)]
+        got = S.collect(batch, sc, walks)
+        assert len(got) == len(seeds)
+        for i, w in enumerate(walks):
+            ref = S.collect(singles[i], sc, w)
+            for key in ("c", "q", "v", "w", "wrench", "probes"):
+                assert got[i][key].shape == ref[key].shape, (r, i, key)
+                assert np.array_equal(got[i][key], ref[key]), (r, i, key)
+            assert np.count_nonzero(ref["probes"]) > 0 and np.abs(ref["wrench"]).max() > 0
+        cs = [w[0][-1] + 1e-3 * w[2][-1] for w in walks]
+    # the copies walked apart
+    assert not np.array_equal(got[0]["wrench"], got[1]["wrench"])
 
 
 def test_surrogate_beats_hold_between_sph_updates():
     import torch
     assert torch.cuda.is_available(), "GPU tests need a visible GPU"
     from paper_2511_15908_amd import surrogate as S
-    r = S.run_experiment(train_segments=4, ticks=3000, eval_ticks=1500, steps=1500,
+    r = S.run_experiment(train_segments=16, ticks=1500, eval_ticks=1000, eval_segments=15, steps=1500, batch=16,
                          log=lambda m: print(m, flush=True))
+    assert r["training_walks"] == 16 and r["eval_walks"] == 15
     e = r["errors"]
     print({k: round(v["mean"], 4) for k, v in e.items()}, "p95",
           {k: round(v["p95"], 4) for k, v in e.items()},
           f"rates {r['host_round_trip_hz']:.0f} Hz host, {r['device_chain_hz']:.0f} Hz device")
-    # pooled over three evaluation walks; the hold's error swings several-fold
-    # with a walk's smoothness, the surrogate's much less: it must beat both
-    # baselines on the mean and the hold clearly on the tail
+    # pooled over fifteen walks: the hold's error swings several-fold with a
+    # walk's smoothness, the surrogate's on a walk that leaves the states the
+    # training walks covered; it must beat both baselines on the mean and the
+    # hold clearly on the tail
     base = min(e["zero_order_hold"]["mean"], e["hold_rolling_mean"]["mean"])
     assert e["surrogate"]["mean"] < base
     assert e["surrogate"]["p95"] < 0.85 * e["zero_order_hold"]["p95"]
