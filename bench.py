@@ -285,6 +285,9 @@ def main():
             "tick_rate_hz": {"host_round_trip": round(r["host_round_trip_hz"], 1),
                              "device_chain": round(r["device_chain_hz"], 1)},
             "eval_walks": r["eval_walks"],
+            # "surrogate": the haptic loop with its plain-SPH fallback (rows outside the
+            # training range keep the last SPH wrench); "network_only": the network alone
+            "fallback": {"margin": S.GUARD_MARGIN, "rows_frac": round(e["surrogate"].get("fallback_frac", 0.0), 4)},
             "training": {"walks": r["training_walks"], "rows": r["training_rows"], "steps": r["train_steps"],
                          "seconds": round(r["train_s"], 2), "scene_copies_stepped_together": r["batch"],
                          "ticks_simulated": r["ticks_collected"], "collect_seconds": round(r["collect_s"], 1)}}

@@ -92,6 +92,29 @@ mlp_status mlp_set_normalizer(mlp_ctx *ctx, const float *mu_x, const float *sd_x
                               const float *sd_y);
 mlp_status mlp_get_normalizer(mlp_ctx *ctx, float *mu_x, float *sd_x, float *mu_y, float *sd_y);
 
+/*
+ * Plain SPH as the fallback (Sec. 3.3: the learned force stands in for the
+ * simulator between its updates; where the network would extrapolate, the
+ * haptic loop keeps the simulator's own last wrench).  mlp_fit_normalizer also
+ * records the minimum lo_j and maximum hi_j of every input column of X;
+ * mlp_set_input_range sets them from host arrays (n_in floats each, finite,
+ * lo <= hi) and mlp_get_input_range reads them back.  mlp_set_guard(margin)
+ * with margin >= 0 turns the guard on: with w_j = hi_j - lo_j and, in FP32,
+ * a_j = lo_j - margin w_j, b_j = hi_j + margin w_j, a row whose input fails
+ * a_j <= x_j <= b_j in some column (NaN included) gets the residual base
+ * instead of the network's output: out_j = x[residual_from - 1 + j], for the
+ * wrench surrogate the last SPH wrench (zero-order hold).  mlp_forward and
+ * both haptic-tick calls apply it; training and mlp_gradients never do.
+ * margin < 0 turns it off (the default).  Errors: MLP_ERR_ARG
+ * for a model without residual_from or a bad range, MLP_ERR_STATE when no
+ * range was fitted or set.  mlp_guard_count: out[0] rows checked by guarded
+ * calls since init, out[1] rows that fell back (synchronises).
+ */
+mlp_status mlp_set_input_range(mlp_ctx *ctx, const float *lo, const float *hi);
+mlp_status mlp_get_input_range(mlp_ctx *ctx, float *lo, float *hi);
+mlp_status mlp_set_guard(mlp_ctx *ctx, float margin);
+mlp_status mlp_guard_count(mlp_ctx *ctx, uint64_t out[2]);
+
 /* Batched inference: out [m][n_out] (raw units) from X [m][n_in] (raw), m <= max_batch. */
 mlp_status mlp_forward(mlp_ctx *ctx, const float *X, uint32_t m, float *out);
 

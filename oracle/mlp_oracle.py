@@ -16,7 +16,12 @@ What it computes (plain numpy, binary64):
   * the loss L = 1/(m n_out) sum (out' - y')^2 over the first n_out outputs and
     its gradient by the chain rule (backpropagation written out per layer);
   * Adam (Kingma and Ba 2015, Algorithm 1: moment estimates with bias
-    correction).
+    correction);
+  * the plain-SPH fallback of the haptic loop: a row whose input leaves the
+    training range (column minimum and maximum, widened by margin times the
+    range on each side) returns the residual base, the simulator's own last
+    wrench, instead of the network's output (the decision in FP32, as the
+    library takes it).
 With quant=True the values that the GPU path feeds to its BF16 matrix
 products (weights, standardised inputs, hidden activations, output and
 hidden-layer gradients) are rounded to BF16 at the same points; everything
@@ -100,6 +105,36 @@ def fit_normalizer(X, Y, res_col=None):
     sx = np.where(sx < 1e-12, 1.0, sx)
     sy = np.where(sy < 1e-12, 1.0, sy)
     return mx, sx, my, sy
+
+
+def input_range(X):
+    """Column minimum and maximum of the training inputs."""
+    X = np.asarray(X, np.float32)
+    return X.min(0), X.max(0)
+
+
+def guard_bounds(lo, hi, margin):
+    """a = lo - margin (hi - lo), b = hi + margin (hi - lo), each operation
+    rounded to FP32."""
+    lo, hi = np.asarray(lo, np.float32), np.asarray(hi, np.float32)
+    mw = np.float32(margin) * (hi - lo)
+    return lo - mw, hi + mw
+
+
+def guard_rows(X, lo, hi, margin):
+    """True for rows with a column outside [a, b] (NaN counts as outside)."""
+    a, b = guard_bounds(lo, hi, margin)
+    X = np.asarray(X, np.float32)
+    inside = (X >= a) & (X <= b)
+    return ~inside.all(1)
+
+
+def guarded(out, X, lo, hi, margin, n_out, res_col):
+    """The haptic loop's output: the network's where the row is inside the
+    range, the residual base (input columns res_col ..) where it is not."""
+    fall = guard_rows(X, lo, hi, margin)
+    base = np.asarray(X, np.float64)[:, res_col:res_col + n_out]
+    return np.where(fall[:, None], base, out), fall
 
 
 def _q(a, quant):

@@ -310,22 +310,44 @@ void launch_to_bf16(hipStream_t s, const float *w, uint16_t *wb, uint32_t count)
 }
 
 __global__ void k_destandardize(const float *__restrict__ out, uint32_t m, uint32_t n_out, const float *__restrict__ mu,
-                                const float *__restrict__ sd, Residual res, float *__restrict__ Y)
+                                const float *__restrict__ sd, Residual res, const uint8_t *__restrict__ flags,
+                                float *__restrict__ Y)
 {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
     if (i >= m * n_out) return;
     const uint32_t r = i / n_out, j = i % n_out;
-    float y = out[(size_t)r * kOutPad + j] * sd[j] + mu[j];
+    const bool fall = flags && flags[r];
+    float y = fall ? 0.0f : out[(size_t)r * kOutPad + j] * sd[j] + mu[j];
     if (res.X) y += res.X[(size_t)r * res.ldx + res.col0 + j];
     Y[i] = y;
 }
 
 void launch_destandardize(hipStream_t s, const float *out, uint32_t m, uint32_t n_out, const float *mu,
-                          const float *sd, const Residual &res, float *Y)
+                          const float *sd, const Residual &res, const uint8_t *flags, float *Y)
 {
     if (!m) return;
     hipLaunchKernelGGL(k_destandardize, dim3((m * n_out + 255) / 256), dim3(256), 0, s, out, m, n_out, mu, sd, res,
-                       Y);
+                       flags, Y);
+}
+
+__device__ __forceinline__ bool in_range(float x, float a, float b) { return x >= a && x <= b; }
+
+// One thread per row: the guard's decision for the row.
+__global__ void k_guard_rows(const float *__restrict__ X, uint32_t m, uint32_t n_in, Guard g,
+                             uint8_t *__restrict__ flags)
+{
+    const uint32_t r = blockIdx.x * 256u + threadIdx.x;
+    if (r >= m) return;
+    bool out = false;
+    for (uint32_t j = 0; j < n_in; ++j) out = out || !in_range(X[(size_t)r * n_in + j], g.a[j], g.b[j]);
+    flags[r] = out ? 1u : 0u;
+    if (out) atomicAdd(g.count, 1ull);
+}
+
+void launch_guard_rows(hipStream_t s, const float *X, uint32_t m, uint32_t n_in, const Guard &g, uint8_t *flags)
+{
+    if (!m) return;
+    hipLaunchKernelGGL(k_guard_rows, dim3((m + 255) / 256), dim3(256), 0, s, X, m, n_in, g, flags);
 }
 
 // Column mean and population standard deviation (two passes, FP64 sums, fixed
@@ -339,17 +361,35 @@ __device__ __forceinline__ double fit_value(const float *__restrict__ X, uint32_
 }
 
 __global__ __launch_bounds__(256) void k_fit_normalizer(const float *__restrict__ X, uint32_t m, uint32_t cols,
-                                                        Residual res, float *__restrict__ mu, float *__restrict__ sd)
+                                                        Residual res, float *__restrict__ mu, float *__restrict__ sd,
+                                                        float *__restrict__ lo, float *__restrict__ hi)
 {
     __shared__ double red[256];
+    __shared__ float rlo[256], rhi[256];
     const uint32_t c = blockIdx.x, t = threadIdx.x;
     double s = 0.0;
-    for (uint32_t r = t; r < m; r += 256u) s += fit_value(X, cols, res, r, c);
+    float vlo = __builtin_huge_valf(), vhi = -__builtin_huge_valf();
+    for (uint32_t r = t; r < m; r += 256u) {
+        s += fit_value(X, cols, res, r, c);
+        const float x = X[(size_t)r * cols + c];
+        vlo = fminf(vlo, x);
+        vhi = fmaxf(vhi, x);
+    }
     red[t] = s;
+    rlo[t] = vlo;
+    rhi[t] = vhi;
     __syncthreads();
     for (uint32_t h = 128; h > 0; h >>= 1) {
-        if (t < h) red[t] += red[t + h];
+        if (t < h) {
+            red[t] += red[t + h];
+            rlo[t] = fminf(rlo[t], rlo[t + h]);
+            rhi[t] = fmaxf(rhi[t], rhi[t + h]);
+        }
         __syncthreads();
+    }
+    if (t == 0 && lo) {
+        lo[c] = rlo[0];
+        hi[c] = rhi[0];
     }
     const double mean = red[0] / (double)m;
     __syncthreads();
@@ -372,10 +412,10 @@ __global__ __launch_bounds__(256) void k_fit_normalizer(const float *__restrict_
 }
 
 void launch_fit_normalizer(hipStream_t s, const float *X, uint32_t m, uint32_t cols, const Residual &res, float *mu,
-                           float *sd)
+                           float *sd, float *lo, float *hi)
 {
     if (!cols) return;
-    hipLaunchKernelGGL(k_fit_normalizer, dim3(cols), dim3(256), 0, s, X, m, cols, res, mu, sd);
+    hipLaunchKernelGGL(k_fit_normalizer, dim3(cols), dim3(256), 0, s, X, m, cols, res, mu, sd, lo, hi);
 }
 
 __global__ void k_fill_f32(float *__restrict__ p, float v, uint32_t count)
@@ -394,11 +434,20 @@ void launch_fill_f32(hipStream_t s, float *p, float v, uint32_t count)
 
 // The whole network for one sample in one workgroup: thread u computes unit u
 // of each layer from the previous activation vector held in LDS (BF16 values,
-// FP32 arithmetic, ascending contraction order).
+// FP32 arithmetic, ascending contraction order).  With the guard on, a sample
+// outside the training range skips the network and returns the residual base.
 __global__ __launch_bounds__(256) void k_predict_one(PredictArgs a)
 {
     __shared__ float act[256];
     const uint32_t t = threadIdx.x;
+    if (a.guard.a) {
+        const bool out = t < a.n_in && !in_range(a.x[t], a.guard.a[t], a.guard.b[t]);
+        if (__syncthreads_or(out)) {                        // uniform
+            if (t < a.n_out) a.y[t] = a.x[a.res_col0 + (int32_t)t];
+            if (t == 0) atomicAdd(a.guard.count, 1ull);
+            return;
+        }
+    }
     if (t < kIn) {
         float v = 0.f;
         if (t < a.n_in) v = (a.x[t] - a.mu_x[t]) / a.sd_x[t];

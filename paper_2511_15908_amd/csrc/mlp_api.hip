@@ -33,6 +33,14 @@ struct mlp_ctx {
     uint32_t max_splits = 1;
     double *loss_part = nullptr, *loss = nullptr;
     float *px = nullptr, *py = nullptr;
+    // training-range guard (plain-SPH fallback)
+    float *xlo = nullptr, *xhi = nullptr;        // device: fitted column range
+    float *ga = nullptr, *gb = nullptr;          // device: guard bounds a_j, b_j
+    uint8_t *gflags = nullptr;                   // [max_batch] rows that fell back
+    unsigned long long *gcount = nullptr;        // rows that fell back
+    std::vector<float> lo, hi;                   // host copy of the range (empty: none)
+    float margin = -1.0f;                        // < 0: guard off
+    uint64_t guarded_rows = 0;
     uint64_t t = 0;                     // Adam steps taken
     bool dead = false;
     std::string last_error;
@@ -152,6 +160,12 @@ size_t carve(mlp_ctx *c, char *base)
     c->loss = cv.take<double>(1);
     c->px = cv.take<float>(kIn);
     c->py = cv.take<float>(kOutPad);
+    c->xlo = cv.take<float>(kIn);
+    c->xhi = cv.take<float>(kIn);
+    c->ga = cv.take<float>(kIn);
+    c->gb = cv.take<float>(kIn);
+    c->gflags = cv.take<uint8_t>(B);
+    c->gcount = cv.take<unsigned long long>(1);
     return cv.off;
 }
 
@@ -298,6 +312,30 @@ mlp_status check_batch(mlp_ctx *c, const void *X, uint32_t m)
 
 extern "C" {
 
+// Guard bounds a_j = lo_j - margin w_j, b_j = hi_j + margin w_j in FP32 (one
+// rounding per operation, no fused multiply-add), uploaded when the guard is on.
+static mlp_status upload_guard(mlp_ctx *c)
+{
+    if (c->margin < 0.0f || c->lo.empty()) return MLP_OK;
+    const uint32_t n = c->cfg.n_in;
+    std::vector<float> a(n), b(n);
+    for (uint32_t j = 0; j < n; ++j) {
+        const float w = c->hi[j] - c->lo[j];
+        const float mw = c->margin * w;
+        a[j] = c->lo[j] - mw;
+        b[j] = c->hi[j] + mw;
+    }
+    MLPCHK(c, hipMemcpyAsync(c->ga, a.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+    MLPCHK(c, hipMemcpyAsync(c->gb, b.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+    MLPCHK(c, hipStreamSynchronize(c->stream));
+    return MLP_OK;
+}
+
+static Guard guard_of(const mlp_ctx *c)
+{
+    return c->margin >= 0.0f ? Guard{c->ga, c->gb, c->gcount} : Guard{nullptr, nullptr, nullptr};
+}
+
 mlp_status mlp_workspace_size(const mlp_config *cfg, size_t *bytes)
 {
     std::string why;
@@ -337,6 +375,7 @@ mlp_status mlp_init(const mlp_config *cfg, void *d_workspace, size_t ws_bytes, v
     launch_fill_f32(s, c->sd_x, 1.f, kIn);
     launch_fill_f32(s, c->mu_y, 0.f, kOutPad);
     launch_fill_f32(s, c->sd_y, 1.f, kOutPad);
+    launch_fill_f32(s, reinterpret_cast<float *>(c->gcount), 0.f, 2);
     refresh_bf16(c);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -388,10 +427,12 @@ mlp_status mlp_fit_normalizer(mlp_ctx *c, const float *X, const float *Y, uint32
     if (!c) return MLP_ERR_ARG;
     if (c->dead) return MLP_ERR_STATE;
     if (m < 1 || !X || !Y) return arg_fail(c, "m >= 1 and device arrays required");
-    launch_fit_normalizer(c->stream, X, m, c->cfg.n_in, Residual{nullptr, 0, 0}, c->mu_x, c->sd_x);
-    launch_fit_normalizer(c->stream, Y, m, c->cfg.n_out, residual(c, X), c->mu_y, c->sd_y);
+    launch_fit_normalizer(c->stream, X, m, c->cfg.n_in, Residual{nullptr, 0, 0}, c->mu_x, c->sd_x, c->xlo, c->xhi);
+    launch_fit_normalizer(c->stream, Y, m, c->cfg.n_out, residual(c, X), c->mu_y, c->sd_y, nullptr, nullptr);
     MLPCHK(c, hipGetLastError());
-    std::vector<float> a(kIn), b(kIn), d(kOutPad), e(kOutPad);
+    std::vector<float> a(kIn), b(kIn), d(kOutPad), e(kOutPad), lo(c->cfg.n_in), hi(c->cfg.n_in);
+    MLPCHK(c, hipMemcpyAsync(lo.data(), c->xlo, c->cfg.n_in * 4, hipMemcpyDeviceToHost, c->stream));
+    MLPCHK(c, hipMemcpyAsync(hi.data(), c->xhi, c->cfg.n_in * 4, hipMemcpyDeviceToHost, c->stream));
     MLPCHK(c, hipMemcpyAsync(a.data(), c->mu_x, kIn * 4, hipMemcpyDeviceToHost, c->stream));
     MLPCHK(c, hipMemcpyAsync(b.data(), c->sd_x, kIn * 4, hipMemcpyDeviceToHost, c->stream));
     MLPCHK(c, hipMemcpyAsync(d.data(), c->mu_y, kOutPad * 4, hipMemcpyDeviceToHost, c->stream));
@@ -401,7 +442,11 @@ mlp_status mlp_fit_normalizer(mlp_ctx *c, const float *X, const float *Y, uint32
         if (!isfinite(a[i]) || !isfinite(b[i])) return MLP_ERR_NONFINITE;
     for (uint32_t i = 0; i < c->cfg.n_out; ++i)
         if (!isfinite(d[i]) || !isfinite(e[i])) return MLP_ERR_NONFINITE;
-    return MLP_OK;
+    for (uint32_t i = 0; i < c->cfg.n_in; ++i)
+        if (!isfinite(lo[i]) || !isfinite(hi[i])) return MLP_ERR_NONFINITE;
+    c->lo = lo;
+    c->hi = hi;
+    return upload_guard(c);
 }
 
 mlp_status mlp_set_normalizer(mlp_ctx *c, const float *mu_x, const float *sd_x, const float *mu_y, const float *sd_y)
@@ -444,8 +489,65 @@ mlp_status mlp_forward(mlp_ctx *c, const float *X, uint32_t m, float *out)
     if (st != MLP_OK) return st;
     if (!out) return arg_fail(c, "null output");
     forward(c, X, m);
-    launch_destandardize(c->stream, c->out, m, c->cfg.n_out, c->mu_y, c->sd_y, residual(c, X), out);
+    const Guard g = guard_of(c);
+    if (g.a) {
+        launch_guard_rows(c->stream, X, m, c->cfg.n_in, g, c->gflags);
+        c->guarded_rows += m;
+    }
+    launch_destandardize(c->stream, c->out, m, c->cfg.n_out, c->mu_y, c->sd_y, residual(c, X),
+                         g.a ? c->gflags : nullptr, out);
     MLPCHK(c, hipGetLastError());
+    return MLP_OK;
+}
+
+mlp_status mlp_set_input_range(mlp_ctx *c, const float *lo, const float *hi)
+{
+    if (!c) return MLP_ERR_ARG;
+    if (c->dead) return MLP_ERR_STATE;
+    if (!lo || !hi) return arg_fail(c, "null range array");
+    const uint32_t n = c->cfg.n_in;
+    for (uint32_t j = 0; j < n; ++j)
+        if (!isfinite(lo[j]) || !isfinite(hi[j]) || !(lo[j] <= hi[j])) return arg_fail(c, "bad input range");
+    c->lo.assign(lo, lo + n);
+    c->hi.assign(hi, hi + n);
+    return upload_guard(c);
+}
+
+mlp_status mlp_get_input_range(mlp_ctx *c, float *lo, float *hi)
+{
+    if (!c) return MLP_ERR_ARG;
+    if (c->dead) return MLP_ERR_STATE;
+    if (!lo || !hi) return arg_fail(c, "null range array");
+    if (c->lo.empty()) return MLP_ERR_STATE;
+    std::copy(c->lo.begin(), c->lo.end(), lo);
+    std::copy(c->hi.begin(), c->hi.end(), hi);
+    return MLP_OK;
+}
+
+mlp_status mlp_set_guard(mlp_ctx *c, float margin)
+{
+    if (!c) return MLP_ERR_ARG;
+    if (c->dead) return MLP_ERR_STATE;
+    if (isnan(margin) || isinf(margin)) return arg_fail(c, "margin must be finite");
+    if (margin < 0.0f) {
+        c->margin = -1.0f;
+        return MLP_OK;
+    }
+    if (!c->cfg.residual_from) return arg_fail(c, "the guard's fallback is the residual base: set residual_from");
+    if (c->lo.empty()) return MLP_ERR_STATE;
+    c->margin = margin;
+    return upload_guard(c);
+}
+
+mlp_status mlp_guard_count(mlp_ctx *c, uint64_t out[2])
+{
+    if (!c || !out) return MLP_ERR_ARG;
+    if (c->dead) return MLP_ERR_STATE;
+    unsigned long long n = 0;
+    MLPCHK(c, hipMemcpyAsync(&n, c->gcount, sizeof(n), hipMemcpyDeviceToHost, c->stream));
+    MLPCHK(c, hipStreamSynchronize(c->stream));
+    out[0] = c->guarded_rows;
+    out[1] = (uint64_t)n;
     return MLP_OK;
 }
 
@@ -516,6 +618,8 @@ static PredictArgs predict_args(mlp_ctx *c, const float *x, float *y)
     a.hidden = c->H;
     a.layers = c->L;
     a.res_col0 = c->cfg.residual_from ? (int32_t)c->cfg.residual_from - 1 : -1;
+    a.guard = guard_of(c);
+    if (a.guard.a) c->guarded_rows += 1;
     return a;
 }
 

@@ -54,10 +54,19 @@ void launch_bias_grad(hipStream_t s, const uint16_t *dz, uint32_t m, uint32_t n,
 void launch_adam(hipStream_t s, float *w, float *m1, float *m2, const float *g, uint16_t *wb, uint32_t count,
                  float lr, float beta1, float beta2, float eps, float bc1, float bc2);
 void launch_to_bf16(hipStream_t s, const float *w, uint16_t *wb, uint32_t count);
+// flags (null: none): rows whose output is the residual base alone.
 void launch_destandardize(hipStream_t s, const float *out, uint32_t m, uint32_t n_out, const float *mu,
-                          const float *sd, const Residual &res, float *Y);
+                          const float *sd, const Residual &res, const uint8_t *flags, float *Y);
+// lo, hi (null: not wanted): column minimum and maximum of X.
 void launch_fit_normalizer(hipStream_t s, const float *X, uint32_t m, uint32_t cols, const Residual &res, float *mu,
-                           float *sd);
+                           float *sd, float *lo, float *hi);
+// Training-range guard: a row falls back when some column j fails
+// a[j] <= x_j <= b[j] (NaN included); count (device) adds the rows that did.
+struct Guard {
+    const float *a, *b;          // null: guard off
+    unsigned long long *count;
+};
+void launch_guard_rows(hipStream_t s, const float *X, uint32_t m, uint32_t n_in, const Guard &g, uint8_t *flags);
 void launch_fill_f32(hipStream_t s, float *p, float v, uint32_t count);
 
 struct PredictArgs {
@@ -68,6 +77,7 @@ struct PredictArgs {
     const float *mu_x, *sd_x, *mu_y, *sd_y;
     uint32_t n_in, n_out, hidden, layers;
     int32_t res_col0;    // first residual input column, or -1
+    Guard guard;         // out of the training range: y = residual base
 };
 void launch_predict_one(hipStream_t s, const PredictArgs &a);
 

@@ -19,7 +19,8 @@ STATUS = {0: "MLP_OK", 1: "MLP_ERR_ARG", 2: "MLP_ERR_WORKSPACE", 3: "MLP_ERR_DEV
 EXPORTED = ["mlp_workspace_size", "mlp_init", "mlp_param_count", "mlp_set_params", "mlp_get_params",
             "mlp_fit_normalizer", "mlp_set_normalizer", "mlp_get_normalizer", "mlp_forward", "mlp_gradients",
             "mlp_adam_step", "mlp_train_step", "mlp_last_loss", "mlp_predict_one", "mlp_predict_one_device",
-            "mlp_gemm_bf16", "mlp_destroy", "mlp_last_error"]
+            "mlp_gemm_bf16", "mlp_destroy", "mlp_last_error", "mlp_set_input_range", "mlp_get_input_range",
+            "mlp_set_guard", "mlp_guard_count"]
 
 
 class MlpError(RuntimeError):
@@ -61,6 +62,10 @@ def lib():
         L.mlp_predict_one_device.argtypes = [vp, vp, vp]
         L.mlp_gemm_bf16.argtypes = [vp, C.c_int, C.c_int, vp, C.c_uint32, vp, C.c_uint32, C.c_uint32, C.c_uint32,
                                     C.c_uint32, vp, C.c_uint32]
+        L.mlp_set_input_range.argtypes = [vp, f32p, f32p]
+        L.mlp_get_input_range.argtypes = [vp, f32p, f32p]
+        L.mlp_set_guard.argtypes = [vp, C.c_float]
+        L.mlp_guard_count.argtypes = [vp, C.POINTER(C.c_uint64)]
         L.mlp_destroy.argtypes = [vp]
         L.mlp_last_error.argtypes = [vp]
         L.mlp_last_error.restype = C.c_char_p
@@ -146,6 +151,27 @@ class Mlp:
              np.zeros(self.n_out, np.float32), np.zeros(self.n_out, np.float32)]
         self._check(self.L.mlp_get_normalizer(self.ctx, *[_fp(v) for v in a]), "mlp_get_normalizer")
         return a
+
+    def set_input_range(self, lo, hi):
+        a = [np.ascontiguousarray(v, np.float32) for v in (lo, hi)]
+        self._check(self.L.mlp_set_input_range(self.ctx, *[_fp(v) for v in a]), "mlp_set_input_range")
+
+    def get_input_range(self):
+        a = [np.zeros(self.n_in, np.float32), np.zeros(self.n_in, np.float32)]
+        self._check(self.L.mlp_get_input_range(self.ctx, *[_fp(v) for v in a]), "mlp_get_input_range")
+        return a
+
+    def set_guard(self, margin):
+        """Plain-SPH fallback: rows outside the training range (widened by
+        margin x range per side) return the residual base; margin < 0: off."""
+        self._check(self.L.mlp_set_guard(self.ctx, float(margin)), "mlp_set_guard")
+        self.guard_margin = float(margin) if margin >= 0 else -1.0
+
+    def guard_count(self):
+        """(rows checked by guarded calls, rows that fell back) since init."""
+        v = (C.c_uint64 * 2)()
+        self._check(self.L.mlp_guard_count(self.ctx, v), "mlp_guard_count")
+        return int(v[0]), int(v[1])
 
     def forward(self, X):
         X = self._f32(X, self.n_in)

@@ -44,6 +44,7 @@ def init_params(seed, hidden, layers, n_in, n_out):
 
 N_HIST = 8
 SPH_EVERY = 10
+GUARD_MARGIN = 0.5     # plain-SPH fallback outside the training range widened by half of it per side
 N_PROBES = 64
 N_FEATURES = 13 + 6 * N_HIST + N_PROBES + 1
 RES_COL = 13
@@ -232,21 +233,37 @@ def train(net, X, Y, steps, batch=4096, lr0=1e-3, lr1=1e-5, seed=1, holdout=None
 def evaluate(net, logs, scene):
     """Errors of the surrogate and of the two baselines on the ticks between
     SPH updates (d > 0), against the plain-SPH haptic wrench at every tick;
-    `logs` is one log or a list, whose ticks are pooled."""
+    `logs` is one log or a list, whose ticks are pooled.  With the network's
+    guard on, "surrogate" is the haptic loop with its plain-SPH fallback and
+    "network_only" the network's own outputs; surrogate.fallback_frac is the
+    share of evaluated rows (every tick) that fell back."""
     if isinstance(logs, dict):
         logs = [logs]
-    errs = {"surrogate": [], "zero_order_hold": [], "hold_rolling_mean": []}
+    margin = getattr(net, "guard_margin", -1.0)
+    names = ("surrogate", "network_only", "zero_order_hold", "hold_rolling_mean")
+    errs = {k: [] for k in names}
+    n0 = net.guard_count() if margin >= 0 else (0, 0)
     for log in logs:
         t, d, (X, Y) = eval_rows(log)
         truth = Y.astype(np.float64)
         zoh, avg = baselines(log, t, d)
-        for name, p in (("surrogate", predict(net, X)), ("zero_order_hold", zoh), ("hold_rolling_mean", avg)):
-            errs[name].append(wrench_errors(p, truth, scene)[d > 0])
+        p = predict(net, X)
+        if margin >= 0:
+            net.set_guard(-1.0)
+            p_net = predict(net, X)
+            net.set_guard(margin)
+        else:
+            p_net = p
+        for name, q in zip(names, (p, p_net, zoh, avg)):
+            errs[name].append(wrench_errors(q, truth, scene)[d > 0])
     out = {}
     for name, parts in errs.items():
         e = np.concatenate(parts)
         out[name] = {"mean": float(e.mean()), "p50": float(np.median(e)), "p95": float(np.percentile(e, 95)),
                      "max": float(e.max()), "walk_means": [float(x.mean()) for x in parts]}
+    if margin >= 0:
+        n1 = net.guard_count()
+        out["surrogate"]["fallback_frac"] = (n1[1] - n0[1]) / max(n1[0] - n0[0], 1)
     return out
 
 
@@ -274,7 +291,7 @@ def haptic_rate(net, X, n=500):
 
 
 def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=1500, steps=1500, seed=1,
-                   warmup_ticks=300, eval_segments=3, batch=1, log=print):
+                   warmup_ticks=300, eval_segments=3, batch=1, guard_margin=GUARD_MARGIN, log=print):
     """Collect plain-SPH haptic logs (a 1 kHz smooth walk per segment, 4 SPH
     steps per tick), train on the first segments with early stopping on a
     held-out segment, evaluate on the last ones (pooled: a single walk's
@@ -285,7 +302,8 @@ def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=150
     training walks are train_segments rounded up to a multiple of the batch,
     the first walk after them is the held-out one and the rest, at least
     eval_segments, are evaluated.  A copy's walk starts where its previous one
-    ended.  Returns a summary dict."""
+    ended.  After training the network's plain-SPH fallback is set with
+    guard_margin (None: no fallback).  Returns a summary dict."""
     import time
     import torch
     k = int(batch)
@@ -317,6 +335,8 @@ def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=150
     hist = train(net, X, Y, steps, seed=seed, holdout=(logs[n_train], sc))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    if guard_margin is not None and guard_margin >= 0:
+        net.set_guard(guard_margin)
     errs = evaluate(net, logs[n_train + 1:], sc)
     rate = haptic_rate(net, eval_rows(logs[-1])[2][0])
     return {"scene": sc.name, "n_particles": int(sc.n), "batch": k, "training_walks": n_train,

@@ -199,3 +199,59 @@ def test_residual_output_matches_oracle(torch):
     assert loss_gpu == pytest.approx(loss_o, rel=2e-3)
     rel = np.linalg.norm(g_gpu - g_o) / np.linalg.norm(g_o)
     assert rel < 2e-3
+
+
+def test_guard_falls_back_to_residual_base(torch):
+    """Plain-SPH fallback: the fitted range equals the columns' min/max; rows
+    outside it (margin 0.25; one column beyond a bound, NaN) return exactly the
+    residual input columns, rows inside the unguarded output bit for bit,
+    batched and one-sample, and the counters count them; margin < 0 turns
+    the guard off."""
+    from paper_2511_15908_amd import mlp, surrogate
+    rc, margin = 13, 0.25
+    X, Y = _data(8, 700)
+    Y = (Y + X[:, rc:rc + N_OUT]).astype(np.float32)
+    net = mlp.Mlp(N_IN, N_OUT, hidden=H, layers=LAYERS, max_batch=1024, residual_col=rc)
+    net.set_params(surrogate.init_params(18, H, LAYERS, N_IN, N_OUT))
+    with pytest.raises(mlp.MlpError):
+        net.set_guard(margin)                       # no range yet
+    dX, dY = torch.tensor(X, device="cuda"), torch.tensor(Y, device="cuda")
+    net.fit_normalizer(dX, dY)
+    lo, hi = net.get_input_range()
+    lo_o, hi_o = M.input_range(X)
+    assert np.array_equal(lo, lo_o) and np.array_equal(hi, hi_o)
+    # test rows: the first ones inside, then single columns pushed past the bounds
+    a, b = M.guard_bounds(lo, hi, margin)
+    Xt = X[:64].copy()
+    Xt[3, 0] = np.nextafter(b[0], np.float32(np.inf))
+    Xt[9, 100] = np.nextafter(a[100], np.float32(-np.inf))
+    Xt[20, 50] = b[50]                              # on the bound: inside
+    Xt[21, 60] = a[60]
+    Xt[30, rc + 2] = hi[rc + 2] + 5.0 * (hi[rc + 2] - lo[rc + 2])
+    Xt[40, 7] = np.nan
+    fall_o = M.guard_rows(Xt, lo, hi, margin)
+    assert fall_o.tolist().count(True) == 4 and not fall_o[20] and not fall_o[21]
+    dXt = torch.tensor(Xt, device="cuda")
+    plain = net.forward(dXt).cpu().numpy()
+    net.set_guard(margin)
+    got = net.forward(dXt).cpu().numpy()
+    exp, _ = M.guarded(plain.astype(np.float64), Xt, lo, hi, margin, N_OUT, rc)
+    assert np.array_equal(got[fall_o], Xt[fall_o, rc:rc + N_OUT])
+    ok = ~fall_o
+    ok[40] = False                                  # NaN row: the plain output is NaN there
+    assert np.array_equal(got[ok], plain[ok]) and np.array_equal(got[~fall_o & ok], exp[~fall_o & ok].astype(np.float32))
+    assert net.guard_count() == (64, 4)
+    # the one-sample haptic chain
+    for r in (0, 3, 9, 20, 30, 40):
+        y = net.predict_one(Xt[r])
+        if fall_o[r]:
+            assert np.array_equal(y, Xt[r, rc:rc + N_OUT]), r
+        else:
+            net.set_guard(-1.0)
+            y_plain = net.predict_one(Xt[r])
+            net.set_guard(margin)
+            assert np.array_equal(y, y_plain), r
+    assert net.guard_count() == (64 + 6, 4 + 4)
+    net.set_guard(-1.0)
+    assert np.array_equal(net.forward(dXt).cpu().numpy()[ok], plain[ok])
+    assert net.guard_count() == (70, 8)

@@ -4,8 +4,9 @@ sphere, 4 SPH steps per tick, 40 ms haptic rolling mean), training by the
 library's own forward/backward/Adam kernels, and the gain over the haptic
 loop without the network (zero-order hold of the 100 Hz SPH wrench, and the
 hold followed by a rolling mean) on fifteen walks it never saw, judged
-against plain SPH at every tick.  The logs come from sixteen copies of the
-scene stepped together, one walk each."""
+against plain SPH at every tick, with the haptic loop's plain-SPH fallback
+outside the training range.  The logs come from sixteen copies of the scene
+stepped together, one walk each."""
 import numpy as np
 import pytest
 
@@ -60,4 +61,10 @@ def test_surrogate_beats_hold_between_sph_updates():
     base = min(e["zero_order_hold"]["mean"], e["hold_rolling_mean"]["mean"])
     assert e["surrogate"]["mean"] < base
     assert e["surrogate"]["p95"] < 0.85 * e["zero_order_hold"]["p95"]
+    # the plain-SPH fallback takes the walks that leave the training range
+    # and costs little elsewhere: the loop beats the network alone, and the
+    # network still serves most ticks
+    print("network only", round(e["network_only"]["mean"], 4), "fallback rows", e["surrogate"]["fallback_frac"])
+    assert e["surrogate"]["mean"] < e["network_only"]["mean"]
+    assert e["surrogate"]["fallback_frac"] < 0.25
     assert r["host_round_trip_hz"] > 1000.0

@@ -117,6 +117,48 @@ def test_residual_output_closed_form():
     assert np.allclose(g[-16:-16 + n_out], 2 * b / n_out, rtol=1e-13)
 
 
+def test_guard_closed_forms():
+    """The plain-SPH fallback decision at hand-picked values: lo = 0, hi = 2,
+    margin 0.5 give the exact bounds [-1, 3]; the bounds themselves are
+    inside, the next float beyond them and NaN are outside; margin 0 is the
+    training range itself; a column that was constant in training admits
+    only its value."""
+    lo = np.array([0.0, -4.0, 7.0], np.float32)
+    hi = np.array([2.0, 4.0, 7.0], np.float32)
+    a, b = M.guard_bounds(lo, hi, 0.5)
+    assert a.tolist() == [-1.0, -8.0, 7.0] and b.tolist() == [3.0, 8.0, 7.0]
+    a0, b0 = M.guard_bounds(lo, hi, 0.0)
+    assert a0.tolist() == lo.tolist() and b0.tolist() == hi.tolist()
+    up = np.nextafter(np.float32(3.0), np.float32(4.0))
+    dn = np.nextafter(np.float32(7.0), np.float32(0.0))
+    X = np.array([[3.0, 0.0, 7.0],        # on the upper bound
+                  [-1.0, -8.0, 7.0],      # on the lower bounds
+                  [up, 0.0, 7.0],         # one ulp above
+                  [0.0, 0.0, dn],         # the constant column moved
+                  [np.nan, 0.0, 7.0],     # not a number
+                  [1.0, 1.0, 7.0]], np.float32)
+    assert M.guard_rows(X, lo, hi, 0.5).tolist() == [False, False, True, True, True, False]
+    assert M.guard_rows(X[[5]], lo, hi, 0.0).tolist() == [False]
+    assert M.guard_rows(X[[0]], lo, hi, 0.0).tolist() == [True]
+
+
+def test_guarded_output_is_the_residual_base():
+    """Rows that fall back carry exactly the residual input columns, the
+    others the network's output unchanged; the range is the columns' min/max."""
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((40, 10)).astype(np.float32)
+    lo, hi = M.input_range(X)
+    assert np.array_equal(lo, X.min(0)) and np.array_equal(hi, X.max(0))
+    Xt = X[:6].copy()
+    Xt[1, 4] = hi[4] + 10.0
+    Xt[3, 0] = np.nan
+    out = rng.standard_normal((6, 3))
+    g, fall = M.guarded(out, Xt, lo, hi, 0.0, 3, res_col=2)
+    assert fall.tolist() == [False, True, False, True, False, False]
+    assert np.array_equal(g[[1, 3]], Xt[[1, 3], 2:5].astype(np.float64))
+    assert np.array_equal(g[[0, 2, 4, 5]], out[[0, 2, 4, 5]])
+
+
 def test_adam_closed_forms():
     """Step 1 from zero moments moves every weight by lr g/(|g| + eps); a
     constant gradient keeps the bias-corrected moments at g and g^2 exactly,
