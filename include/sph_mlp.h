@@ -93,9 +93,10 @@ mlp_status mlp_set_normalizer(mlp_ctx *ctx, const float *mu_x, const float *sd_x
 mlp_status mlp_get_normalizer(mlp_ctx *ctx, float *mu_x, float *sd_x, float *mu_y, float *sd_y);
 
 /*
- * Plain SPH as the fallback (Sec. 3.3: the learned force stands in for the
- * simulator between its updates; where the network would extrapolate, the
- * haptic loop keeps the simulator's own last wrench).  mlp_fit_normalizer also
+ * Plain SPH as the fallback: the device loop of Sec. 3.3 holds the
+ * simulator's last wrench between its updates; the network refines that hold
+ * only on inputs like those it was trained on, and elsewhere the loop keeps
+ * the simulator's own wrench.  mlp_fit_normalizer also
  * records the minimum lo_j and maximum hi_j of every input column of X;
  * mlp_set_input_range sets them from host arrays (n_in floats each, finite,
  * lo <= hi) and mlp_get_input_range reads them back.  mlp_set_guard(margin)
