@@ -267,6 +267,30 @@ def evaluate(net, logs, scene):
     return out
 
 
+def force_spectrum(log, bands=((0, 2), (2, 10), (10, 25), (25, 50), (50, 100), (100, 500))):
+    """Share of the haptic force's variance (sum over the three components,
+    mean removed, 1 kHz samples) in each frequency band (a, b] in Hz."""
+    F = log["wrench"][:, :3]
+    P = (np.abs(np.fft.rfft(F - F.mean(0), axis=0)) ** 2).sum(1)
+    f = np.fft.rfftfreq(F.shape[0], 1e-3)
+    tot = P[1:].sum()
+    return {f"{a}-{b} Hz": float(P[(f > a) & (f <= b)].sum() / tot) for a, b in bands}
+
+
+def spectrum_run(n_fluid, ticks=3000, warmup_ticks=300):
+    """Band shares of the haptic force over one walk (seed 101) after a
+    warm-up walk (seed 11), one context."""
+    sc = scenes.haptic_scene(n_fluid=n_fluid)
+    sim = make_sim(sc, max_ticks=max(ticks, warmup_ticks))
+    lo, hi = sc.info["walk_lo"], sc.info["walk_hi"]
+    c = sc.info["c0"]
+    for n, sd in ((warmup_ticks, 11), (ticks, 101)):
+        walk = scenes.smooth_walk(sd, n, c, lo, hi)
+        lg = collect(sim, sc, walk)
+        c = walk[0][-1] + 1e-3 * walk[2][-1]
+    return force_spectrum(lg)
+
+
 def haptic_rate(net, X, n=500):
     """Haptic ticks per second of the one-workgroup chain: host round trip
     (features in, wrench out, synchronised) and device-only back to back."""
@@ -357,7 +381,12 @@ if __name__ == "__main__":
     ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--eval-segments", type=int, default=3)
     ap.add_argument("--batch", type=int, default=1, help="scene copies stepped together, one walk each")
+    ap.add_argument("--spectrum", action="store_true",
+                    help="only the band shares of the haptic force over one walk (no training)")
     a = ap.parse_args()
+    if a.spectrum:
+        print(json.dumps({"n_fluid": a.n_fluid, "band_share": spectrum_run(a.n_fluid)}), flush=True)
+        raise SystemExit(0)
     r = run_experiment(a.n_fluid, a.segments, a.ticks, a.eval_ticks, a.steps, eval_segments=a.eval_segments,
                        batch=a.batch, log=lambda m: print(m, flush=True))
     print(json.dumps(r), flush=True)
