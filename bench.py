@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 256-scene batch leg and print its record (for profiling it alone)")
     return ap.parse_args()
 
 
@@ -131,17 +133,26 @@ def batch_leg(dev, n_scenes=256, steps=64):
         sim.set_body_track(int(sim.obj0[i]) + 1, tr)
     sim.step(2)
     sim.synchronize()
+    s0 = sim.stats()
     t0 = time.perf_counter()
     sim.step(steps)
     sim.synchronize()
     el = time.perf_counter() - t0
+    s1 = sim.stats()
     log = sim.read_log()
     nf = sum(sc.counts()["fluid"] for sc in scs)
+    d = {k: (s1[k] - s0[k]) / steps for k in s0}
+    n_all = sum(sc.n for sc in scs)
     return {"workload": f"{n_scenes} independent stirring tanks, 2k-30k fluid each (log-uniform), "
-                        f"{sum(sc.n for sc in scs):,} particles, dt = 5e-4 s",
+                        f"{n_all:,} particles, dt = 5e-4 s",
             "steps": steps, "ms_per_step": 1e3 * el / steps, "fluid_updates_per_s": nf * steps / el,
-            "particle_updates_per_s": sum(sc.n for sc in scs) * steps / el,
-            "log_records": int(log.shape[0] * log.shape[1])}
+            "particle_updates_per_s": n_all * steps / el,
+            "log_records": int(log.shape[0] * log.shape[1]),
+            "per_particle": {"density_pairs": d["pairs_density"] / n_all, "force_pairs": d["pairs_force"] / n_all,
+                             "candidate_tests": d["candidates"] / n_all},
+            "lane_efficiency_density": d["pairs_density"] / max(64 * d["iter_density"], 1),
+            "lane_efficiency_force": d["pairs_force"] / max(64 * d["iter_force"], 1),
+            "particles_per_wavefront": n_all / max(d["waves"], 1)}
 
 
 def main():
@@ -165,6 +176,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}))
+        return
+    if a.batch_only:
+        print(json.dumps({"batch": batch_leg(dev)}), flush=True)
         return
     t0 = time.perf_counter()
     sc = scenes.coupled_1m(n_fluid=a.n_fluid)
