@@ -7,8 +7,9 @@
 // Work decomposition (gfx950, wave64): one workgroup = one wavefront per
 // occupied grid cell (cell size 2h, so all neighbours of a particle lie in the
 // 27 cells around its own).  Each lane owns one target particle of the home
-// cell (two lanes per target when a pass has at most 32 targets).  The
-// candidates (particles of the 27 cells) are visited in S super-chunks of at
+// cell (two lanes per target when a pass has at most 32 targets; each of the
+// two then tests and walks alternate candidates).  The candidates (particles
+// of the 27 cells) are visited in S super-chunks of at
 // most kScWords*64: super-chunk s holds every S-th particle of every cell
 // (in-cell index = s mod S), which spreads each lane's neighbours evenly over
 // the super-chunks.  Candidates farther than the support from the home cell's
@@ -25,11 +26,13 @@
 
 namespace sphk {
 
-#ifdef SPH_DENSITY_MIN_WAVES
-#define SPH_DENSITY_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SPH_DENSITY_MIN_WAVES)))
-#else
-#define SPH_DENSITY_OCCUPANCY
+// The density pass runs at 5 wavefronts per SIMD (at most 96 VGPRs, a few
+// spilled outside the neighbour loop): without the bound the split-pass test
+// path takes it to 99 registers and 4 wavefronts, measured 5 % slower.
+#ifndef SPH_DENSITY_MIN_WAVES
+#define SPH_DENSITY_MIN_WAVES 5
 #endif
+#define SPH_DENSITY_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SPH_DENSITY_MIN_WAVES)))
 // The force pass runs at 6 wavefronts per SIMD (at most 80 VGPRs, a few
 // spilled outside the neighbour loop): measured 3 % faster than 5.
 #ifndef SPH_FORCES_MIN_WAVES
@@ -313,6 +316,32 @@ __device__ __forceinline__ uint64_t hit_word(const V4<T> &me, const V4<T> *cand,
     return ((uint64_t)hi << 32) | lo;
 }
 
+#ifndef SPH_SPLIT_UNROLL
+#define SPH_SPLIT_UNROLL 4
+#endif
+// Split passes (two lanes per target, below): the lane of half h = lane / 32
+// tests only the word's candidates h, h + 2, h + 4, ... (n of them), which
+// are the ones it walks; bit i of the result is candidate h + 2 i.
+template <typename T>
+__device__ __forceinline__ uint32_t hit_bits_stride2(const V4<T> &me, const V4<T> *cand, uint32_t n, T R2)
+{
+    uint32_t bits = 0;
+#pragma unroll SPH_SPLIT_UNROLL
+    for (uint32_t i = n; i-- > 0u;) bits = __builtin_amdgcn_alignbit(bits, gap_sign<T>(me, cand[2u * i], R2), 31u);
+    return bits;
+}
+
+// Bit i of the low 16 bits of x moved to bit 2 i.
+__device__ __forceinline__ uint32_t spread16(uint32_t x)
+{
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
 // This lane's hit words are held in registers, mw[0] first, and walked
 // lowest bit first: the loop over a lane's hits is
 //     for (;;) { skip_empty_word(mw, base); if (mw[0] == 0) break;
@@ -517,7 +546,19 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                     uint64_t m = 0;
                     if ((uint32_t)q < nwc) {
                         const uint32_t nv = size > (uint32_t)q * kWave ? min(size - (uint32_t)q * kWave, (uint32_t)kWave) : 0u;
-                        m = hit_word<T>(me, cand + q * kWave, nv, R2);
+                        if (sp.split) {
+                            // each half tests the alternate candidates it walks; the
+                            // full word (stored for the force pass) joins both halves
+                            const uint32_t h = lane >> 5, n2 = (nv + 1u) >> 1;
+                            uint32_t bits = hit_bits_stride2<T>(me, cand + q * kWave + h, n2, R2);
+                            if (h && (nv & 1u)) bits &= ~(1u << (n2 - 1u));    // slot nv is past the word
+                            // candidate h + 2 i at bit h + 2 i (even bits never reach bit 31)
+                            const uint32_t lo = spread16(bits) << h, hi = spread16(bits >> 16) << h;
+                            m = ((uint64_t)(hi | (uint32_t)__shfl_xor((int)hi, 32, 64)) << 32) |
+                                (lo | (uint32_t)__shfl_xor((int)lo, 32, 64));
+                        } else {
+                            m = hit_word<T>(me, cand + q * kWave, nv, R2);
+                        }
                         if (act && sp.lead) masks[(size_t)(w0 + q) * n + p] = m;
                         npair += (want && sp.lead) ? (uint32_t)__popcll(m) : 0u;
                     }
