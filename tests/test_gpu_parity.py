@@ -122,6 +122,49 @@ def test_small_scene_one_step(gpu, orc, prec, seed):
     _check_step(sc, o, g, r, prec, TOL[prec])
 
 
+def _split_pass_share(sc, keys):
+    """Share of the density pass's wavefront passes that have at most 32
+    movable targets (fluid, soft, kinematic) and are served two lanes per
+    target, from the cell keys of the step (the kernel's pass rule: 64
+    targets per pass, a remainder of at most 8 served inside the last full
+    pass)."""
+    kin = np.asarray(sc.object_kinematic)
+    static = (sc.type == 2) & (sc.object >= 0) & (kin[np.maximum(sc.object, 0)] == 0)
+    order = np.argsort(keys, kind="stable")
+    k, st = keys[order], static[order]
+    edges = np.flatnonzero(np.r_[True, k[1:] != k[:-1], True])
+    total = split = 0
+    for a, b in zip(edges[:-1], edges[1:]):
+        n = b - a
+        left = n > 64 and 0 < n % 64 <= 8
+        npass = n // 64 if left else -(-n // 64)
+        for c in range(npass):
+            mov = int((~st[a + 64 * c:min(a + 64 * c + 64, b)]).sum())
+            if mov == 0:
+                continue
+            total += 1
+            split += (not (left and c + 1 == npass)) and mov <= 32
+    return split / max(total, 1)
+
+
+def test_coarse_tank_split_passes(gpu, orc):
+    """A coarse stirring tank (2-4k fluid, cells of 10-60 particles, a third
+    of them static wall particles) where most density passes run two lanes
+    per target, each lane testing only its alternate candidates: keys and
+    neighbour sets bit-exact, density, forces and the paddle's wrench within
+    the FP32 tolerances, over two steps of the moving paddle."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.stirring_batch(seed=4, n_scenes=4, n_min=2000, n_max=4000)[0]
+    poses = {1: scenes.batch_pose(sc, 0.0)}
+    x0 = orc.round_to(sc.x, "f32")
+    share = _split_pass_share(sc, orc.cell_keys(sc.params, "f32", x0))
+    print(f"{sc.name}: {sc.n} particles, split passes {share:.2f}")
+    assert share > 0.3
+    sim, o, init, outs = _run_both(gpu, orc, sc, "f32", poses, steps=2)
+    for g, r in outs:
+        _check_step(sc, o, g, r, "f32", TOL["f32"])
+
+
 def test_small_scene_three_steps_fp64(gpu, orc):
     """FP64: the GPU trajectory tracks the oracle's step after step."""
     from paper_2511_15908_amd import scenes
