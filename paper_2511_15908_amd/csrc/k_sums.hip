@@ -7,8 +7,9 @@
 // Work decomposition (gfx950, wave64): one workgroup = one wavefront per
 // occupied grid cell (cell size 2h, so all neighbours of a particle lie in the
 // 27 cells around its own).  Each lane owns one target particle of the home
-// cell (two lanes per target when a pass has at most 32 targets; each of the
-// two then tests and walks alternate candidates).  The candidates (particles
+// cell (two lanes per target when a pass has at most 32 targets, four when it
+// has at most 16; each lane then tests and walks every second or fourth
+// candidate).  The candidates (particles
 // of the 27 cells) are visited in S super-chunks of at
 // most kScWords*64: super-chunk s holds every S-th particle of every cell
 // (in-cell index = s mod S), which spreads each lane's neighbours evenly over
@@ -319,15 +320,15 @@ __device__ __forceinline__ uint64_t hit_word(const V4<T> &me, const V4<T> *cand,
 #ifndef SPH_SPLIT_UNROLL
 #define SPH_SPLIT_UNROLL 4
 #endif
-// Split passes (two lanes per target, below): the lane of half h = lane / 32
-// tests only the word's candidates h, h + 2, h + 4, ... (n of them), which
-// are the ones it walks; bit i of the result is candidate h + 2 i.
+// Split passes (L lanes per target, below): the lane of group g tests only
+// the word's candidates g, g + L, g + 2 L, ... (n of them), which are the
+// ones it walks; bit i of the result is candidate g + L i.
 template <typename T>
-__device__ __forceinline__ uint32_t hit_bits_stride2(const V4<T> &me, const V4<T> *cand, uint32_t n, T R2)
+__device__ __forceinline__ uint32_t hit_bits_stride(const V4<T> &me, const V4<T> *cand, uint32_t n, uint32_t L, T R2)
 {
     uint32_t bits = 0;
 #pragma unroll SPH_SPLIT_UNROLL
-    for (uint32_t i = n; i-- > 0u;) bits = __builtin_amdgcn_alignbit(bits, gap_sign<T>(me, cand[2u * i], R2), 31u);
+    for (uint32_t i = n; i-- > 0u;) bits = __builtin_amdgcn_alignbit(bits, gap_sign<T>(me, cand[L * i], R2), 31u);
     return bits;
 }
 
@@ -339,6 +340,16 @@ __device__ __forceinline__ uint32_t spread16(uint32_t x)
     x = (x | (x << 4)) & 0x0F0F0F0Fu;
     x = (x | (x << 2)) & 0x33333333u;
     x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+// Bit i of the low 8 bits of x moved to bit 4 i.
+__device__ __forceinline__ uint32_t spread8x4(uint32_t x)
+{
+    x &= 0xFFu;
+    x = (x | (x << 12)) & 0x000F000Fu;
+    x = (x | (x << 6)) & 0x03030303u;
+    x = (x | (x << 3)) & 0x11111111u;
     return x;
 }
 
@@ -374,16 +385,28 @@ struct Cand64 {
 };
 
 // A pass whose cell part holds at most 32 targets (fluid, soft or kinematic
-// particles) is served with two lanes per target: lanes r and r + 32 take the
-// r-th target, each walking alternate bits of its hit words (even slots for
-// the lower half, odd for the upper), and the two partial sums are added at
-// the end of the pass; only the lower lane stores.  Halves the neighbour
-// loop of cells at walls and at the free surface.
+// particles) is served with L = 2 lanes per target, at most 16 with L = 4:
+// lanes r, r + 64/L, ... take the r-th target, lane group g = lane / (64/L)
+// walking the hit bits of the slots = g mod L, and the L partial sums are
+// added at the end of the pass; only group 0 stores.  Divides the neighbour
+// loop of cells at walls, at the free surface and in sparse scenes.
 struct SplitPass {
-    bool split;      // uniform
-    bool lead;       // this lane stores (lower half, or every lane when not split)
+    bool split;      // uniform: L > 1
+    uint32_t ways;   // uniform: L
+    uint32_t grp;    // this lane's group g
+    bool lead;       // this lane stores (group 0, or every lane when not split)
     uint64_t bits;   // hit bits this lane walks
 };
+
+// Sum of v over the L lanes of this lane's target (fixed order:
+// (g0 + g1) + (g2 + g3) for L = 4).
+template <typename V>
+__device__ __forceinline__ V split_sum(V v, const SplitPass &sp)
+{
+    if (sp.ways == 4u) v += __shfl_xor(v, 16, 64);
+    if (sp.ways >= 2u) v += __shfl_xor(v, 32, 64);
+    return v;
+}
 
 __device__ __forceinline__ SplitPass split_pass(bool target, bool with_left, uint32_t lane, uint32_t t0, uint32_t e0,
                                                uint32_t s0, const uint32_t *__restrict__ auxv, uint8_t *tmap,
@@ -391,19 +414,22 @@ __device__ __forceinline__ SplitPass split_pass(bool target, bool with_left, uin
 {
     const uint64_t tb = __ballot(target);
     const uint32_t nt = (uint32_t)__popcll(tb);
-    SplitPass sp{false, true, ~0ull};
+    SplitPass sp{false, 1u, 0u, true, ~0ull};
     if (with_left || nt == 0u || nt > 32u) return sp;
     __syncthreads();                      // the previous pass's readers of tmap are done
     if (target) tmap[lanes_below(tb, lane)] = (uint8_t)lane;
     __syncthreads();
-    const uint32_t r = lane & 31u;
+    const uint32_t L = nt <= 16u ? 4u : 2u, shift = L == 4u ? 4u : 5u;
+    const uint32_t r = lane & ((kWave / L) - 1u);
     act = r < nt;
     p = act ? t0 + tmap[r] : e0;
     pc = act ? p : s0;
     aux = act ? auxv[pc] : 0u;
     sp.split = true;
-    sp.lead = lane < 32u;
-    sp.bits = sp.lead ? 0x5555555555555555ull : 0xAAAAAAAAAAAAAAAAull;
+    sp.ways = L;
+    sp.grp = lane >> shift;
+    sp.lead = sp.grp == 0u;
+    sp.bits = (L == 4u ? 0x1111111111111111ull : 0x5555555555555555ull) << sp.grp;
     return sp;
 }
 
@@ -473,9 +499,9 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         bool act = p < e0;
         uint32_t pc = act ? p : s0;
         uint32_t aux = act ? st.aux[pc] : 0u;
-        // a pass with at most 32 targets is split: two lanes per target (no
-        // lane then serves the cell's static boundary particles, whose density
-        // and force the reorder has already set to 0)
+        // a pass with at most 32 targets is split: two or four lanes per
+        // target (no lane then serves the cell's static boundary particles,
+        // whose density and force the reorder has already set to 0)
         const SplitPass sp = split_pass(act && (aux_type(aux) != TY_BOUNDARY || aux_kin(aux)), with_left, lane,
                                         t0, e0, s0, st.aux, tmap, p, act, pc, aux);
         V4<T> me = st.pos[pc];
@@ -547,15 +573,26 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                     if ((uint32_t)q < nwc) {
                         const uint32_t nv = size > (uint32_t)q * kWave ? min(size - (uint32_t)q * kWave, (uint32_t)kWave) : 0u;
                         if (sp.split) {
-                            // each half tests the alternate candidates it walks; the
-                            // full word (stored for the force pass) joins both halves
-                            const uint32_t h = lane >> 5, n2 = (nv + 1u) >> 1;
-                            uint32_t bits = hit_bits_stride2<T>(me, cand + q * kWave + h, n2, R2);
-                            if (h && (nv & 1u)) bits &= ~(1u << (n2 - 1u));    // slot nv is past the word
-                            // candidate h + 2 i at bit h + 2 i (even bits never reach bit 31)
-                            const uint32_t lo = spread16(bits) << h, hi = spread16(bits >> 16) << h;
-                            m = ((uint64_t)(hi | (uint32_t)__shfl_xor((int)hi, 32, 64)) << 32) |
-                                (lo | (uint32_t)__shfl_xor((int)lo, 32, 64));
+                            // each group tests the candidates it walks; the full word
+                            // (stored for the force pass) joins the groups.  Slots past
+                            // the word's nv hold +inf (no hit) up to slot 63.
+                            const uint32_t L = sp.ways, g = sp.grp, nl = (nv + L - 1u) / L;
+                            const uint32_t bits = hit_bits_stride<T>(me, cand + q * kWave + g, nl, L, R2);
+                            // candidate g + L i at bit g + L i (the spread bits stay below
+                            // bit 32 - L + 1, so the shift by g keeps each word apart)
+                            uint32_t lo, hi;
+                            if (L == 4u) {
+                                lo = spread8x4(bits) << g;
+                                hi = spread8x4(bits >> 8) << g;
+                                lo |= (uint32_t)__shfl_xor((int)lo, 16, 64);
+                                hi |= (uint32_t)__shfl_xor((int)hi, 16, 64);
+                            } else {
+                                lo = spread16(bits) << g;
+                                hi = spread16(bits >> 16) << g;
+                            }
+                            lo |= (uint32_t)__shfl_xor((int)lo, 32, 64);
+                            hi |= (uint32_t)__shfl_xor((int)hi, 32, 64);
+                            m = ((uint64_t)hi << 32) | lo;
                         } else {
                             m = hit_word<T>(me, cand + q * kWave, nv, R2);
                         }
@@ -639,7 +676,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                 cstat[4] += witer;
             }
         }
-        if (sp.split) acc += __shfl_xor(acc, 32, 64);
+        if (sp.split) acc = split_sum(acc, sp);
         if (act && sp.lead) {
             V2<T> d{(T)0, (T)0};
             if (fs) {
@@ -957,9 +994,9 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
         }
         if (lane == 0) cstat += witer;
         if (sp.split) {
-            fx += __shfl_xor(fx, 32, 64);
-            fy += __shfl_xor(fy, 32, 64);
-            fz += __shfl_xor(fz, 32, 64);
+            fx = split_sum(fx, sp);
+            fy = split_sum(fy, sp);
+            fz = split_sum(fz, sp);
         }
         if (tgt && sp.lead) store_force<T>(p, aux, ma, fx, fy, fz, ph, fspring, force, fbody);
         if (with_left && lane < nleft) {
