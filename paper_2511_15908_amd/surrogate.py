@@ -79,6 +79,19 @@ def make_net(max_batch=4096, device="cuda", seed=1, hidden=256, layers=3):
     return net
 
 
+def tick_means(tail, steps, per_tick, K):
+    """The haptic wrench at the end of every tick: the mean of the last
+    min(K, available) per-step wrenches, where `tail` holds the (at most
+    K - 1) per-step wrenches before `steps` ([per_tick * ticks][6]).  Returns
+    the [ticks][6] means and the tail for the next call."""
+    allw = np.concatenate([tail, steps])
+    cs = np.concatenate([np.zeros((1, steps.shape[1])), np.cumsum(allw, 0)])
+    end = tail.shape[0] + per_tick * np.arange(1, steps.shape[0] // per_tick + 1)   # samples up to each tick's end
+    start = np.maximum(end - K, 0)
+    means = (cs[end] - cs[start]) / (end - start)[:, None]
+    return means, (allw[-(K - 1):] if K > 1 else allw[:0])
+
+
 def collect(sim, scene, walks):
     """Drive the grabbed sphere of each scene copy with its walk (c, q, v, w
     per tick; `walks` holds one walk per copy, or is one walk for a context
@@ -114,13 +127,7 @@ def collect(sim, scene, walks):
     logs = []
     for i, (b, (C, Q, V, W)) in enumerate(zip(sim.bodies, walks)):
         kb = sim.kinematic.index(b)
-        tail = sim.wrench_tail[i]
-        allw = np.concatenate([tail, rec[:, kb, 13:19]])
-        cs = np.concatenate([np.zeros((1, 6)), np.cumsum(allw, 0)])
-        end = tail.shape[0] + per_tick * np.arange(1, n + 1)     # samples up to each tick's end
-        start = np.maximum(end - K, 0)
-        wr = (cs[end] - cs[start]) / (end - start)[:, None]
-        sim.wrench_tail[i] = allw[-(K - 1):] if K > 1 else allw[:0]
+        wr, sim.wrench_tail[i] = tick_means(sim.wrench_tail[i], rec[:, kb, 13:19], per_tick, K)
         pr = probes[end_rows, i * N_PROBES:(i + 1) * N_PROBES]
         q = np.where(Q[:, :1] < 0, -Q, Q)
         logs.append({"c": C.copy(), "q": q, "v": V.copy(), "w": W.copy(), "wrench": wr, "probes": pr})
