@@ -100,9 +100,10 @@ def cpu_baseline(scene, min_seconds=10.0):
                       f"({nmov:,} fluid+soft), {dt:.1f} s wall"}
 
 
-def profiled_traffic(kernel):
+def profiled_traffic(kernel, n_particles):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 summary,
-    only while the profiled kernel source is unchanged."""
+    only for the workload it was taken on (the 1M coupled scene, by its
+    particle count) and while the profiled kernel source is unchanged."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_sums_coupled_1m_traffic.json")
     src = os.path.join(ROOT, "paper_2511_15908_amd", "csrc", "k_sums.hip")
@@ -112,6 +113,8 @@ def profiled_traffic(kernel):
     except OSError:
         return None
     if rec.get("source_sha256_k_sums") != sha or kernel not in rec.get("kernels", {}):
+        return None
+    if rec.get("n_particles") != n_particles:
         return None
     return rec["kernels"][kernel]["bytes"]
 
@@ -226,7 +229,7 @@ def main():
     achieved = lane_ops[dom] / (ms[dom] * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": f"k_{dom}", "achieved": round(achieved, 3),
             "peak": round(PEAK_LANE_TOPS, 2), "unit": "Tlane-op/s", "frac": round(achieved / PEAK_LANE_TOPS, 4),
-            "traffic": profiled_traffic(f"k_{dom}"), "avg_launch_ms": round(ms[dom], 4),
+            "traffic": profiled_traffic(f"k_{dom}", int(info["n"])), "avg_launch_ms": round(ms[dom], 4),
             "algorithmic_lane_ops_per_launch": int(lane_ops[dom]),
             "other_kernel": {k: {"avg_launch_ms": round(ms[k], 4),
                                  "frac": round(lane_ops[k] / (ms[k] * 1e-3) / 1e12 / PEAK_LANE_TOPS, 4)}
