@@ -266,6 +266,251 @@ def test_fluid_body_newton_third_law(orc):
     assert np.abs(F_body + f[~body].sum(0)).max() < 1e-12 * np.abs(f).sum()
 
 
+# ---------------------------------------------------------------- fluid-boundary coupling (Sec. 3.2)
+#
+# Sec. 3.2 gives every particle a type; rigid particles are packed densely to
+# keep fluid out, interact with the fluid through the SPH pressure force, and
+# pass their point forces to the parent body.  The reading pinned here:
+# boundary volumes psi_b = rho0 / sum_{same object} W (from the boundary
+# particles' own neighbourhood), psi_b in place of a mass in the density sum,
+# the pressure mirrored into the boundary particle (p_b = p_i, rho_b = rho_i,
+# so the pressure factor is 2 p_i / rho_i^2), and the viscosity of Alg. 1
+# applied to the fluid-boundary pair with 1/rho_i.  Each test below fails for
+# a plausible slip in one of these terms: a sign, psi_b or the mass in the
+# wrong place, p_b or rho_b taken from the boundary particle's own (unused)
+# entries, a single pressure term, or 1/rho_j in the viscosity.
+
+_WALL_M = 7          # wall half-width in sites: support 4 s fits inside
+
+
+def _wall_params(S, flags=0, nu=0.0, g=(0.0, 0.0, 0.0)):
+    ext = (_WALL_M + 6) * S
+    return {"h": 2 * S, "rho0": 1000.0, "k_pressure": 250.0, "nu": nu, "gravity": g, "dt": 1e-3,
+            "domain_lo": (-ext, -ext, -ext), "domain_hi": (ext, ext, ext + 12 * S), "flags": flags}
+
+
+def _wall_sites(S):
+    r = np.arange(-_WALL_M, _WALL_M + 1) * S
+    X, Y = np.meshgrid(r, r, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], 1)
+
+
+def _plane_integral(orc, h, z, fn):
+    """int over the plane at distance z of fn(r), r = sqrt(rho^2 + z^2), by
+    adaptive quadrature in the in-plane radius (split at the kernel's knot)."""
+    from scipy import integrate
+    R = 2.0 * h
+    rmax = math.sqrt(R * R - z * z)
+    knots = [math.sqrt(h * h - z * z)] if z < h else None
+    val, _ = integrate.quad(lambda q: 2.0 * math.pi * q * fn(math.sqrt(q * q + z * z)), 0.0, rmax,
+                            points=knots, limit=200, epsabs=0.0, epsrel=1e-12)
+    return val
+
+
+def test_near_wall_density_single_layer(orc):
+    """Fluid half-space lattice (sites at heights s, 2s, ...) over a flat
+    single-layer wall whose psi_b comes from the wall itself.  The density at
+    heights s, 2s, 3s, 4s above the wall is the exact lattice sum
+    1.3718 / 1.1331 / 1.0117 / 1.0001 rho0 (computed independently of the
+    oracle; at 4s the wall is out of reach and the value is the interior
+    lattice density).  Boundary masses are set to a nonsense value, so using
+    the mass instead of psi_b, dropping the wall term or counting it twice
+    fails."""
+    S = 0.25
+    wall = _wall_sites(S)
+    nw = wall.shape[0]
+    layers = [wall + [0.0, 0.0, k * S] for k in range(1, 11)]
+    x = np.concatenate([wall] + layers)
+    n = x.shape[0]
+    typ = np.zeros(n, np.uint8)
+    typ[:nw] = 2
+    obj = np.full(n, -1, np.int32)
+    obj[:nw] = 0
+    P = _wall_params(S)
+    psi = orc.boundary_psi(P, "f64", x, typ, obj)
+    c = int(np.argmin(np.linalg.norm(wall, axis=1)))
+    assert psi[c] / (1000.0 * S ** 3) == pytest.approx(2.857263968350786, rel=1e-12)
+    mass = np.full(n, 1000.0 * S ** 3)
+    mass[:nw] = 123.0
+    targets = [nw + (k - 1) * nw + c for k in range(1, 5)]
+    rho, p = orc.density(P, "f64", x, mass, typ, psi, targets)
+    expect = [1.3718, 1.1331, 1.0117, 1.0001]
+    assert np.abs(rho / 1000.0 - expect).max() < 1e-4
+    assert np.array_equal(p, 250.0 * (rho - 1000.0))        # literal Eq. pressure (no clamp flag)
+
+
+@pytest.mark.parametrize("z_over_s", [0.5, 1.0, 1.5, 2.3])
+def test_flat_wall_mirrored_pressure_force(orc, z_over_s):
+    """Pressure force of a flat single-layer wall on one fluid particle at
+    height z with given p_i, rho_i.  The mirrored reading gives
+    F_z = 2 m_i p_i / rho_i^2 sum_b psi_b |dW/dr| z / r (repulsive for p > 0).
+    Averaged over the particle's in-plane position in the wall's unit cell the
+    wall sum is exactly (1/s^2) times the in-plane integral of the same
+    function up to the lattice's aliasing error, here < 1e-5; the integral is
+    taken by quadrature.  The boundary particles' own density and pressure
+    entries are set to nonsense values (p_b, rho_b must come from i), and
+    BOUNDARY_SINGLE_TERM must give exactly half."""
+    S = 0.25
+    h = 2 * S
+    z = z_over_s * S
+    wall = _wall_sites(S)
+    nw = wall.shape[0]
+    psi_b = 2.857 * 1000.0 * S ** 3
+    mi, rhoi, pi_ = 1000.0 * S ** 3, 1100.0, 300.0
+    F, F1 = [], []
+    nsub = 8
+    for a in range(nsub):
+        for b in range(nsub):
+            xi = np.array([[(a + 0.5) / nsub * S, (b + 0.5) / nsub * S, z]])
+            x = np.concatenate([wall, xi])
+            n = nw + 1
+            typ = np.zeros(n, np.uint8)
+            typ[:nw] = 2
+            psi = np.zeros(n)
+            psi[:nw] = psi_b
+            mass = np.full(n, 7.0)
+            mass[nw] = mi
+            rho = np.full(n, 555.0)
+            rho[nw] = rhoi
+            p = np.full(n, -999.0)
+            p[nw] = pi_
+            F.append(orc.forces(_wall_params(S), "f64", x, np.zeros_like(x), mass, typ, psi, rho, p, None,
+                                [nw])[0])
+            F1.append(orc.forces(_wall_params(S, flags=orc.BOUNDARY_SINGLE_TERM), "f64", x, np.zeros_like(x),
+                                 mass, typ, psi, rho, p, None, [nw])[0])
+    F, F1 = np.array(F), np.array(F1)
+    integral = _plane_integral(orc, h, z, lambda r: -orc.dWdr(r, h) * z / r)
+    expect = 2.0 * mi * pi_ / rhoi ** 2 * psi_b / S ** 2 * integral
+    assert expect > 0.0
+    assert F[:, 2].mean() == pytest.approx(expect, rel=1e-5)
+    assert np.all(F[:, 2] > 0.0)                                  # repulsive at every position
+    assert abs(F[:, 0].mean()) < 1e-12 * expect and abs(F[:, 1].mean()) < 1e-12 * expect
+    assert np.allclose(F1, 0.5 * F, rtol=1e-15, atol=0.0)
+
+
+@pytest.mark.parametrize("z_over_s", [0.5, 1.0, 1.5])
+def test_flat_wall_boundary_viscosity(orc, z_over_s):
+    """A wall sliding at u along x under a fluid particle at rest (p = 0):
+    the viscous term of Alg. 1 applied to the fluid-boundary pair with 1/rho_i
+    drags the particle along +x with
+    F_x = 2 nu m_i (psi_b / rho_i) u (1/s^2) int |r dW/dr| / (r^2 + 0.01 h^2) dA
+    (cell-averaged, as above) and no other component; zero when the particle
+    moves with the wall, and zero under NO_BOUNDARY_VISCOSITY.  The boundary
+    particles' own density entry is a nonsense value (1/rho_j or
+    2/(rho_i + rho_j) would fail)."""
+    S = 0.25
+    h = 2 * S
+    z = z_over_s * S
+    wall = _wall_sites(S)
+    nw = wall.shape[0]
+    psi_b = 2.857 * 1000.0 * S ** 3
+    mi, rhoi, nu, u = 1000.0 * S ** 3, 1100.0, 0.7, 0.3
+    eps = 0.01 * h * h
+    P = _wall_params(S, nu=nu)
+    F = []
+    nsub = 8
+    for a in range(nsub):
+        for b in range(nsub):
+            xi = np.array([[(a + 0.5) / nsub * S, (b + 0.5) / nsub * S, z]])
+            x = np.concatenate([wall, xi])
+            n = nw + 1
+            typ = np.zeros(n, np.uint8)
+            typ[:nw] = 2
+            psi = np.zeros(n)
+            psi[:nw] = psi_b
+            mass = np.full(n, 7.0)
+            mass[nw] = mi
+            rho = np.full(n, 555.0)
+            rho[nw] = rhoi
+            v = np.zeros_like(x)
+            v[:nw, 0] = u
+            F.append(orc.forces(P, "f64", x, v, mass, typ, psi, rho, np.zeros(n), None, [nw])[0])
+            if a == 1 and b == 2:
+                v_with = v.copy()
+                v_with[nw, 0] = u
+                f0 = orc.forces(P, "f64", x, v_with, mass, typ, psi, rho, np.zeros(n), None, [nw])[0]
+                assert np.all(f0 == 0.0)
+                f_off = orc.forces(_wall_params(S, nu=nu, flags=orc.NO_BOUNDARY_VISCOSITY), "f64", x, v, mass,
+                                   typ, psi, rho, np.zeros(n), None, [nw])[0]
+                assert np.all(f_off == 0.0)
+    F = np.array(F)
+    integral = _plane_integral(orc, h, z, lambda r: -orc.dWdr(r, h) * r / (r * r + eps))
+    expect = 2.0 * nu * mi * psi_b / rhoi * u / S ** 2 * integral
+    assert F[:, 0].mean() == pytest.approx(expect, rel=1e-5)
+    assert np.all(F[:, 0] > 0.0)
+    assert np.all(F[:, 1:] == 0.0)
+
+
+def test_body_place_rigid_velocity(orc):
+    """Placement of a rigid body's particles (Sec. 3.2, constant body-frame
+    offsets): x_b = c + R(q) r_loc and v_b = v + w x (x_b - c), worked by hand
+    for a quarter turn about z."""
+    a = math.pi / 2
+    q = np.array([math.cos(a / 2), 0.0, 0.0, math.sin(a / 2)])       # R e_x = e_y, R e_y = -e_x
+    obj = np.array([3, 3, -1], np.int32)
+    r_loc = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 2.0], [0.0, 0.0, 0.0]])
+    c = np.array([5.0, 6.0, 7.0])
+    vc = np.array([0.1, -0.2, 0.3])
+    x = np.full((3, 3), -42.0)
+    v = np.full((3, 3), -42.0)
+    w = np.array([1.0, 0.0, 2.0])
+    lib = orc.lib()
+    import ctypes as C
+
+    def ptr(arr, ct=C.c_double):
+        return arr.ctypes.data_as(C.POINTER(ct))
+    lib.orc_body_place(3, ptr(obj, C.c_int32), 3, ptr(c), ptr(q), ptr(vc), ptr(w), ptr(r_loc), ptr(x), ptr(v))
+    # particle 0: R r = (0, 1, 0); w x (0,1,0) = (1,0,2) x (0,1,0) = (-2, 0, 1)
+    assert np.allclose(x[0], [5.0, 7.0, 7.0], atol=1e-15)
+    assert np.allclose(v[0], [0.1 - 2.0, -0.2, 0.3 + 1.0], atol=1e-15)
+    # particle 1: R r = (0, 0, 2); w x (0,0,2) = (0*2 - 2*0, 2*0 - 1*2, 0) = (0, -2, 0)
+    assert np.allclose(x[1], [5.0, 6.0, 9.0], atol=1e-15)
+    assert np.allclose(v[1], [0.1, -2.2, 0.3], atol=1e-15)
+    assert np.all(x[2] == -42.0) and np.all(v[2] == -42.0)        # other objects untouched
+
+
+def test_archimedes_submerged_fixed_cube(orc):
+    """Loose physics check of the coupling (Sec. 3.2): a fixed cube (surface
+    of a 5^3 lattice block, side 4 s) in the middle of a water column settles
+    to a steady upward force of the order of rho0 g V, where V lies between
+    the sampled block (side 5 s, each surface particle owning s/2 outward)
+    and the region the fluid was kept out of (side 8 s, 1.5 s clearance on
+    each side): a sign slip in the boundary pressure term, or a wall that
+    does not repel, fails.  The viscosity is raised to 0.04 m^2/s so the
+    column settles in 0.3 s; Archimedes' force does not depend on it."""
+    from paper_2511_15908_amd import scenes
+    s, dt, ncol, depth, nb = 0.02, 1e-3, 12, 16, 5
+    Wx = scenes.tank_width(ncol, s)
+    tank = scenes.open_tank(Wx, Wx, depth + 6, s)
+    off = np.array([Wx / 2 - (nb - 1) * s / 2, Wx / 2 - (nb - 1) * s / 2, 6 * s])
+    cube = scenes.block_surface_sites(0, nb - 1, 0, nb - 1, 0, nb - 1).astype(float) * s + off
+    c = off + (nb - 1) * s / 2
+    g = scenes.WALL_GAP
+    fl = scenes.fill_to_count(ncol * ncol * depth, (1, ncol), (1, ncol), s, set(),
+                              exclude_fn=scenes.clearance(cube, scenes.OBSTACLE_CLEARANCE * s), gap=g)
+    fl = (fl.astype(float) + (g - 1.0)) * s
+    params = scenes._params(2 * s, dt, (-0.5 * s,) * 3, (Wx + 0.5 * s, Wx + 0.5 * s, (depth + 10) * s), "f64",
+                            nu=0.04, flags=1)
+    sc = scenes._assemble("archimedes", "f64", params, s,
+                          [(fl, 0, -1, 1000.0 * s ** 3), (tank, 2, 0, 0.0), (cube, 2, 1, 0.0)],
+                          kin=[0, 1], poses=[[0, 0, 0, 1, 0, 0, 0], list(c) + [1, 0, 0, 0]])
+    o = orc.Oracle(sc, "f64")
+    W = []
+    for _ in range(400):
+        r = o.step()
+        F, T = r["wrench"][1]
+        W.append(np.concatenate([F, T]))
+    W = np.array(W[-100:])
+    Fz = W[:, 2].mean()
+    lo, hi = 1000.0 * 9.81 * (nb * s) ** 3, 1000.0 * 9.81 * ((nb + 3) * s) ** 3
+    assert lo < Fz < hi
+    assert W[:, 2].std() < 0.05 * Fz                              # settled
+    assert np.abs(W[:, :2].mean(0)).max() < 0.05 * Fz            # no sideways force
+    assert np.abs(W[:, 3:].mean(0)).max() < 0.05 * Fz * nb * s   # no torque about the centre
+    sp = np.linalg.norm(o.v[sc.type == 0], axis=1)
+    assert sp.max() < 0.1
+
+
 # ---------------------------------------------------------------- rigid body, wrench, integrator
 
 def test_quaternion_rotation(orc):
