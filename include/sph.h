@@ -47,7 +47,11 @@ typedef enum {
     SPH_ERR_STATE = 4,       /* call not valid in the context's state (after a device error) */
     SPH_ERR_UNSTABLE = 5,    /* a particle velocity or position became non-finite or exceeded v_max */
     SPH_ERR_UNSUPPORTED = 6, /* precision/flag/geometry the library does not implement */
-    SPH_ERR_CAPACITY = 7     /* a cell neighbourhood exceeded the candidate capacity (extreme compression) */
+    SPH_ERR_CAPACITY = 7     /* a cell neighbourhood exceeded the candidate capacity (extreme compression);
+                                the step that raised it and any enqueued after it used stale density and
+                                force in the overflowing cells, so the state is undefined: from then on
+                                sph_step returns this status without enqueuing, syncing calls report it
+                                again, and only reads and sph_destroy remain useful */
 } sph_status;
 
 typedef enum { SPH_FP32 = 0, SPH_FP64 = 1 } sph_precision;

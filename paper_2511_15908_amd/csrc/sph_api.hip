@@ -97,6 +97,7 @@ struct sph_ctx {
     std::vector<uint32_t> probe_host_scene;
     uint64_t steps = 0;
     bool dead = false;
+    bool overflowed = false;              // a step exceeded the neighbourhood capacity: state undefined
     std::string last_error;
     std::vector<uint8_t> type_of_id;      // host copy of types (read_field)
     std::vector<sph_params> prms;         // per scene
@@ -876,12 +877,17 @@ sph_status check_err(sph_ctx *c)
     uint32_t e = 0;
     HIPCHK(c, hipMemcpyAsync(&e, c->err, 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->overflowed) return SPH_ERR_CAPACITY;
     if (e) {
         const uint32_t z = 0;
         HIPCHK(c, hipMemcpyAsync(c->err, &z, 4, hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (e & ERR_CAPACITY) {
-            c->last_error = "a cell neighbourhood exceeded the candidate capacity";
+            // the overflowing cells kept stale density and force, which the
+            // integration and the wrench then used: the state is no longer a
+            // simulation state, so the context refuses further steps
+            c->overflowed = true;
+            c->last_error = "a cell neighbourhood exceeded the candidate capacity; the state is undefined";
             return SPH_ERR_CAPACITY;
         }
         c->last_error = "non-finite or over-speed particle";
@@ -1195,6 +1201,7 @@ sph_status sph_step(sph_ctx *ctx, uint32_t n_steps, void *hip_stream)
 {
     if (!ctx) return SPH_ERR_ARG;
     if (ctx->dead) return SPH_ERR_STATE;
+    if (ctx->overflowed) return SPH_ERR_CAPACITY;
     ctx->stream = (hipStream_t)hip_stream;
     if (!ctx->n) {
         ctx->steps += n_steps;

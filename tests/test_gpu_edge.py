@@ -111,7 +111,8 @@ def test_particles_outside_grid(gpu, orc):
 
 def test_capacity_overflow_is_reported(gpu):
     """5,000 particles in one cell exceed the 64-word neighbourhood capacity:
-    the step reports SPH_ERR_CAPACITY instead of computing garbage."""
+    the step reports SPH_ERR_CAPACITY, and since the overflowing cells kept
+    stale values the context refuses every later step (the error is sticky)."""
     from paper_2511_15908_amd import scenes
     rng = scenes.SplitMix64(7, 9)
     x = (rng.uniform(15000).reshape(5000, 3) - 0.5) * 0.03 - 0.02
@@ -121,7 +122,17 @@ def test_capacity_overflow_is_reported(gpu):
     with pytest.raises(gpu.SphError) as e:
         sim.synchronize()
     assert e.value.status == 7
-    sim.synchronize()      # the condition was reported once and cleared
+    steps = sim.info()["steps"]
+    with pytest.raises(gpu.SphError) as e:
+        sim.step(1)            # refused, nothing enqueued
+    assert e.value.status == 7
+    assert sim.info()["steps"] == steps
+    with pytest.raises(gpu.SphError) as e:
+        sim.synchronize()      # reported again
+    assert e.value.status == 7
+    x = sim.read("x", check=False)   # reads still copy the (undefined) state for diagnosis
+    assert x.shape == (sc.n, 3)
+    sim.close()
 
 
 def test_instability_flag(gpu):
