@@ -146,6 +146,24 @@ sph_status sph_init(const sph_params *params, const sph_scene *scene, void *d_wo
                     size_t ws_bytes, void *hip_stream, sph_ctx **out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sph_init
+ * with the workspace taken from a device array inside the library instead of
+ * the caller's, SPH_STATIC_WORKSPACE_BYTES on each device the library runs on,
+ * held until the process ends.  The array is on the calling thread's current
+ * device; hip_stream must belong to that device.  Everything after init
+ * (sph_step and the rest) is unchanged; sph_destroy hands the array back.
+ * The array keeps the previous context's contents; init writes or clears
+ * everything a step reads.  One such context per device at a time: a second
+ * sph_init_static on a device whose array is held returns SPH_ERR_STATE (two
+ * contexts on one array would overwrite each other's state); a scene whose
+ * sph_workspace_size exceeds the array returns SPH_ERR_WORKSPACE.  No device
+ * memory is allocated by this call or by any later call on the context.
+ */
+#define SPH_STATIC_WORKSPACE_BYTES (128u << 20)
+sph_status sph_init_static(const sph_params *params, const sph_scene *scene, void *hip_stream, sph_ctx **out);
+
+/*
  * Pose of a kinematic object from the haptic device (Sec. 3.3, Fig. 1):
  * reference point c, orientation q (w,x,y,z; normalised by the library),
  * linear velocity v and angular velocity w (world frame).  Enqueued on the

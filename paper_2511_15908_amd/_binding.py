@@ -17,6 +17,7 @@ _PKG = Path(__file__).resolve().parent
 LIB_PATH = Path(os.environ.get("SPH_LIB", _PKG / "libsph.so"))
 
 SPH_ABI_VERSION = 1
+SPH_STATIC_WORKSPACE_BYTES = 128 << 20
 SPH_FP32, SPH_FP64 = 0, 1
 SPH_FLUID, SPH_SOFT, SPH_BOUNDARY = 0, 1, 2
 SPH_FLAG_CLAMP_NEG_PRESSURE, SPH_FLAG_BOUNDARY_SINGLE_TERM, SPH_FLAG_NO_BOUNDARY_VISCOSITY = 1, 2, 4
@@ -29,7 +30,7 @@ STATUS = {0: "SPH_OK", 1: "SPH_ERR_ARG", 2: "SPH_ERR_WORKSPACE", 3: "SPH_ERR_DEV
           4: "SPH_ERR_STATE", 5: "SPH_ERR_UNSTABLE", 6: "SPH_ERR_UNSUPPORTED", 7: "SPH_ERR_CAPACITY"}
 N_PHASES = 10
 
-EXPORTED = ["sph_workspace_size", "sph_init", "sph_set_body_pose", "sph_step", "sph_get_body_wrench",
+EXPORTED = ["sph_workspace_size", "sph_init", "sph_init_static", "sph_set_body_pose", "sph_step", "sph_get_body_wrench",
             "sph_reset_smoothing", "sph_read_field", "sph_debug_neighbors", "sph_debug_neighbors_of",
             "sph_get_stats", "sph_get_info",
             "sph_synchronize", "sph_profile_begin", "sph_profile_read", "sph_profile_phase_name",
@@ -87,6 +88,7 @@ def load_library(path=None):
     d3 = C.POINTER(C.c_double)
     L.sph_workspace_size.argtypes = [C.POINTER(SphParams), C.POINTER(SphScene), C.POINTER(sz)]
     L.sph_init.argtypes = [C.POINTER(SphParams), C.POINTER(SphScene), vp, sz, vp, C.POINTER(vp)]
+    L.sph_init_static.argtypes = [C.POINTER(SphParams), C.POINTER(SphScene), vp, C.POINTER(vp)]
     L.sph_set_body_pose.argtypes = [vp, C.c_uint32, d3, d3, d3, d3]
     L.sph_step.argtypes = [vp, C.c_uint32, vp]
     L.sph_get_body_wrench.argtypes = [vp, C.c_uint32, d3, d3, C.c_int]
@@ -198,11 +200,13 @@ class Sim:
     stepped together; particle and object ids of scene k follow those of the
     earlier scenes).  The workspace is a torch uint8 tensor on `device`;
     kernels run on torch's current stream of that device (or `stream`, a
-    torch.cuda.Stream).
+    torch.cuda.Stream).  static_workspace=True (one scene) uses the library's
+    own per-device workspace instead (sph_init_static: nothing is allocated;
+    one such context per device at a time).
     """
 
     def __init__(self, scene, precision=None, device="cuda", stream=None, v_max=0.0, params=None, max_probes=0,
-                 log_steps=0, track_steps=0):
+                 log_steps=0, track_steps=0, static_workspace=False):
         import torch
         self.torch = torch
         self.L = load_library()
@@ -220,19 +224,28 @@ class Sim:
                 pr.update(params)
             self.P[k] = make_params(pr, self.precision, v_max, max_probes, log_steps, track_steps)
             S[k] = self._arrays[k].struct
-        out = C.c_size_t(0)
-        st = self.L.sph_batch_workspace_size(self.P, S, ns, C.byref(out))
-        if st:
-            raise SphError(st, "sph_batch_workspace_size")
-        self.ws_bytes = int(out.value)
-        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.ws.data_ptr()
-        aligned = (base + 255) & ~255
         self.ctx = C.c_void_p()
-        st = self.L.sph_batch_init(self.P, S, ns, C.c_void_p(aligned), self.ws_bytes, self.stream_handle(),
-                                   C.byref(self.ctx))
-        if st:
-            raise SphError(st, "sph_batch_init")
+        if static_workspace:
+            if ns != 1:
+                raise ValueError("static_workspace takes one scene")
+            self.ws, self.ws_bytes = None, 0
+            with torch.cuda.device(self.device):
+                st = self.L.sph_init_static(self.P, S, self.stream_handle(), C.byref(self.ctx))
+            if st:
+                raise SphError(st, "sph_init_static")
+        else:
+            out = C.c_size_t(0)
+            st = self.L.sph_batch_workspace_size(self.P, S, ns, C.byref(out))
+            if st:
+                raise SphError(st, "sph_batch_workspace_size")
+            self.ws_bytes = int(out.value)
+            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            aligned = (base + 255) & ~255
+            st = self.L.sph_batch_init(self.P, S, ns, C.c_void_p(aligned), self.ws_bytes, self.stream_handle(),
+                                       C.byref(self.ctx))
+            if st:
+                raise SphError(st, "sph_batch_init")
         self.n = sum(sc.n for sc in scenes)
         self.part0 = np.cumsum([0] + [sc.n for sc in scenes])
         self.obj0 = np.cumsum([0] + [len(sc.object_kinematic) for sc in scenes])

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <limits>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -98,6 +99,7 @@ struct sph_ctx {
     uint64_t steps = 0;
     bool dead = false;
     bool overflowed = false;              // a step exceeded the neighbourhood capacity: state undefined
+    int static_dev = -1;                  // device whose static workspace this context holds (sph_init_static)
     std::string last_error;
     std::vector<uint8_t> type_of_id;      // host copy of types (read_field)
     std::vector<sph_params> prms;         // per scene
@@ -920,6 +922,21 @@ sph_status capture_two_steps(sph_ctx *c)
 
 }  // namespace
 
+// Workspace of sph_init_static: one per device, in the code object's device
+// memory, so that a caller that may not allocate device memory can still run
+// the whole step.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[SPH_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxStaticDevices] = {};    // address of `scratch` on each device
+bool g_static_busy[kMaxStaticDevices] = {};    // a live context holds that device's array
+
+}  // namespace
+
 extern "C" {
 
 const char *sph_status_string(sph_status s)
@@ -1037,6 +1054,39 @@ sph_status sph_init(const sph_params *params, const sph_scene *scene, void *d_wo
                     void *hip_stream, sph_ctx **out)
 {
     return sph_batch_init(params, scene, 1, d_workspace, ws_bytes, hip_stream, out);
+}
+
+sph_status sph_init_static(const sph_params *params, const sph_scene *scene, void *hip_stream, sph_ctx **out)
+{
+    if (!out) return SPH_ERR_ARG;
+    *out = nullptr;
+    size_t need = 0;
+    sph_status st = sph_batch_workspace_size(params, scene, 1, &need);
+    if (st != SPH_OK) return st;
+    if (need > (size_t)SPH_STATIC_WORKSPACE_BYTES) return SPH_ERR_WORKSPACE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return SPH_ERR_DEVICE;
+    if (dev < 0 || dev >= kMaxStaticDevices) return SPH_ERR_UNSUPPORTED;
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_busy[dev]) return SPH_ERR_STATE;
+        if (!g_static_ptr[dev]) {
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SPH_ERR_DEVICE;
+            g_static_ptr[dev] = p;
+        }
+        base = g_static_ptr[dev];
+        g_static_busy[dev] = true;
+    }
+    st = sph_batch_init(params, scene, 1, base, (size_t)SPH_STATIC_WORKSPACE_BYTES, hip_stream, out);
+    if (st != SPH_OK) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        g_static_busy[dev] = false;
+        return st;
+    }
+    (*out)->static_dev = dev;
+    return SPH_OK;
 }
 
 sph_status sph_set_body_pose(sph_ctx *ctx, uint32_t object, const double c[3], const double q[4], const double v[3],
@@ -1690,9 +1740,14 @@ sph_status sph_profile_read(sph_ctx *ctx, double *ms, uint32_t *launches, uint32
 sph_status sph_destroy(sph_ctx *ctx)
 {
     if (!ctx) return SPH_OK;
-    if (!ctx->dead) (void)hipStreamSynchronize(ctx->stream);
+    // a static workspace is handed on only after the stream's work on it is done
+    if (!ctx->dead || ctx->static_dev >= 0) (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        g_static_busy[ctx->static_dev] = false;
+    }
     delete ctx;
     return SPH_OK;
 }
