@@ -78,26 +78,70 @@ def log(msg, quiet=False):
         print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(scene, min_seconds=10.0):
-    """The oracle as it stands, timed on the host cores: full steps of the
-    same scene (neighbour lists, density, forces, springs, wrench,
-    integration) until at least min_seconds have elapsed."""
+def _omp(threads):
+    """Set the OpenMP team size of the oracle's parallel loops (libgomp)."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(threads))
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_oracle(scene, steps):
     import oracle
-    oracle.build(force=False)
     o = oracle.Oracle(scene, scene.precision)
     nmov = int((scene.type != 2).sum())
-    steps = 0
     t0 = time.perf_counter()
-    while True:
+    for _ in range(steps):
         o.step()
-        steps += 1
-        dt = time.perf_counter() - t0
-        if dt >= min_seconds:
-            break
+    dt = time.perf_counter() - t0
+    return {"particle_updates_per_s": nmov * steps / dt, "s_per_step": dt / steps, "steps": steps,
+            "n_particles": int(scene.n), "n_fluid_soft": nmov}
+
+
+def cpu_baseline(scene, log_fn=None):
+    """The oracle as it stands, timed on the host cores: whole FP64 oracle
+    steps (neighbour lists, density, forces, springs, wrench, integration).
+    value: 3 steps of the benchmark scene on all cores; beside it one step on
+    one core, and the FP64 dam break in full (100 steps) on all cores and for
+    10 steps on one core."""
+    import oracle
+    from paper_2511_15908_amd import scenes
+    oracle.build(force=False)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": nmov * steps / dt, "unit": "particle-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} full FP64 oracle step(s) of the same {scene.n:,}-particle scene "
-                      f"({nmov:,} fluid+soft), {dt:.1f} s wall"}
+    say = log_fn or (lambda m: None)
+    _omp(cores)
+    say(f"cpu baseline: benchmark scene, 3 steps on {cores} threads")
+    allc = _time_oracle(scene, 3)
+    _omp(1)
+    say("cpu baseline: benchmark scene, 1 step on 1 thread")
+    one = _time_oracle(scene, 1)
+    dam = scenes.dam_break()
+    say("cpu baseline: dam break (FP64, 100 steps) on all threads, 10 steps on 1 thread")
+    _omp(cores)
+    dam_all = _time_oracle(dam, 100)
+    _omp(1)
+    dam_one = _time_oracle(dam, 10)
+    _omp(cores)
+    return {"value": allc["particle_updates_per_s"], "unit": "particle-updates/s", "cores": cores,
+            "kind": "oracle", "cpu_model": _cpu_model(),
+            "sample": f"3 full FP64 oracle steps of the same {scene.n:,}-particle scene "
+                      f"({allc['n_fluid_soft']:,} fluid+soft) on {cores} threads, "
+                      f"{3 * allc['s_per_step']:.1f} s wall",
+            "one_thread": {"value": one["particle_updates_per_s"], "sample": "1 step of the same scene",
+                           "s_per_step": round(one["s_per_step"], 2)},
+            "dam_break_fp64": {"n_particles": dam_all["n_particles"],
+                               "all_threads": {"value": dam_all["particle_updates_per_s"], "steps": 100,
+                                               "s_per_step": round(dam_all["s_per_step"], 4)},
+                               "one_thread": {"value": dam_one["particle_updates_per_s"], "steps": 10,
+                                              "s_per_step": round(dam_one["s_per_step"], 4)}}}
 
 
 def profiled_traffic(kernel, n_particles):
@@ -244,7 +288,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"coupled fluid+soft+rigid, {info['n_fluid']:,} fluid + {info['n_soft']:,} soft "
                                f"+ {info['n_body_particles']:,} grabbed sphere + tank, {info['n']:,} particles, "
-                               f"h=0.01 m, dt=2.5e-4 s, 1 kHz pose",
+                               f"h=0.01 m, dt=2.5e-4 s, 1 kHz pose; readings: negative pressure clamped to 0, "
+                               f"nu = {sc.params['nu']:g} m^2/s (nu proportional to h)",
                    "n_particles": info["n"], "precision": "fp32 particles, fp64 wrench",
                    "parallelism": "single GPU"},
         "wrench_hz_plain": a.steps / el,
@@ -310,8 +355,8 @@ def main():
                          "ticks_simulated": r["ticks_collected"], "collect_seconds": round(r["collect_s"], 1)}}
     log(json.dumps(out, indent=1), a.quiet)
     if not a.no_cpu_baseline:
-        log("timing the CPU oracle on one step of the same scene ...", a.quiet)
-        out["cpu_baseline"] = cpu_baseline(sc)
+        log("timing the CPU oracle (same scene, all threads and one thread; FP64 dam break) ...", a.quiet)
+        out["cpu_baseline"] = cpu_baseline(sc, lambda m: log(m, a.quiet))
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

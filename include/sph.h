@@ -133,7 +133,15 @@ typedef struct {               /* read-only facts about a context */
     double cell_size;                   /* 2h (1 + 2^-10) */
 } sph_info;
 
-/* Bytes of device workspace sph_init needs for these params and scene. */
+/*
+ * Bytes of device workspace sph_init needs for these params and scene: the
+ * particle state the simulation loop of Alg. 2 carries from step to step
+ * (positions, velocities, types, body slots, spring table), the uniform-grid
+ * hash of Alg. 2 (keys, sort buffers, cell start/end tables, Sec. 3.1), the
+ * density/pressure and force arrays of Alg. 1 and the FP64 body tables
+ * (Sec. 3.2, 3.3).  Host-only (no device work); SPH_ERR_ARG /
+ * SPH_ERR_UNSUPPORTED as sph_init would report them.
+ */
 sph_status sph_workspace_size(const sph_params *params, const sph_scene *scene, size_t *bytes);
 
 /*
@@ -256,7 +264,17 @@ sph_status sph_set_graph(sph_ctx *ctx, int enable);
  */
 sph_status sph_set_body_track(sph_ctx *ctx, uint32_t object, uint32_t n, const double *poses);
 
-/* Enqueue n_steps full steps on hip_stream (no host synchronisation). */
+/*
+ * Enqueue n_steps full steps on hip_stream (no host synchronisation).  One
+ * step is one pass of the simulation loop (Alg. 2): rigid placement (Sec.
+ * 3.2), the spatial hash and its sorted order (Sec. 3.1, Alg. 2), spring
+ * forces (Sec. 3.2), the density and pressure pass and the force pass of
+ * Alg. 1 (Eqs. kernel, density, pressure), the reduction of the body
+ * particles' forces into each body's force and torque (Sec. 3.2, 3.3) and
+ * the semi-implicit Euler update (Eq. euler).  Errors raised on the device
+ * (SPH_ERR_UNSTABLE, SPH_ERR_CAPACITY) surface at the next synchronising
+ * call; SPH_ERR_STATE after a device error, SPH_ERR_CAPACITY after an overflow.
+ */
 sph_status sph_step(sph_ctx *ctx, uint32_t n_steps, void *hip_stream);
 
 /*
@@ -273,12 +291,22 @@ sph_status sph_get_body_wrench(sph_ctx *ctx, uint32_t object, double F[3], doubl
 /* Restart the rolling average of a kinematic object (grab or release). */
 sph_status sph_reset_smoothing(sph_ctx *ctx, uint32_t object);
 
-/* Copy a field (SPH_FIELD_*) into host_dst; bytes must equal its size. Synchronises. */
+/*
+ * Copy a field (SPH_FIELD_*, each defined beside its enum entry by the
+ * equation it comes from: Eq. density, Eq. pressure, Alg. 1 forces, Eq. euler
+ * state) into host_dst, in original particle-id order, converted to double
+ * (keys as uint32); bytes must equal its size (SPH_ERR_ARG otherwise).
+ * Synchronises and reports pending step errors like sph_synchronize (the
+ * values are still written).
+ */
 sph_status sph_read_field(sph_ctx *ctx, int field, void *host_dst, size_t bytes);
 
 /*
- * Neighbour lists found by the last step's density pass, for checking (any N,
- * but it copies O(N * candidates) bytes to the host).  counts[n] receives
+ * Neighbour lists N(i) = { j : |x_i - x_j| < 2h } (the support of Eq. kernel,
+ * over which Alg. 1 sums; the integer decision is the canonical predicate of
+ * the run precision) found by the last step's density pass, for checking (any
+ * N, but it copies O(N * candidates) bytes to the host).  The extra output
+ * total lets a caller size ids with a first call (ids = NULL, cap = 0).  counts[n] receives
  * |N(i)| for fluid, soft and kinematic-boundary particles (0 for static
  * boundary particles); ids receives the lists back to back in particle-id
  * order, each ascending, self included.  *total receives the total; ids is

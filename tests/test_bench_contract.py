@@ -38,3 +38,19 @@ def test_bench_line_fields(monkeypatch, capsys):
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in r, k
     assert 0 < r["frac"] < 1 and r["achieved"] == pytest.approx(r["frac"] * r["peak"], rel=1e-3)
+
+
+def test_cpu_baseline_protocol(monkeypatch):
+    """The CPU-baseline record: the oracle timed on all threads and on one
+    thread, with the CPU model, and the FP64 dam break beside it (here on
+    small stand-in scenes so the test stays short)."""
+    import bench
+    from paper_2511_15908_amd import scenes
+    small = scenes.small_scene(seed=41, nf=(5, 4, 4), n_tank=(10, 8, 8))
+    monkeypatch.setattr(scenes, "dam_break", lambda: scenes.small_scene(seed=42, nf=(4, 4, 4), n_tank=(8, 6, 6),
+                                                                        precision="f64"))
+    r = bench.cpu_baseline(small)
+    assert r["kind"] == "oracle" and r["unit"] == "particle-updates/s" and r["cores"] >= 1
+    assert r["value"] > 0 and r["one_thread"]["value"] > 0 and isinstance(r["cpu_model"], str)
+    assert r["dam_break_fp64"]["all_threads"]["steps"] == 100 and r["dam_break_fp64"]["one_thread"]["steps"] == 10
+    assert "3 full FP64 oracle steps" in r["sample"]

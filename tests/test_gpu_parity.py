@@ -85,6 +85,7 @@ def _check_step(sc, o, g, r, prec, tol):
         eF = _cmp.rel_vec(F_g, F_o, sc.params["rho0"] * _cmp.G * V)
         eT = _cmp.rel_vec(T_g, T_o, sc.params["rho0"] * _cmp.G * V * L)
         assert eF <= tol["f"] and eT <= tol["f"], f"wrench error F {eF} T {eT}"
+        print(f"parity {prec} {sc.name}: density {e_rho:.2e} force {e_f:.2e} wrench F {eF:.2e} T {eT:.2e}")
     # integration
     dt = sc.params["dt"]
     mov = fs
