@@ -616,7 +616,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                         const int k = (int)__builtin_ctzll(m);
                         m &= m - 1ull;
                         const Cand64 c = cand64[k];
-                        acc = fma(c.m, spline_shape64(c.x - mx, c.y - my, c.z - mz, ph.inv_h64), acc);
+                        acc = fma(c.m, spline_shape64<sizeof(T) == 8>(c.x - mx, c.y - my, c.z - mz, ph.inv_h64), acc);
                     }
                 } else {
                     int base = 0;
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                         if (mw[0] == 0ull) break;
                         const int k = take_hit(mw, base);
                         const Cand64 c = cand64[k];
-                        acc = fma(c.m, spline_shape64(c.x - mx, c.y - my, c.z - mz, ph.inv_h64), acc);
+                        acc = fma(c.m, spline_shape64<sizeof(T) == 8>(c.x - mx, c.y - my, c.z - mz, ph.inv_h64), acc);
                     }
                 }
             }
@@ -651,7 +651,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                             nleftpair_d += fs_t ? cnt : 0u;
                             if (fs_t && hit) {
                                 const Cand64 c64 = cand64[q * kWave + lane];
-                                part = fma(c64.m, spline_shape64(c64.x - tx, c64.y - ty, c64.z - tz, ph.inv_h64),
+                                part = fma(c64.m, spline_shape64<sizeof(T) == 8>(c64.x - tx, c64.y - ty, c64.z - tz, ph.inv_h64),
                                            part);
                             }
                         }

@@ -195,25 +195,34 @@ __device__ __forceinline__ double grid_R2<double>(const Grid &g) { return g.R2_6
 // carries FP64 terms: p = k (rho - rho0) turns a relative density error e
 // into e rho / (rho - rho0) (~1e4 e near rest) in the pressure, whose pair
 // terms nearly cancel.  The constant alpha/6 multiplies finished sums.
+// EXACT = false (FP32 runs): r from an FP32 rsqrt seed and one Newton step in
+// FP64, relative error ~5e-15, far below the FP32 result's rounding.
+// EXACT = true (FP64 runs): r = sqrt(r^2) in binary64, so the density is good
+// to a few ulps and the pressure the force pass sees to ~1e-12 relative.
+template <bool EXACT>
 __device__ __forceinline__ double spline_shape64(double dx, double dy, double dz, double inv_h)
 {
     const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    // r from an FP32 rsqrt seed and one Newton step in FP64 (~1e-14)
-    const double y = (double)frsqrt((float)fmax(r2, 1e-30));
-    double r = r2 * y;
-    r = fma(0.5 * y, fma(-r, r, r2), r);
+    double r;
+    if constexpr (EXACT) {
+        r = sqrt(r2);
+    } else {
+        const double y = (double)frsqrt((float)fmax(r2, 1e-30));
+        r = r2 * y;
+        r = fma(0.5 * y, fma(-r, r, r2), r);
+    }
     const double q = r * inv_h;
     const double t2 = fmax(2.0 - q, 0.0);
     const double t1 = fmax(1.0 - q, 0.0);
     return fma(t2 * t2, t2, -4.0 * (t1 * (t1 * t1)));
 }
 
-// Kernel value W(|c - me|) in FP64.
+// Kernel value W(|c - me|) in FP64 (exact square root in FP64 runs).
 template <typename T>
 __device__ __forceinline__ double kernel_w64(const V4<T> &c, const V4<T> &me, const Phys<T> &ph)
 {
-    return ph.alpha6_64 * spline_shape64((double)c.x - (double)me.x, (double)c.y - (double)me.y,
-                                         (double)c.z - (double)me.z, ph.inv_h64);
+    return ph.alpha6_64 * spline_shape64<sizeof(T) == 8>((double)c.x - (double)me.x, (double)c.y - (double)me.y,
+                                                         (double)c.z - (double)me.z, ph.inv_h64);
 }
 
 // --- batches of independent scenes ---

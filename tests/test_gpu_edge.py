@@ -93,7 +93,7 @@ def test_overfull_cell(gpu, orc, prec):
     x = (rng.uniform(600).reshape(200, 3) - 0.5) * 0.03 - 0.02     # inside the cell [-0.04, 0.0002)^3
     v = (rng.uniform(600).reshape(200, 3) - 0.5) * 0.2
     sc = _scene(x, v, precision=prec)
-    tol = (1e-5, 1e-4) if prec == "f32" else (1e-12, 1e-10)
+    tol = (1e-5, 1e-4) if prec == "f32" else (1e-13, 1e-12)
     _compare_one_step(gpu, orc, sc, prec, *tol)
 
 
@@ -161,12 +161,12 @@ def test_reading_flags(gpu, orc, flag):
     o.set_pose(1, *pose)
     r = o.step()
     fs = np.nonzero(sc.type != 2)[0]
-    assert _cmp.rel_density(sim.read("rho")[fs], r["rho"][fs]) <= 1e-12
+    assert _cmp.rel_density(sim.read("rho")[fs], r["rho"][fs]) <= 1e-13
     assert np.allclose(sim.read("p")[fs], r["p"][fs], rtol=1e-9, atol=1e-9)
     mref = float(np.median(sc.mass[fs]))
-    assert _cmp.rel_force(sim.read("f")[fs], r["f"][fs], mref * 9.81) <= 1e-10
+    assert _cmp.rel_force(sim.read("f")[fs], r["f"][fs], mref * 9.81) <= 1e-12
     F, T = sim.wrench(1)
-    assert _cmp.rel_vec(F, r["wrench"][1][0], 1000 * 9.81 * 27 * sc.spacing ** 3) <= 1e-10
+    assert _cmp.rel_vec(F, r["wrench"][1][0], 1000 * 9.81 * 27 * sc.spacing ** 3) <= 1e-12
 
 
 def test_non_default_stream(gpu):

@@ -255,3 +255,143 @@ def test_guard_falls_back_to_residual_base(torch):
     net.set_guard(-1.0)
     assert np.array_equal(net.forward(dXt).cpu().numpy()[ok], plain[ok])
     assert net.guard_count() == (70, 8)
+
+
+# ---------------------------------------------------------------- element-wise bounds
+#
+# Element-wise error bounds derived from the arithmetic and propagated layer
+# by layer through the oracle's cached activations (standardised units).
+#
+# Against the BF16-mirroring oracle (quant=True) both sides round the same
+# values to BF16 at the same points, so an operand differs only where the
+# GPU's FP32 value and the oracle's FP64 value can fall on different sides of
+# a BF16 rounding midpoint: there by one BF16 step, elsewhere not at all.
+# Whether that can happen is decided per element from the bound on the
+# pre-rounding value.  Products accumulate in FP32 (K 2^-24 of sum |a||w|).
+#
+# Against the pure FP64 network (quant=False) every GEMM operand is rounded to
+# BF16 on the GPU (2^-9 relative, weights and activations), a worst-case sum.
+#
+# GELU is 1.129-Lipschitz and its derivative 0.798-Lipschitz; the FP32 GELU
+# and its derivative are taken as accurate to 2^-21 relative plus 2^-23 |z|.
+
+U8, U9, U21, U22, U23, U24 = (2.0 ** -e for e in (8, 9, 21, 22, 23, 24))
+LIP_GELU, LIP_DGELU = 1.129, 0.798
+
+
+def _bf16_step(v):
+    """One BF16 step at |v| (8 significant bits)."""
+    r = np.abs(M.bf16(v))
+    e = np.floor(np.log2(np.maximum(r, 2.0 ** -126)))
+    return 2.0 ** (e - 7)
+
+
+def _flip(v, err):
+    """Largest change of bf16(v) when v moves by at most err: 0 unless a
+    rounding midpoint lies within err (+ the FP32 rounding of v) of v."""
+    step = _bf16_step(v)
+    gap = 0.5 * step - np.abs(v - M.bf16(v))
+    return np.where(gap <= err + U23 * np.abs(v), 2.0 * step, 0.0)
+
+
+def _fwd_bounds(p, c, quant, xs_err):
+    """Bounds on |d a_l| (GEMM inputs) and |d z_l| for every layer."""
+    wb = M.unpack(p, H, LAYERS)
+    A, E = [], []
+    da = _flip(c["pre"][0], xs_err) if quant else U9 * np.abs(c["acts"][0]) + xs_err
+    for l, (W, _) in enumerate(wb):
+        A.append(da)
+        a = np.abs(c["acts"][l])
+        Wq = np.abs(M.bf16(W))
+        aw = a @ Wq.T
+        e = da @ Wq.T + (0.0 if quant else U9) * aw + W.shape[1] * U24 * aw + U24 * np.abs(c["zs"][l])
+        E.append(e)
+        if l + 1 < len(wb):
+            z = c["zs"][l]
+            v_err = LIP_GELU * e + U21 * np.abs(c["pre"][l + 1]) + U23 * np.abs(z)
+            da = _flip(c["pre"][l + 1], v_err) if quant else U9 * np.abs(c["acts"][l + 1]) + v_err
+    return A, E
+
+
+def _grad_bounds(p, c, A, E, ddz, m, quant):
+    """Bounds on the gradient elements (parameter layout), from the bound
+    ddz on the output-layer gradient dz_L."""
+    wb = M.unpack(p, H, LAYERS)
+    L = len(wb)
+    cur = c["dz_L"]
+    out = [None] * L
+    for l in range(L - 1, -1, -1):
+        W, _ = wb[l]
+        a = np.abs(c["acts"][l])
+        ac = np.abs(cur)
+        gW = ddz.T @ a + ac.T @ A[l] + m * U24 * (ac.T @ a)
+        gb = ddz.sum(0) + m * U24 * ac.sum(0)
+        if l == L - 1:
+            gW[N_OUT:] = 0.0
+            gb[N_OUT:] = 0.0
+        out[l] = (gW, gb)
+        if l > 0:
+            Wb = M.bf16(W) if quant else W
+            Wq = np.abs(M.bf16(W))
+            da = cur @ Wb
+            g1 = M.gelu_grad(c["zs"][l - 1])
+            dda = ddz @ Wq + (0.0 if quant else U9) * (ac @ Wq) + W.shape[0] * U24 * (ac @ Wq)
+            pre = da * g1
+            err = dda * np.abs(g1) + np.abs(da) * LIP_DGELU * E[l - 1] + U21 * np.abs(pre)
+            if quant:
+                cur = M.bf16(pre)
+                ddz = _flip(pre, err)
+            else:
+                cur = pre
+                ddz = err + U9 * np.abs(pre)
+    return M.pack(out)
+
+
+def _forward_with_pre(p, X, norm, quant):
+    """The oracle's forward pass plus the pre-rounding values of every GEMM
+    input (standardised inputs, GELU outputs)."""
+    out, c = M.forward(p, X, norm, H, LAYERS, N_OUT, quant=quant)
+    mx, sx = norm[0], norm[1]
+    xs = np.zeros((X.shape[0], M.K_IN))
+    xs[:, :N_IN] = (X.astype(np.float64) - mx) / sx
+    c["pre"] = [xs] + [M.gelu(z) for z in c["zs"][:-1]]
+    return out, c, xs
+
+
+@pytest.mark.parametrize("quant", [True, False])
+def test_elementwise_forward_and_gradients(torch, quant):
+    """Batch 4096 (16 split-K slices in the weight gradients): every output
+    and every gradient element within its derived bound, against the
+    BF16-mirroring oracle and against the pure FP64 network."""
+    m = 4096
+    X, Y = _data(6, m)
+    net, p = _net(torch, seed=19)
+    dX, dY = torch.tensor(X, device="cuda"), torch.tensor(Y, device="cuda")
+    net.fit_normalizer(dX, dY)
+    norm = [np.asarray(v, np.float64) for v in net.get_normalizer()]
+    p64 = p.astype(np.float64)
+    out_o, c, xs = _forward_with_pre(p64, X, norm, quant)
+    A, E = _fwd_bounds(p64, c, quant, U22 * np.abs(xs))
+    sy = norm[3]
+    out_g = net.forward(dX).cpu().numpy().astype(np.float64)
+    bound_out = E[-1][:, :N_OUT] * sy + U22 * np.abs(out_o)
+    diff = np.abs(out_g - out_o)
+    print(f"quant={quant}: forward max |diff|/bound {np.max(diff / bound_out):.3f}, "
+          f"max |diff| {diff.max():.2e}, elements at zero bound {int(np.sum(bound_out == 0))}")
+    assert np.all(diff <= bound_out)
+    g_gpu, loss_gpu = net.gradients(dX, dY)
+    loss_o, g_o = M.loss_and_grad(p64, X, Y, norm, H, LAYERS, N_OUT, quant=quant)
+    ys = (Y.astype(np.float64) - norm[2]) / sy
+    dz_L = np.zeros((m, 16))
+    dz_L[:, :N_OUT] = 2.0 * (c["out_s"] - ys) / (m * N_OUT)
+    c["dz_L"] = M.bf16(dz_L) if quant else dz_L
+    err = np.zeros((m, 16))
+    err[:, :N_OUT] = 2.0 * (E[-1][:, :N_OUT] + U22 * np.abs(ys)) / (m * N_OUT) + U22 * np.abs(dz_L[:, :N_OUT])
+    ddz = _flip(dz_L, err) if quant else err + U9 * np.abs(dz_L)
+    bound_g = _grad_bounds(p64, c, A, E, ddz, m, quant)
+    diff = np.abs(g_gpu.astype(np.float64) - g_o)
+    worst = float(np.max(diff / np.maximum(bound_g, 1e-300)))
+    print(f"quant={quant}: gradient max |diff|/bound {worst:.3f} over {g_o.size} elements "
+          f"(max |diff| {diff.max():.2e})")
+    assert np.all(diff <= bound_g), np.flatnonzero(diff > bound_g)[:10]
+    assert loss_gpu == pytest.approx(loss_o, rel=2e-3 if quant else 2e-2)
