@@ -70,6 +70,9 @@ def parse():
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the 256-scene batch leg and print its record (for profiling it alone)")
+    ap.add_argument("--mlp-train-only", action="store_true",
+                    help="run only surrogate training steps (batch 4096, 126-256-256-256-6) and print their "
+                         "rate in matrix-core FLOP/s (for profiling the MFMA kernels)")
     return ap.parse_args()
 
 
@@ -202,6 +205,46 @@ def batch_leg(dev, n_scenes=256, steps=64):
             "particles_per_wavefront": n_all / max(d["waves"], 1)}
 
 
+# Dense products of one surrogate training step per sample (126 inputs padded
+# to 128, three hidden layers of 256, 6 outputs padded to 16): forward
+# X W^T of every layer, weight gradients dZ^T A of every layer, and the data
+# gradients dZ W of every layer but the first; 2 FLOP per multiply-add.
+MLP_SHAPES = [(256, 128), (256, 256), (256, 256), (16, 256)]
+MLP_FLOP_PER_SAMPLE = 2 * (2 * sum(n * k for n, k in MLP_SHAPES) + sum(n * k for n, k in MLP_SHAPES[1:]))
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def mlp_train_leg(dev, steps=200, warmup=20, batch=4096):
+    """Training steps of the wrench surrogate on synthetic rows (the
+    library's BF16-MFMA kernels), timed with HIP events on the network's
+    stream."""
+    import torch
+    from paper_2511_15908_amd import mlp, scenes, surrogate
+    rng = scenes.SplitMix64(77, 9)
+    n_in, n_out = 126, 6
+    X = torch.tensor(rng.normal(batch * n_in).reshape(batch, n_in).astype(np.float32), device=dev)
+    Y = torch.tensor(rng.normal(batch * n_out).reshape(batch, n_out).astype(np.float32), device=dev)
+    net = mlp.Mlp(n_in, n_out, hidden=256, layers=3, max_batch=batch, device=dev)
+    net.set_params(surrogate.init_params(7, 256, 3, n_in, n_out))
+    net.fit_normalizer(X, Y)
+    for _ in range(warmup):
+        net.train_step(X, Y, 1e-4)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        net.train_step(X, Y, 1e-4)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    tflops = MLP_FLOP_PER_SAMPLE * batch / (ms * 1e-3) / 1e12
+    return {"batch": batch, "steps": steps, "ms_per_train_step": round(ms, 4),
+            "flop_per_step": MLP_FLOP_PER_SAMPLE * batch, "achieved_tflops": round(tflops, 3),
+            "peak_bf16_tflops": PEAK_BF16_TFLOPS, "frac": round(tflops / PEAK_BF16_TFLOPS, 5),
+            "loss": net.last_loss()}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -226,6 +269,9 @@ def main():
         return
     if a.batch_only:
         print(json.dumps({"batch": batch_leg(dev)}), flush=True)
+        return
+    if a.mlp_train_only:
+        print(json.dumps({"mlp_train": mlp_train_leg(dev)}), flush=True)
         return
     t0 = time.perf_counter()
     sc = scenes.coupled_1m(n_fluid=a.n_fluid)

@@ -235,12 +235,17 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, con
     if (t == 0) partials[blockIdx.x] = red[0];
 }
 
-__global__ void k_loss_final(const double *__restrict__ partials, uint32_t nblk, double denom, double *__restrict__ loss)
+// Sum of the per-block loss partials in a fixed order: lane i adds partials
+// i, i + 64, ... in turn, then the 64 lane sums are added pairwise (xor
+// butterfly, the same order on every run).
+__global__ __launch_bounds__(64) void k_loss_final(const double *__restrict__ partials, uint32_t nblk, double denom,
+                                                   double *__restrict__ loss)
 {
-    if (threadIdx.x != 0) return;
+    const uint32_t lane = threadIdx.x;
     double s = 0.0;
-    for (uint32_t b = 0; b < nblk; ++b) s += partials[b];
-    *loss = s / denom;
+    for (uint32_t b = lane; b < nblk; b += 64u) s += partials[b];
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) *loss = s / denom;
 }
 
 uint32_t loss_blocks(uint32_t m) { return (m * kOutPad + 255) / 256; }
@@ -252,24 +257,54 @@ void launch_loss(hipStream_t s, const float *out, const float *Y, uint32_t m, ui
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, partials, nblk, (double)m * n_out, loss);
 }
 
-// db[c] = sum over rows of dz[r][c]: 64 columns x 4 row groups per block,
-// fixed-order combination.
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *__restrict__ dz, uint32_t m, uint32_t n,
-                                                   uint32_t ld, float *__restrict__ db)
+// db[c] = sum over rows of dz[r][c] in two passes with a fixed order.  Pass
+// 1: block (x, y) sums rows [128 y, 128 y + 128) of columns [64 x, 64 x + 64)
+// (4 row groups of 64 threads, combined in LDS) into part[y][c]; pass 2 adds
+// the slices of each column the same way (slice groups y mod 4).
+constexpr uint32_t kBiasRows = 128;
+
+__global__ void k_fill_f32(float *__restrict__ p, float v, uint32_t count);
+
+__global__ __launch_bounds__(256) void k_bias_partial(const uint16_t *__restrict__ dz, uint32_t m, uint32_t n,
+                                                      uint32_t ld, float *__restrict__ part)
+{
+    __shared__ float red[4][64];
+    const uint32_t c = blockIdx.x * 64u + (threadIdx.x & 63u), g = threadIdx.x >> 6;
+    const uint32_t r0 = blockIdx.y * kBiasRows, r1 = min(r0 + kBiasRows, m);
+    float s = 0.f;
+    if (c < n)
+        for (uint32_t r = r0 + g; r < r1; r += 4u) s += from_bf16(dz[(size_t)r * ld + c]);
+    red[g][threadIdx.x & 63u] = s;
+    __syncthreads();
+    if (g == 0 && c < n)
+        part[(size_t)blockIdx.y * n + c] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_bias_reduce(const float *__restrict__ part, uint32_t slices, uint32_t n,
+                                                     float *__restrict__ db)
 {
     __shared__ float red[4][64];
     const uint32_t c = blockIdx.x * 64u + (threadIdx.x & 63u), g = threadIdx.x >> 6;
     float s = 0.f;
     if (c < n)
-        for (uint32_t r = g; r < m; r += 4u) s += from_bf16(dz[(size_t)r * ld + c]);
+        for (uint32_t y = g; y < slices; y += 4u) s += part[(size_t)y * n + c];
     red[g][threadIdx.x & 63u] = s;
     __syncthreads();
-    if (g == 0 && c < n) db[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    if (g == 0 && c < n)
+        db[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
-void launch_bias_grad(hipStream_t s, const uint16_t *dz, uint32_t m, uint32_t n, uint32_t ld, float *db)
+void launch_bias_grad(hipStream_t s, const uint16_t *dz, uint32_t m, uint32_t n, uint32_t ld, float *db,
+                      float *part)
 {
-    hipLaunchKernelGGL(k_bias_grad, dim3((n + 63) / 64), dim3(256), 0, s, dz, m, n, ld, db);
+    const uint32_t slices = (m + kBiasRows - 1) / kBiasRows;
+    if (!slices) {
+        hipLaunchKernelGGL(k_fill_f32, dim3((n + 255) / 256), dim3(256), 0, s, db, 0.0f, n);
+        return;
+    }
+    hipLaunchKernelGGL(k_bias_partial, dim3((n + 63) / 64, slices), dim3(256), 0, s, dz, m, n, ld, part);
+    hipLaunchKernelGGL(k_bias_reduce, dim3((n + 63) / 64), dim3(256), 0, s, part, slices, n, db);
 }
 
 // Adam (Kingma and Ba, Algorithm 1) with precomputed bias corrections

@@ -155,7 +155,10 @@ size_t carve(mlp_ctx *c, char *base)
     c->dz[1] = cv.take<uint16_t>(B * H);
     size_t maxwk = 0;
     for (uint32_t l = 0; l <= c->L; ++l) maxwk = std::max(maxwk, (size_t)c->Nl[l] * c->Kl[l]);
-    c->partials = cv.take<float>((size_t)c->max_splits * maxwk);
+    // split-K partials of the weight gradients, later the bias-gradient row
+    // slices (128 rows each) of the same layer
+    const size_t bias_part = (size_t)((c->B + 127) / 128) * std::max<uint32_t>(c->H, 16u);
+    c->partials = cv.take<float>(std::max((size_t)c->max_splits * maxwk, bias_part));
     c->loss_part = cv.take<double>(loss_blocks(c->B));
     c->loss = cv.take<double>(1);
     c->px = cv.take<float>(kIn);
@@ -266,7 +269,8 @@ void backward(mlp_ctx *c, const float *X, const float *Y, uint32_t m)
         g.ldc = K;
         launch_gemm(s, LD_R, LD_R, EPI_PARTIAL, g, splits);
         launch_splitk_reduce(s, c->partials, splits, N * K, c->grad + c->off[l]);
-        launch_bias_grad(s, dz, m, N, ldd, c->grad + c->off[l] + (size_t)N * K);
+        // the split-K partials are consumed: their buffer holds the bias partials
+        launch_bias_grad(s, dz, m, N, ldd, c->grad + c->off[l] + (size_t)N * K, c->partials);
         if (l > 0) {
             // dz_{l-1} = (dz W_l) * GELU'(z_{l-1})
             GemmArgs h{};

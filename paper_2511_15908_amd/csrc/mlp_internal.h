@@ -50,7 +50,9 @@ struct Residual {
 void launch_loss(hipStream_t s, const float *out, const float *Y, uint32_t m, uint32_t n_out, const float *mu,
                  const float *sd, const Residual &res, uint16_t *dout, double *partials, uint32_t nblk, double *loss);
 uint32_t loss_blocks(uint32_t m);
-void launch_bias_grad(hipStream_t s, const uint16_t *dz, uint32_t m, uint32_t n, uint32_t ld, float *db);
+// db = column sums of dz (m rows); part: scratch of ceil(m / 128) * n floats.
+void launch_bias_grad(hipStream_t s, const uint16_t *dz, uint32_t m, uint32_t n, uint32_t ld, float *db,
+                      float *part);
 void launch_adam(hipStream_t s, float *w, float *m1, float *m2, const float *g, uint16_t *wb, uint32_t count,
                  float lr, float beta1, float beta2, float eps, float bc1, float bc2);
 void launch_to_bf16(hipStream_t s, const float *w, uint16_t *wb, uint32_t count);

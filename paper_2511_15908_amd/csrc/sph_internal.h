@@ -200,14 +200,13 @@ __device__ __forceinline__ double grid_R2<double>(const Grid &g) { return g.R2_6
 // EXACT = true (FP64 runs): r = sqrt(r^2) in binary64, so the density is good
 // to a few ulps and the pressure the force pass sees to ~1e-12 relative.
 template <bool EXACT>
-__device__ __forceinline__ double spline_shape64(double dx, double dy, double dz, double inv_h)
+__device__ __forceinline__ double spline_r2(double r2, double inv_h)
 {
-    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     double r;
     if constexpr (EXACT) {
         r = sqrt(r2);
     } else {
-        const double y = (double)frsqrt((float)fmax(r2, 1e-30));
+        const double y = (double)frsqrt(fmaxf((float)r2, 1e-30f));
         r = r2 * y;
         r = fma(0.5 * y, fma(-r, r, r2), r);
     }
@@ -215,6 +214,12 @@ __device__ __forceinline__ double spline_shape64(double dx, double dy, double dz
     const double t2 = fmax(2.0 - q, 0.0);
     const double t1 = fmax(1.0 - q, 0.0);
     return fma(t2 * t2, t2, -4.0 * (t1 * (t1 * t1)));
+}
+
+template <bool EXACT>
+__device__ __forceinline__ double spline_shape64(double dx, double dy, double dz, double inv_h)
+{
+    return spline_r2<EXACT>(fma(dz, dz, fma(dy, dy, dx * dx)), inv_h);
 }
 
 // Kernel value W(|c - me|) in FP64 (exact square root in FP64 runs).
