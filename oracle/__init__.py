@@ -25,7 +25,7 @@ _SRC = _HERE / "sph_oracle.c"
 _LIB = _HERE / "_build" / "liboracle.so"
 
 FLUID, SOFT, BOUNDARY = 0, 1, 2
-CLAMP_NEG_PRESSURE, BOUNDARY_SINGLE_TERM, NO_BOUNDARY_VISCOSITY = 1, 2, 4
+CLAMP_NEG_PRESSURE, BOUNDARY_SINGLE_TERM, NO_BOUNDARY_VISCOSITY, UNIFIED_BOUNDARY = 1, 2, 4, 8
 
 
 def build(force: bool = True) -> Path:
@@ -357,6 +357,7 @@ class Oracle:
             self.pose[o] = [p0[:3].copy(), q, np.zeros(3), np.zeros(3)]
         self.psi = round_to(self._psi(), self.prec).copy()
         self.K = int(self.params.get("smoothing_window", 20))
+        self.unified = bool(int(self.params.get("flags", 0)) & UNIFIED_BOUNDARY)
         self.samples = {o: [] for o in self.kin}
         self.nsteps = 0
 
@@ -454,8 +455,11 @@ class Oracle:
         rho_full = np.zeros(self.n)
         p_full = np.zeros(self.n)
         sub = lambda idx: (counts[idx], offs[idx], ids)   # noqa: E731
-        r, p = self.density(mov, sub(mov))
-        rho_full[mov], p_full[mov] = r, p
+        # unified reading: boundary particles carry their own density and
+        # pressure (Eq. density with psi_b as their mass)
+        dens_t = np.arange(self.n) if self.unified else mov
+        r, p = self.density(dens_t, sub(dens_t))
+        rho_full[dens_t], p_full[dens_t] = r, p
         kin_b = np.nonzero((self.type == BOUNDARY) & np.isin(self.obj, self.kin))[0]
         tg = np.concatenate([mov, kin_b])
         f_t = self.forces(tg, sub(tg), rho_full, p_full, fspring)
@@ -501,7 +505,7 @@ class Oracle:
         mark[targets] = True
         mark[nb_t[2]] = True
         union = np.nonzero(mark)[0]
-        union_mov = union[self.type[union] != BOUNDARY]
+        union_mov = union if self.unified else union[self.type[union] != BOUNDARY]
         nb_u = neighbors(self.params, self.prec, self.x, union_mov)
         rho_full = np.zeros(self.n)
         p_full = np.zeros(self.n)

@@ -38,6 +38,7 @@
 #define ORC_CLAMP_NEG_PRESSURE 1u
 #define ORC_BOUNDARY_SINGLE_TERM 2u
 #define ORC_NO_BOUNDARY_VISCOSITY 4u
+#define ORC_UNIFIED_BOUNDARY 8u
 
 typedef struct {
     int32_t precision; /* 0: decisions in binary32, 1: decisions in binary64 */
@@ -609,6 +610,9 @@ void orc_springs(int64_t n, const double *x, const double *v, int64_t ns, const 
 /*   j fluid/soft: -m_i m_j (p_i/rho_i^2 + p_j/rho_j^2) gradW_ij         */
 /*                 + 2 nu m_i m_j [2/(rho_i+rho_j)] (x_ij.gradW)/(r^2+eps) v_ij */
 /*   j boundary b: the same with m_j = psi_b, p_j = p_i, rho_j = rho_i   */
+/*   (pressure mirrored into the boundary particle); with the unified   */
+/*   reading (every typed particle an SPH particle, Sec. 3.2) the same   */
+/*   with m_j = psi_b and the boundary particle's own rho_b and p_b.      */
 /* gradW_ij = dW/dr(r) x_ij / r (0 at r = 0).                           */
 /* ------------------------------------------------------------------ */
 
@@ -626,7 +630,14 @@ static void pair_force(const orc_params *p, int64_t i, int64_t j, const double *
     double vij[3] = {v[3 * i] - v[3 * j], v[3 * i + 1] - v[3 * j + 1], v[3 * i + 2] - v[3 * j + 2]};
     double xg = d[0] * gw[0] + d[1] * gw[1] + d[2] * gw[2];
     double mi = mass[i];
-    if (type[j] == ORC_BOUNDARY) {
+    if (type[j] == ORC_BOUNDARY && (p->flags & ORC_UNIFIED_BOUNDARY)) {
+        double mj = psi[j];
+        double pterm = pi / (rhoi * rhoi) + pj / (rhoj * rhoj);
+        double visc = (p->flags & ORC_NO_BOUNDARY_VISCOSITY)
+                          ? 0.0
+                          : 2.0 * p->nu * mi * mj * (2.0 / (rhoi + rhoj)) * xg / (r * r + eps);
+        for (int a = 0; a < 3; ++a) out[a] = -mi * mj * pterm * gw[a] + visc * vij[a];
+    } else if (type[j] == ORC_BOUNDARY) {
         double psib = psi[j];
         double pterm = (p->flags & ORC_BOUNDARY_SINGLE_TERM) ? pi / (rhoi * rhoi) : 2.0 * pi / (rhoi * rhoi);
         double visc = (p->flags & ORC_NO_BOUNDARY_VISCOSITY) ? 0.0 : 2.0 * p->nu * mi * psib * (1.0 / rhoi) * xg / (r * r + eps);

@@ -441,6 +441,67 @@ def test_flat_wall_boundary_viscosity(orc, z_over_s):
     assert np.all(F[:, 1:] == 0.0)
 
 
+def test_unified_boundary_reading(orc):
+    """UNIFIED_BOUNDARY (every typed particle an SPH particle, Sec. 3.2): a
+    boundary particle carries its own density and pressure, with psi_b as
+    its mass.  (a) With its own rho_b, p_b equal to the fluid particle's, the
+    wall's force equals the mirrored one (pinned against the in-plane
+    integral above), and with p_b = 0 the pressure part halves; (b) the
+    centre of a flat single-layer wall alone reads exactly rho0 (its psi_b
+    was made from the same kernel sum); (c) the fluid-side density does not
+    change."""
+    S = 0.25
+    wall = _wall_sites(S)
+    nw = wall.shape[0]
+    psi_b = 2.857 * 1000.0 * S ** 3
+    mi, rhoi, pi_ = 1000.0 * S ** 3, 1100.0, 300.0
+    xi = np.array([[0.3 * S, -0.2 * S, 1.1 * S]])
+    x = np.concatenate([wall, xi])
+    n = nw + 1
+    typ = np.zeros(n, np.uint8)
+    typ[:nw] = 2
+    psi = np.zeros(n)
+    psi[:nw] = psi_b
+    mass = np.full(n, 7.0)
+    mass[nw] = mi
+    v = np.zeros_like(x)
+    v[:nw, 0] = 0.3
+    U = orc.UNIFIED_BOUNDARY
+    for nu in (0.0, 0.7):
+        rho_m = np.full(n, 555.0)
+        rho_m[nw] = rhoi
+        p_m = np.full(n, -999.0)
+        p_m[nw] = pi_
+        f_mirror = orc.forces(_wall_params(S, nu=nu), "f64", x, v, mass, typ, psi, rho_m, p_m, None, [nw])[0]
+        rho_u = np.full(n, rhoi)
+        p_u = np.full(n, pi_)
+        f_unified = orc.forces(_wall_params(S, nu=nu, flags=U), "f64", x, v, mass, typ, psi, rho_u, p_u, None,
+                               [nw])[0]
+        assert np.allclose(f_unified, f_mirror, rtol=1e-14, atol=1e-14 * np.abs(f_mirror).max())
+        # the unified pair reads the boundary particle's own values: mirrored
+        # values in the boundary entries change the result
+        f_other = orc.forces(_wall_params(S, nu=nu, flags=U), "f64", x, v, mass, typ, psi, rho_m, p_m, None,
+                             [nw])[0]
+        assert not np.allclose(f_other, f_unified)
+    p0 = np.full(n, 0.0)
+    p0[nw] = pi_
+    half = orc.forces(_wall_params(S, flags=U), "f64", x, np.zeros_like(x), mass, typ, psi, rho_u, p0, None, [nw])[0]
+    full = orc.forces(_wall_params(S, flags=U), "f64", x, np.zeros_like(x), mass, typ, psi, rho_u, p_u, None, [nw])[0]
+    assert np.allclose(half, 0.5 * full, rtol=1e-14, atol=1e-14 * np.abs(full).max())
+    # (b) the wall's own density: psi_b of every wall particle from its own
+    # in-plane kernel sum, so the centre reads rho0 (wall alone)
+    P = _wall_params(S)
+    tw = np.full(nw, 2, np.uint8)
+    psi_w = orc.boundary_psi(P, "f64", wall, tw, np.zeros(nw, np.int32))
+    c = int(np.argmin(np.linalg.norm(wall, axis=1)))
+    rho_c, _ = orc.density(P, "f64", wall, np.full(nw, 123.0), tw, psi_w, [c])
+    assert rho_c[0] == pytest.approx(1000.0, rel=1e-13)
+    # (c) the fluid particle's density is the same with or without the flag
+    r0, _ = orc.density(_wall_params(S), "f64", x, mass, typ, psi, [nw])
+    r1, _ = orc.density(_wall_params(S, flags=U), "f64", x, mass, typ, psi, [nw])
+    assert r0[0] == r1[0]
+
+
 def test_body_place_rigid_velocity(orc):
     """Placement of a rigid body's particles (Sec. 3.2, constant body-frame
     offsets): x_b = c + R(q) r_loc and v_b = v + w x (x_b - c), worked by hand
