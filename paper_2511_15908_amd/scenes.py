@@ -319,6 +319,29 @@ def stirring_tank(seed: int = 2, n_fluid: int = 250_000, precision: str = "f32")
                      info={"body": 1, "phase": phase, "amplitude": 0.1, "freq": 1.0, "c0": c0})
 
 
+# Soft cube material: a Young's modulus of 5e4 Pa.  Equal central springs on
+# the 6 axis and 12 face-diagonal lattice neighbours give an isotropic solid
+# with lambda = mu = k_s / s (Cauchy relation), i.e. E = 2.5 k_s / s and a
+# Poisson ratio of exactly 1/4 (a ratio of 0.3 cannot be reached with central
+# springs); matching E gives k_s = 0.4 E s = 100 N/m at s = 5 mm.
+SOFT_E = 5e4
+
+
+def coupled_soft_cube(s: float, g: float = 1.0):
+    """The coupled scene's 20^3 soft cube at lattice spacing s: its lattice
+    indices, positions, spring pairs (indices into the cube) and per-spring
+    rest length, stiffness and damping (damping ratio about 0.1 at mass
+    rho0 s^3)."""
+    ijk = _grid(11, 30, 41, 60, 1, 20)
+    pos = (ijk.astype(np.float64) + (g - 1.0)) * s
+    m = 1000.0 * s ** 3
+    ij = soft_cube_springs(ijk)
+    L0 = np.linalg.norm(pos[ij[:, 0]] - pos[ij[:, 1]], axis=1)
+    ks = 0.4 * SOFT_E * s                  # 100 N/m at s = 5 mm
+    cs = 0.1 * 2.0 * math.sqrt(ks * m)
+    return ijk, pos, ij, L0, np.full(len(L0), ks), np.full(len(L0), cs)
+
+
 def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") -> Scene:
     """Coupled fluid + soft + rigid: 100 x 100 fluid columns at spacing 5 mm in
     an open tank of about 0.51 x 0.51 x 0.6 m, a 20^3 soft cube on the fluid
@@ -329,7 +352,7 @@ def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") 
     g = WALL_GAP
     W = tank_width(100, s)
     tank = open_tank(W, W, 120, s)
-    soft_ijk = _grid(11, 30, 41, 60, 1, 20)
+    soft_ijk, soft, ij, L0, ks, cs = coupled_soft_cube(s, g)
     occ = set(map(tuple, soft_ijk.tolist()))
     c0 = np.array([0.30, 0.25, 0.25])
     R = 0.05
@@ -338,12 +361,7 @@ def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") 
     sph = np.concatenate(shells, 0)
     fl = (fill_to_count(n_fluid, (1, 100), (1, 100), s, occ, clearance(sph, OBSTACLE_CLEARANCE * s), gap=g)
           .astype(np.float64) + (g - 1.0)) * s
-    soft = (soft_ijk.astype(np.float64) + (g - 1.0)) * s
     m = 1000.0 * s ** 3
-    ij = soft_cube_springs(soft_ijk)
-    L0 = np.linalg.norm(soft[ij[:, 0]] - soft[ij[:, 1]], axis=1)
-    ks = 100.0
-    cs = 0.1 * 2.0 * math.sqrt(ks * m)
     nf = fl.shape[0]
     ij_glob = ij + nf                       # soft particles follow the fluid
     lo = (-0.5 * s, -0.5 * s, -0.5 * s)
@@ -354,7 +372,7 @@ def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") 
                      [(fl, FLUID, -1, m), (soft, SOFT, -1, m), (tank, BOUNDARY, 0, 0.0),
                       (sph, BOUNDARY, 1, 0.0)],
                      kin=[0, 1], poses=poses,
-                     springs=(ij_glob, L0, np.full(len(L0), ks), np.full(len(L0), cs)),
+                     springs=(ij_glob, L0, ks, cs),
                      info={"body": 1, "radius": R, "c0": c0})
 
 

@@ -572,6 +572,85 @@ def test_archimedes_submerged_fixed_cube(orc):
     assert sp.max() < 0.1
 
 
+# ---------------------------------------------------------------- soft-body elasticity (Sec. 3.2)
+
+def _cube_traction(orc, strain, axis, s=0.005):
+    """Stress component sigma[:, axis] of the coupled scene's soft cube under
+    the affine small strain `strain` (3x3, symmetric), from the spring forces
+    across the mid-plane normal to `axis`: only springs whose lower end lies in
+    an interior column count (each such column has the 5 crossing springs of
+    the bulk), and the force they put on the far side is -sigma . e_axis times
+    the columns' area s^2 each."""
+    from paper_2511_15908_amd import scenes
+    ijk, pos, ij, L0, ks, cs = scenes.coupled_soft_cube(s)
+    ctr = pos.mean(0)
+    x = ctr + (pos - ctr) @ (np.eye(3) + strain).T
+    lo, hi = ijk.min(0), ijk.max(0)
+    mid = (lo[axis] + hi[axis]) // 2
+    a, b = ijk[ij[:, 0]], ijk[ij[:, 1]]
+    lower = np.where((a[:, axis] <= b[:, axis])[:, None], a, b)
+    cross = (np.minimum(a[:, axis], b[:, axis]) == mid) & (np.maximum(a[:, axis], b[:, axis]) == mid + 1)
+    others = [d for d in range(3) if d != axis]
+    inner = np.ones(len(ij), bool)
+    for d in others:
+        inner &= (lower[:, d] > lo[d]) & (lower[:, d] < hi[d])
+    sel = cross & inner
+    ncol = int(np.prod([hi[d] - lo[d] - 1 for d in others]))
+    assert sel.sum() == 5 * ncol
+    f = orc.springs(len(pos), x, np.zeros_like(x), ij[sel], L0[sel], ks[sel], cs[sel])
+    far = ijk[:, axis] > mid
+    return -f[far].sum(0) / (ncol * s * s), float(ks[0])
+
+
+def test_soft_cube_uniaxial_stress(orc):
+    """The soft cube's spring lattice as an elastic solid (Sec. 3.2 mass-spring
+    model): under axial strain e with lateral strain -e/4 the axial stress is
+    E e with E = 2.5 k_s / s (5e4 Pa at k_s = 100 N/m, s = 5 mm) and the
+    lateral stress vanishes (Poisson ratio 1/4).  Closed form: with k_s on the
+    3 axis springs (length s) and 6 face diagonals (length s sqrt 2) of each
+    site, C_11 = 3 k_s/s and C_12 = C_44 = k_s/s, so lambda = mu = k_s/s."""
+    e = 1e-6
+    strain = np.diag([e, -e / 4, -e / 4])
+    sx, ks = _cube_traction(orc, strain, 0)
+    sy, _ = _cube_traction(orc, strain, 1)
+    sz, _ = _cube_traction(orc, strain, 2)
+    from paper_2511_15908_amd import scenes
+    assert 2.5 * ks / 0.005 == pytest.approx(scenes.SOFT_E, rel=1e-12)
+    assert sx[0] == pytest.approx(scenes.SOFT_E * e, rel=1e-5)
+    assert abs(sy[1]) < 1e-5 * sx[0] and abs(sz[2]) < 1e-5 * sx[0]
+    assert np.abs([sx[1], sx[2], sy[0], sy[2], sz[0], sz[1]]).max() < 1e-5 * sx[0]   # no shear
+
+
+def test_soft_cube_shear_and_rest(orc):
+    """Simple shear gamma in the xy plane gives sigma_xy = mu gamma with
+    mu = k_s / s = E / (2 (1 + 1/4)); the undeformed lattice is stress free,
+    and under an affine strain every interior site is in equilibrium (the
+    table holds all 18 springs of a bulk site)."""
+    from paper_2511_15908_amd import scenes
+    gam = 1e-6
+    strain = np.zeros((3, 3))
+    strain[0, 1] = strain[1, 0] = gam / 2
+    sx, ks = _cube_traction(orc, strain, 0)
+    sy, _ = _cube_traction(orc, strain, 1)
+    mu = scenes.SOFT_E / 2.5
+    assert sx[1] == pytest.approx(mu * gam, rel=1e-5)
+    assert sy[0] == pytest.approx(mu * gam, rel=1e-5)
+    assert abs(sx[0]) < 1e-5 * mu * gam
+    s0, _ = _cube_traction(orc, np.zeros((3, 3)), 2)
+    assert np.abs(s0).max() < 1e-9 * mu * gam
+    ijk, pos, ij, L0, ksv, csv = scenes.coupled_soft_cube(0.005)
+    st = np.diag([1e-6, -3e-7, 2e-7]) + strain
+    x = pos.mean(0) + (pos - pos.mean(0)) @ (np.eye(3) + st).T
+    f = orc.springs(len(pos), x, np.zeros_like(x), ij, L0, ksv, csv)
+    deg = np.bincount(ij.ravel(), minlength=len(pos))
+    lo, hi = ijk.min(0), ijk.max(0)
+    interior = np.all((ijk > lo) & (ijk < hi), axis=1)
+    assert (deg[interior] == 18).all()
+    scale = ksv[0] * 0.005 * 1e-6
+    assert np.abs(f[interior]).max() < 1e-6 * scale
+    assert np.abs(f[~interior]).max() > 0.1 * scale           # the free surface is loaded
+
+
 # ---------------------------------------------------------------- rigid body, wrench, integrator
 
 def test_quaternion_rotation(orc):
