@@ -63,14 +63,19 @@ enum { SPH_FLUID = 0, SPH_SOFT = 1, SPH_BOUNDARY = 2 };
 enum {
     SPH_FLAG_CLAMP_NEG_PRESSURE = 1u,   /* p = max(k (rho - rho0), 0) instead of Eq. pressure as printed */
     SPH_FLAG_BOUNDARY_SINGLE_TERM = 2u, /* fluid-boundary pressure term p_i/rho_i^2 once, not mirrored */
-    SPH_FLAG_NO_BOUNDARY_VISCOSITY = 4u /* no viscosity between fluid/soft and boundary particles */
+    SPH_FLAG_NO_BOUNDARY_VISCOSITY = 4u, /* no viscosity between fluid/soft and boundary particles */
+    SPH_FLAG_UNIFIED_BOUNDARY = 8u       /* Sec. 3.2 typed particles: a boundary particle is an SPH particle
+                                            with mass psi_b and a density and pressure of its own (Eq.
+                                            density over all neighbours, Eq. pressure); the pair force then
+                                            uses rho_b, p_b instead of the mirrored rho_i, p_i.  Flag 2 has
+                                            no effect under it.  sph_read_field reports boundary rho and p. */
 };
 
 /* Fields readable with sph_read_field, all in original particle-id order. */
 enum {
     SPH_FIELD_X = 0,        /* double[3n] positions after the last step (or init) */
     SPH_FIELD_V = 1,        /* double[3n] velocities after the last step (or init) */
-    SPH_FIELD_RHO = 2,      /* double[n] density of the last step (fluid/soft; 0 for boundary) */
+    SPH_FIELD_RHO = 2,      /* double[n] density of the last step (fluid/soft; boundary 0, own rho_b with flag 8) */
     SPH_FIELD_PRESSURE = 3, /* double[n] pressure p = k (rho - rho0) of the last step */
     SPH_FIELD_FORCE = 4,    /* double[3n] total force of the last step: pair forces + m g + springs
                                (fluid/soft); reaction force of kinematic boundary particles; 0 static */

@@ -20,7 +20,8 @@ SPH_ABI_VERSION = 1
 SPH_STATIC_WORKSPACE_BYTES = 128 << 20
 SPH_FP32, SPH_FP64 = 0, 1
 SPH_FLUID, SPH_SOFT, SPH_BOUNDARY = 0, 1, 2
-SPH_FLAG_CLAMP_NEG_PRESSURE, SPH_FLAG_BOUNDARY_SINGLE_TERM, SPH_FLAG_NO_BOUNDARY_VISCOSITY = 1, 2, 4
+(SPH_FLAG_CLAMP_NEG_PRESSURE, SPH_FLAG_BOUNDARY_SINGLE_TERM, SPH_FLAG_NO_BOUNDARY_VISCOSITY,
+ SPH_FLAG_UNIFIED_BOUNDARY) = 1, 2, 4, 8
 (SPH_FIELD_X, SPH_FIELD_V, SPH_FIELD_RHO, SPH_FIELD_PRESSURE, SPH_FIELD_FORCE, SPH_FIELD_PSI,
  SPH_FIELD_KEY, SPH_FIELD_SPRING) = range(8)
 FIELD_NAMES = {"x": SPH_FIELD_X, "v": SPH_FIELD_V, "rho": SPH_FIELD_RHO, "p": SPH_FIELD_PRESSURE,

@@ -472,6 +472,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
     const SceneC<T> &scn = b.sc[scene_of_slot(b, slot)];
     const Grid g = scn.g;
     const Phys<T> ph = scn.ph;
+    // unified boundary reading: boundary particles have a density of their own
+    const bool unified = (ph.flags & 8u) != 0u;
     if (!load_nbhd(slot - g.slot0, g, cstart, cend, nb, lane)) {
         if (lane == 0) atomicOr(err, ERR_CAPACITY);
         return;
@@ -502,15 +504,16 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         // a pass with at most 32 targets is split: two or four lanes per
         // target (no lane then serves the cell's static boundary particles,
         // whose density and force the reorder has already set to 0)
-        const SplitPass sp = split_pass(act && (aux_type(aux) != TY_BOUNDARY || aux_kin(aux)), with_left, lane,
-                                        t0, e0, s0, st.aux, tmap, p, act, pc, aux);
+        const SplitPass sp = split_pass(act && (aux_type(aux) != TY_BOUNDARY || aux_kin(aux) || unified), with_left,
+                                        lane, t0, e0, s0, st.aux, tmap, p, act, pc, aux);
         V4<T> me = st.pos[pc];
         me.x = act ? me.x : inf;
         me.y = act ? me.y : inf;
         me.z = act ? me.z : inf;
         const double mx = (double)me.x, my = (double)me.y, mz = (double)me.z;
         const bool fs = act && aux_type(aux) != TY_BOUNDARY;
-        const bool want = act && (fs || aux_kin(aux));
+        const bool dn = fs || (act && unified);        // lanes whose density is summed
+        const bool want = act && (dn || aux_kin(aux));
         const bool lanes_any = __ballot(want) != 0ull;
         if (!lanes_any && !with_left) continue;
         if (with_left && lane < nleft) accl[lane] = 0.0;
@@ -599,7 +602,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                         if (act && sp.lead) masks[(size_t)(w0 + q) * n + p] = m;
                         npair += (want && sp.lead) ? (uint32_t)__popcll(m) : 0u;
                     }
-                    mw[q] = fs ? (m & sp.bits) : 0ull;
+                    mw[q] = dn ? (m & sp.bits) : 0ull;
                 }
                 {
                     uint32_t mine = 0;
@@ -635,7 +638,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                     const uint32_t pt = left0 + t;
                     const uint32_t at = st.aux[pt];
                     const bool fs_t = aux_type(at) != TY_BOUNDARY;
-                    if (!fs_t && !aux_kin(at)) continue;    // uniform: static boundary
+                    const bool dn_t = fs_t || unified;
+                    if (!dn_t && !aux_kin(at)) continue;    // uniform: static boundary
                     const V4<T> mt = st.pos[pt];
                     const double tx = (double)mt.x, ty = (double)mt.y, tz = (double)mt.z;
                     double part = 0.0;
@@ -648,8 +652,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                             if (lane == 0) masks[(size_t)(w0 + q) * n + pt] = m;
                             const uint32_t cnt = (uint32_t)__popcll(m);
                             nleftpair_f += cnt;
-                            nleftpair_d += fs_t ? cnt : 0u;
-                            if (fs_t && hit) {
+                            nleftpair_d += dn_t ? cnt : 0u;
+                            if (dn_t && hit) {
                                 const Cand64 c64 = cand64[q * kWave + lane];
                                 part = fma(c64.m, spline_shape64<sizeof(T) == 8>(c64.x - tx, c64.y - ty, c64.z - tz, ph.inv_h64),
                                            part);
@@ -665,7 +669,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         {
             // step statistics: neighbour pairs of density targets, of force
             // targets, candidate tests, wavefronts, loop iterations
-            uint32_t nd = fs ? npair : 0u, nf = npair;
+            uint32_t nd = dn ? npair : 0u, nf = npair;
             nd = wave_sum_u32(nd);
             nf = wave_sum_u32(nf);
             if (lane == 0) {
@@ -679,7 +683,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         if (sp.split) acc = split_sum(acc, sp);
         if (act && sp.lead) {
             V2<T> d{(T)0, (T)0};
-            if (fs) {
+            if (dn) {
                 const double rho = ph.alpha6_64 * acc;
                 double pr = ph.kp * (rho - ph.rho0);
                 if ((ph.flags & 1u) && pr < 0.0) pr = 0.0;
@@ -690,9 +694,9 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
         }
         if (with_left && lane < nleft) {
             const uint32_t pt = left0 + lane;
-            const bool fs_t = aux_type(st.aux[pt]) != TY_BOUNDARY;
+            const bool dn_t = aux_type(st.aux[pt]) != TY_BOUNDARY || unified;
             V2<T> d{(T)0, (T)0};
-            if (fs_t) {
+            if (dn_t) {
                 const double rho = ph.alpha6_64 * accl[lane];
                 double pr = ph.kp * (rho - ph.rho0);
                 if ((ph.flags & 1u) && pr < 0.0) pr = 0.0;
@@ -719,10 +723,13 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
 // is the exact IEEE negation.
 // P_mir is the pressure a boundary partner takes from this particle: P_a,
 // or 0 with the single-boundary-term flag.  KIN = false: particle a is not a
-// boundary particle; PLAIN: neither boundary flag (2, 4) is set.
+// boundary particle; PLAIN: neither boundary flag (2, 4) is set.  With the
+// unified reading (flag 8) a boundary particle keeps its own density and
+// pressure: its staged mirror factor cv.w is 0 and a boundary target does not
+// take its partner's values either (mirror = false).
 template <typename T, bool KIN, bool PLAIN>
 __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T rho_a, T P_a, T P_mir, bool isBa,
-                                           T ma, const V4<T> &c, const V4<T> &cv, const V2<T> &cd,
+                                           bool mirror, T ma, const V4<T> &c, const V4<T> &cv, const V2<T> &cd,
                                            const Phys<T> &ph, T &fx, T &fy, T &fz)
 {
     const T dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
@@ -732,17 +739,18 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
     const T t1 = max((T)1 - q, (T)0);
     const T t2 = max((T)2 - q, (T)0);
     const T g = ((ph.gch * fma((T)2, t1, -t2)) * fma((T)2, t1, t2)) * rs;
-    // cv.w is 1 for a boundary candidate (0 otherwise), whose staged density
-    // and pressure term are 0: the mirrored values enter by one FMA each
-    const bool isBc = cv.w != (T)0;
+    // cv.w is 1 for a mirrored boundary candidate (0 otherwise), whose staged
+    // density and pressure term are 0: the mirrored values enter by one FMA
+    // each; boundary candidates carry -psi_b in c.w
+    const bool isBc = c.w < (T)0;
     const T mc = fabs(c.w);
     const T Pc = fma(cv.w, P_mir, cd.y);
     const T rc = fma(cv.w, rho_a, cd.x);
     T Pa = P_a, ra = rho_a;
     if (KIN) {
         const T Pb = (!PLAIN && (ph.flags & 2u)) ? (T)0 : cd.y;
-        Pa = isBa ? Pb : P_a;
-        ra = isBa ? cd.x : rho_a;
+        Pa = (isBa && mirror) ? Pb : P_a;
+        ra = (isBa && mirror) ? cd.x : rho_a;
     }
     const T mm = ma * mc;
     T sp = -(mm * (Pa + Pc)) * g;
@@ -769,7 +777,7 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
 // ONE: the staged super-chunk fits one word (no word moves).
 template <typename T, bool KIN, bool PLAIN, bool ONE>
 __device__ __forceinline__ void walk_forces(uint64_t (&mw)[kScWords], const V4<T> &me, const V4<T> &mv,
-                                            const V2<T> &md, T P_mir, bool kin, T ma, const V4<T> *cp,
+                                            const V2<T> &md, T P_mir, bool kin, bool mirror, T ma, const V4<T> *cp,
                                             const V4<T> *cvel, const V2<T> *cden, const Phys<T> &ph, T &cx, T &cy,
                                             T &cz)
 {
@@ -778,7 +786,8 @@ __device__ __forceinline__ void walk_forces(uint64_t (&mw)[kScWords], const V4<T
         while (m) {
             const int k = (int)__builtin_ctzll(m);
             m &= m - 1ull;
-            pair_force<T, KIN, PLAIN>(me, mv, md.x, md.y, P_mir, kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
+            pair_force<T, KIN, PLAIN>(me, mv, md.x, md.y, P_mir, kin, mirror, ma, cp[k], cvel[k], cden[k], ph, cx, cy,
+                                      cz);
         }
         return;
     }
@@ -787,7 +796,7 @@ __device__ __forceinline__ void walk_forces(uint64_t (&mw)[kScWords], const V4<T
         skip_empty_word(mw, base);
         if (mw[0] == 0ull) break;
         const int k = take_hit(mw, base);
-        pair_force<T, KIN, PLAIN>(me, mv, md.x, md.y, P_mir, kin, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
+        pair_force<T, KIN, PLAIN>(me, mv, md.x, md.y, P_mir, kin, mirror, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
     }
 }
 
@@ -838,6 +847,7 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
     const SceneC<T> &scn = b.sc[scene_of_slot(b, slot)];
     const Grid g = scn.g;
     const Phys<T> ph = scn.ph;
+    const bool mirror = (ph.flags & 8u) == 0u;    // pressure mirroring (not the unified reading)
     if (!load_nbhd(slot - g.slot0, g, cstart, cend, nb, lane)) return;   // flagged by the density pass
     const uint32_t S = nb.stride;
     const float invS = 1.0f / (float)S;
@@ -912,7 +922,7 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                     const uint32_t o = size + lanes_below(km, lane);
                     cp[o] = c;
                     V4<T> cv = st.vel[j];
-                    cv.w = c.w < (T)0 ? (T)1 : (T)0;    // boundary flag for the pair loop
+                    cv.w = (mirror && c.w < (T)0) ? (T)1 : (T)0;    // mirror factor for the pair loop
                     cvel[o] = cv;
                     cden[o] = dens[j];
                 }
@@ -943,16 +953,18 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                 const bool one = size <= (uint32_t)kWave;
                 if (wave_kin || (ph.flags & 6u)) {
                     if (one)
-                        walk_forces<T, true, false, true>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
+                        walk_forces<T, true, false, true>(mw, me, mv, md, P_mir, kin, mirror, ma, cp, cvel, cden, ph,
+                                                          cx, cy, cz);
                     else
-                        walk_forces<T, true, false, false>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy,
-                                                           cz);
+                        walk_forces<T, true, false, false>(mw, me, mv, md, P_mir, kin, mirror, ma, cp, cvel, cden, ph,
+                                                           cx, cy, cz);
                 } else {
                     if (one)
-                        walk_forces<T, false, true, true>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy, cz);
+                        walk_forces<T, false, true, true>(mw, me, mv, md, P_mir, kin, mirror, ma, cp, cvel, cden, ph,
+                                                          cx, cy, cz);
                     else
-                        walk_forces<T, false, true, false>(mw, me, mv, md, P_mir, kin, ma, cp, cvel, cden, ph, cx, cy,
-                                                           cz);
+                        walk_forces<T, false, true, false>(mw, me, mv, md, P_mir, kin, mirror, ma, cp, cvel, cden, ph,
+                                                           cx, cy, cz);
                 }
                 fx += (double)cx;
                 fy += (double)cy;
@@ -976,8 +988,8 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                             const uint32_t v = q * kWave + lane;
                             if ((m >> lane) & 1ull)
                                 pair_force<T, true, false>(mt, mvt, mdt.x, mdt.y, (ph.flags & 2u) ? (T)0 : mdt.y,
-                                                           kin_t, fabs(mt.w), cp[v], cvel[v], cden[v], ph, cx, cy,
-                                                           cz);
+                                                           kin_t, mirror, fabs(mt.w), cp[v], cvel[v], cden[v], ph,
+                                                           cx, cy, cz);
                         }
                     }
                     cx = wave_reduce(cx, (T)0, OpAdd{});

@@ -233,7 +233,7 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
         why = "precision must be SPH_FP32 or SPH_FP64";
         return SPH_ERR_ARG;
     }
-    if (p->flags & ~7u) {
+    if (p->flags & ~15u) {
         why = "unknown flag bits";
         return SPH_ERR_UNSUPPORTED;
     }
@@ -1475,12 +1475,16 @@ sph_status read_field_t(sph_ctx *c, int field, void *dst, size_t bytes)
             }
             break;
         case SPH_FIELD_RHO:
-            d[i] = bnd ? 0.0 : (double)v2[p].x;
-            break;
         case SPH_FIELD_PRESSURE: {
-            double pr = bnd ? 0.0 : c->prm.k_pressure * ((double)v2[p].x - c->prm.rho0);
-            if ((c->prm.flags & SPH_FLAG_CLAMP_NEG_PRESSURE) && pr < 0) pr = 0;
-            d[i] = pr;
+            // the parameters of the particle's own scene
+            const uint32_t k =
+                (uint32_t)(std::upper_bound(c->part0.begin(), c->part0.end(), i) - c->part0.begin()) - 1u;
+            const sph_params &pk = c->prms[k];
+            const bool has = !bnd || (pk.flags & SPH_FLAG_UNIFIED_BOUNDARY);
+            const double rho = has ? (double)v2[p].x : 0.0;
+            double pr = has ? pk.k_pressure * (rho - pk.rho0) : 0.0;
+            if ((pk.flags & SPH_FLAG_CLAMP_NEG_PRESSURE) && pr < 0) pr = 0;
+            d[i] = field == SPH_FIELD_RHO ? rho : pr;
             break;
         }
         case SPH_FIELD_PSI:

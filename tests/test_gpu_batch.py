@@ -60,6 +60,32 @@ def test_batch_equals_one_context_per_scene(gpu, prec):
         assert np.array_equal(F, F1) and np.array_equal(T, T1)
 
 
+def test_batch_mixed_readings(gpu):
+    """Scenes of one batch with their own readings and pressure constants:
+    every field, density and pressure included, equals one context per
+    scene bit for bit."""
+    scs = _mixed("f64")
+    for sc, fl, kf in zip(scs, [8, 0, 9, 12, 1], [1.0, 1.5, 0.8, 1.0, 2.0]):
+        sc.params["flags"] = fl
+        sc.params["k_pressure"] = kf * float(sc.params["k_pressure"])
+    batch = gpu.Sim(scs, precision="f64")
+    singles = [gpu.Sim(sc, precision="f64") for sc in scs]
+    for k in range(2):
+        for i, (sc, p) in enumerate(zip(scs, _poses(scs, k))):
+            batch.set_body_pose(int(batch.obj0[i]) + 1, *p)
+            singles[i].set_body_pose(1, *p)
+        batch.step(1)
+        for s in singles:
+            s.step(1)
+    for field in ("x", "v", "rho", "p", "f", "psi"):
+        whole = batch.read(field)
+        for i, s in enumerate(singles):
+            part = whole[batch.part0[i]:batch.part0[i + 1]]
+            assert np.array_equal(part, s.read(field)), (field, i)
+    bnd = scs[0].type == 2
+    assert (batch.read("rho")[:batch.part0[1]][bnd] > 0).all()     # unified: own boundary density
+
+
 def test_batch_parity_with_oracle(gpu, orc):
     """One FP32 step of a 5-scene batch against the oracle scene by scene:
     cell keys (minus the scene's key offset) and neighbour sets bit-exact,

@@ -146,10 +146,12 @@ def test_instability_flag(gpu):
     assert e.value.status == 5
 
 
-@pytest.mark.parametrize("flag", [1, 2, 4, 7])
+@pytest.mark.parametrize("flag", [1, 2, 4, 7, 8, 9, 12, 15])
 def test_reading_flags(gpu, orc, flag):
     """The alternative readings (clamped pressure, single boundary pressure
-    term, no boundary viscosity) match the oracle too."""
+    term, no boundary viscosity, boundary particles with a density and
+    pressure of their own) match the oracle too; with the last, the boundary
+    particles' density and pressure as well."""
     from paper_2511_15908_amd import scenes
     sc = scenes.small_scene(seed=51, precision="f64")
     sc.params["flags"] = flag
@@ -161,8 +163,11 @@ def test_reading_flags(gpu, orc, flag):
     o.set_pose(1, *pose)
     r = o.step()
     fs = np.nonzero(sc.type != 2)[0]
-    assert _cmp.rel_density(sim.read("rho")[fs], r["rho"][fs]) <= 1e-13
-    assert np.allclose(sim.read("p")[fs], r["p"][fs], rtol=1e-9, atol=1e-9)
+    dn = np.arange(sc.n) if flag & 8 else fs
+    assert _cmp.rel_density(sim.read("rho")[dn], r["rho"][dn]) <= 1e-13
+    assert np.allclose(sim.read("p")[dn], r["p"][dn], rtol=1e-9, atol=1e-9)
+    if not flag & 8:
+        assert not sim.read("rho")[sc.type == 2].any()
     mref = float(np.median(sc.mass[fs]))
     assert _cmp.rel_force(sim.read("f")[fs], r["f"][fs], mref * 9.81) <= 1e-12
     F, T = sim.wrench(1)
