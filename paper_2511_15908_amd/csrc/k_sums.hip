@@ -23,6 +23,8 @@
 //    density) and walks the stored masks, so no pair is tested twice; FP32
 //    terms summed per super-chunk, then in FP64.
 // No atomics in the sums, so results are bitwise reproducible.
+#include <algorithm>
+
 #include "sph_internal.h"
 
 namespace sphk {
@@ -52,13 +54,18 @@ struct Nbhd {
     uint32_t size[2];     // their candidate counts
 };
 
-// Blocks are dispatched round-robin over the 8 XCDs; give each XCD runs of 64
-// consecutive Morton cells so that neighbouring cells share an L2.
-__device__ __forceinline__ uint32_t cell_of_block(uint32_t b, uint32_t nslots)
+// The neighbour passes launch one workgroup per occupied cell (the cell
+// table lists them in slot order: Morton order within a scene, scenes one
+// after another); workgroups past the count exit at once.  Blocks are
+// dispatched round-robin over the 8 XCDs: within each full group of 512
+// cells every XCD gets a run of 64 consecutive cells, so that neighbouring
+// cells share its L2; the tail group keeps list order.
+__device__ __forceinline__ uint32_t list_pos(uint32_t i, uint32_t ncell)
 {
-    if (nslots < 512u) return b;
-    const uint32_t grp = b / 512u, r = b % 512u;
-    return grp * 512u + (r & 7u) * 64u + (r >> 3);
+    const uint32_t full = ncell & ~511u;
+    if (i >= full) return i;
+    const uint32_t grp = i >> 9, r = i & 511u;
+    return (grp << 9) + (r & 7u) * 64u + (r >> 3);
 }
 
 // --- cross-lane moves by DPP (gfx9): row_shr:n reads lane i - n of the same
@@ -458,15 +465,20 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                                                 const uint32_t *__restrict__ cstart,
                                                 const uint32_t *__restrict__ cend, V2<T> *__restrict__ dens,
                                                 uint64_t *__restrict__ masks, uint32_t *__restrict__ err,
-                                                unsigned long long *__restrict__ stats)
+                                                unsigned long long *__restrict__ stats,
+                                                const uint32_t *__restrict__ cells,
+                                                const uint32_t *__restrict__ n_occupied)
 {
     __shared__ Nbhd nb;
     __shared__ V4<T> cand[kScWords * kWave];         // tests: T positions, inf past the end
     __shared__ Cand64 cand64[kScWords * kWave];     // terms: FP64 positions and masses
     __shared__ double accl[kLeftD > 0 ? kLeftD : 1];
+    __shared__ unsigned long long cstat[5];
+    __shared__ uint8_t tmap[kWave];
     const uint32_t lane = threadIdx.x;
-    const uint32_t slot = cell_of_block(blockIdx.x, b.nslots);
-    if (slot >= b.nslots) return;
+    const uint32_t ncq = *n_occupied;
+    if (blockIdx.x >= ncq) return;
+    const uint32_t slot = cells[list_pos(blockIdx.x, ncq)];
     const uint32_t s0 = cstart[slot], e0 = cend[slot];
     if (s0 >= e0) return;
     const SceneC<T> &scn = b.sc[scene_of_slot(b, slot)];
@@ -491,9 +503,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
     const uint32_t left0 = s0 + kWave * nlane;
     // work counters of the cell (uniform), added to the slot's own record
     // (kept in LDS by lane 0 rather than in registers)
-    __shared__ unsigned long long cstat[5];
     if (lane < 5u) cstat[lane] = 0ull;
-    __shared__ uint8_t tmap[kWave];
     for (uint32_t ch = 0; ch < nlane; ++ch) {
         const uint32_t t0 = s0 + kWave * ch;
         const bool with_left = (ch + 1 == nlane) && nleft;
@@ -832,16 +842,21 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                                                const uint32_t *__restrict__ cend, const V2<T> *__restrict__ dens,
                                                const uint64_t *__restrict__ masks,
                                                const V4<T> *__restrict__ fspring, V4<T> *__restrict__ force,
-                                               double *__restrict__ fbody, unsigned long long *__restrict__ stats)
+                                               double *__restrict__ fbody, unsigned long long *__restrict__ stats,
+                                               const uint32_t *__restrict__ cells,
+                                               const uint32_t *__restrict__ n_occupied)
 {
     __shared__ Nbhd nb;
     __shared__ V4<T> cp[kScWords * kWave];
     __shared__ V4<T> cvel[kScWords * kWave];
     __shared__ V2<T> cden[kScWords * kWave];
     __shared__ double accf[kLeftF > 0 ? kLeftF : 1][3];
+    __shared__ unsigned long long cstat;   // neighbour-loop iterations of the cell
+    __shared__ uint8_t tmap[kWave];
     const uint32_t lane = threadIdx.x;
-    const uint32_t slot = cell_of_block(blockIdx.x, b.nslots);
-    if (slot >= b.nslots) return;
+    const uint32_t ncq = *n_occupied;
+    if (blockIdx.x >= ncq) return;
+    const uint32_t slot = cells[list_pos(blockIdx.x, ncq)];
     const uint32_t s0 = cstart[slot], e0 = cend[slot];
     if (s0 >= e0) return;
     const SceneC<T> &scn = b.sc[scene_of_slot(b, slot)];
@@ -859,9 +874,7 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
     const uint32_t nlane = use_left ? ncell / kWave : (ncell + kWave - 1) / kWave;
     const uint32_t nleft = use_left ? rem : 0u;
     const uint32_t left0 = s0 + kWave * nlane;
-    __shared__ unsigned long long cstat;   // neighbour-loop iterations of the cell
     if (lane == 0) cstat = 0ull;
-    __shared__ uint8_t tmap[kWave];
     for (uint32_t ch = 0; ch < nlane; ++ch) {
         const uint32_t t0 = s0 + kWave * ch;
         const bool with_left = (ch + 1 == nlane) && nleft;
@@ -1019,6 +1032,7 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                                force, fbody);
         }
     }
+    __syncthreads();
     if (lane == 0) stats[(size_t)slot * kStatWords + 5] += cstat;
 }
 
@@ -1046,35 +1060,44 @@ void launch_stats_sum(hipStream_t s, uint32_t nslots, const unsigned long long *
     hipLaunchKernelGGL(k_stats_sum, dim3(kStats), dim3(256), 0, s, nslots, rec, out);
 }
 
+// One workgroup per occupied cell at most: min(particles, slots).
+inline uint32_t cell_grid(uint32_t n, uint32_t nslots) { return std::max(1u, std::min(n, nslots)); }
+
 template <typename T>
 void launch_density(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, const uint32_t *cstart,
-                    const uint32_t *cend, V2<T> *dens, uint64_t *masks, uint32_t *err, unsigned long long *stats)
+                    const uint32_t *cend, V2<T> *dens, uint64_t *masks, uint32_t *err, unsigned long long *stats,
+                    const uint32_t *cells, const uint32_t *ncell)
 {
     if (!n) return;
-    hipLaunchKernelGGL(k_density<T>, dim3(b.nslots), dim3(64), 0, s, n, st, b, cstart, cend, dens, masks, err,
-                       stats);
+    hipLaunchKernelGGL(k_density<T>, dim3(cell_grid(n, b.nslots)), dim3(64), 0, s, n, st, b, cstart, cend, dens,
+                       masks, err, stats, cells, ncell);
 }
 
 template <typename T>
 void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, const uint32_t *cstart,
                    const uint32_t *cend, const V2<T> *dens, const uint64_t *masks, const V4<T> *fspring,
-                   V4<T> *force, double *fbody, uint32_t *err, unsigned long long *stats)
+                   V4<T> *force, double *fbody, uint32_t *err, unsigned long long *stats, const uint32_t *cells,
+                   const uint32_t *ncell)
 {
     (void)err;
     if (!n) return;
-    hipLaunchKernelGGL(k_forces<T>, dim3(b.nslots), dim3(64), 0, s, n, st, b, cstart, cend, dens, masks, fspring,
-                       force, fbody, stats);
+    hipLaunchKernelGGL(k_forces<T>, dim3(cell_grid(n, b.nslots)), dim3(64), 0, s, n, st, b, cstart, cend, dens,
+                       masks, fspring, force, fbody, stats, cells, ncell);
 }
 
 template void launch_density<float>(hipStream_t, uint32_t, State<float>, const Batch<float> &, const uint32_t *,
-                                    const uint32_t *, V2<float> *, uint64_t *, uint32_t *, unsigned long long *);
+                                    const uint32_t *, V2<float> *, uint64_t *, uint32_t *, unsigned long long *,
+                                    const uint32_t *, const uint32_t *);
 template void launch_density<double>(hipStream_t, uint32_t, State<double>, const Batch<double> &, const uint32_t *,
-                                     const uint32_t *, V2<double> *, uint64_t *, uint32_t *, unsigned long long *);
+                                     const uint32_t *, V2<double> *, uint64_t *, uint32_t *, unsigned long long *,
+                                     const uint32_t *, const uint32_t *);
 template void launch_forces<float>(hipStream_t, uint32_t, State<float>, const Batch<float> &, const uint32_t *,
                                    const uint32_t *, const V2<float> *, const uint64_t *, const V4<float> *,
-                                   V4<float> *, double *, uint32_t *, unsigned long long *);
+                                   V4<float> *, double *, uint32_t *, unsigned long long *, const uint32_t *,
+                                   const uint32_t *);
 template void launch_forces<double>(hipStream_t, uint32_t, State<double>, const Batch<double> &, const uint32_t *,
                                     const uint32_t *, const V2<double> *, const uint64_t *, const V4<double> *,
-                                    V4<double> *, double *, uint32_t *, unsigned long long *);
+                                    V4<double> *, double *, uint32_t *, unsigned long long *, const uint32_t *,
+                                    const uint32_t *);
 
 }  // namespace sphk

@@ -73,7 +73,6 @@ struct sph_ctx {
     uint32_t *id[2] = {nullptr, nullptr}, *aux[2] = {nullptr, nullptr};
     int cur = 0;
     Sort sort{};
-    uint32_t *sorted_keys = nullptr, *sorted_vals = nullptr;
     uint32_t *inv_perm = nullptr, *cstart = nullptr, *cend = nullptr;
     void *dens = nullptr, *force = nullptr, *fspring = nullptr;
     uint64_t *masks = nullptr;
@@ -204,7 +203,7 @@ bool body_mass_props(const sph_scene *s, uint32_t o, double *m_out, double com[3
 }
 
 struct Plan {
-    uint32_t n, nb, nk, rows, nsp2, nblk_w, nslots, K, nblk_sort, max_probes, nscenes, log_steps, track_steps;
+    uint32_t n, nb, nk, rows, nsp2, nblk_w, nslots, K, max_probes, nscenes, log_steps, track_steps;
     int prec;
 };
 
@@ -389,7 +388,6 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
     pl.nblk_w = nblk_w;
     pl.nslots = g.nslots;
     pl.K = p->smoothing_window;
-    pl.nblk_sort = (n + 2047) / 2048;
     pl.prec = p->precision;
     pl.max_probes = p->max_probes;
     pl.nscenes = 1;
@@ -503,7 +501,6 @@ sph_status validate_batch(const sph_params *p, const sph_scene *sc, uint32_t ns,
     tot.n = (uint32_t)n;
     tot.nslots = (uint32_t)slots;
     tot.K = p[0].smoothing_window;
-    tot.nblk_sort = (tot.n + 2047) / 2048;
     tot.prec = p[0].precision;
     tot.nscenes = ns;
     tot.log_steps = p[0].log_steps;
@@ -528,16 +525,16 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
         c->id[b] = cv.take<uint32_t>(n * 4);
         c->aux[b] = cv.take<uint32_t>(n * 4);
     }
-    c->sort.keys_a = cv.take<uint32_t>(n * 4);
-    c->sort.keys_b = cv.take<uint32_t>(n * 4);
-    c->sort.vals_a = cv.take<uint32_t>(n * 4);
-    c->sort.vals_b = cv.take<uint32_t>(n * 4);
-    c->sort.hist = cv.take<uint32_t>((size_t)256 * std::max<uint32_t>(pl.nblk_sort, 1) * 4);
-    c->sort.dbase = cv.take<uint32_t>(256 * 4);
-    c->sort.nblk = pl.nblk_sort;
+    c->sort.keys = cv.take<uint32_t>(n * 4);
+    c->sort.rank = cv.take<uint32_t>(n * 4);
+    c->sort.arrived = cv.take<uint32_t>(n * 4);
+    c->sort.counts = cv.take<uint32_t>((size_t)pl.nslots * 4);
+    c->sort.tiles = cv.take<uint2>((size_t)cell_scan_tiles(pl.nslots) * 8);
+    c->sort.cells = cv.take<uint32_t>((size_t)std::min<uint32_t>(pl.nslots, std::max<uint32_t>(pl.n, 1u)) * 4);
+    c->sort.ncell = cv.take<uint32_t>(4);
     c->inv_perm = cv.take<uint32_t>(n * 4);
-    c->cstart = cv.take<uint32_t>((size_t)pl.nslots * 8);   // cstart and cend back to back: one clear
-    c->cend = c->cstart ? c->cstart + pl.nslots : nullptr;
+    c->cstart = cv.take<uint32_t>((size_t)pl.nslots * 4);
+    c->cend = cv.take<uint32_t>((size_t)pl.nslots * 4);
     c->dens = cv.take<void>(n * 2 * tsz);
     c->force = cv.take<void>(n * 4 * tsz);
     c->masks = cv.take<uint64_t>((size_t)kMaxWords * n * 8);
@@ -630,28 +627,22 @@ Batch<T> batch(const sph_ctx *c)
     return Batch<T>{(const SceneC<T> *)c->scene_tab, c->nscenes, c->nslots};
 }
 
-int key_bits(uint32_t nslots)
-{
-    int b = 0;
-    while (b < 32 && (1ull << b) < nslots) ++b;
-    return b;
-}
-
-// Neighbour search: keys, radix sort, cell table, reorder into the other buffer.
+// Neighbour search: keys and per-cell counts, cell table, scatter, reorder
+// into the other buffer.
 template <typename T>
 void neighbour_search(sph_ctx *c)
 {
     const uint32_t n = c->n;
     prof_mark(c, 1, true);
-    launch_keys<T>(c->stream, n, (const V4<T> *)c->pos[c->cur], batch<T>(c), c->sort.keys_a);
+    launch_keys<T>(c->stream, n, (const V4<T> *)c->pos[c->cur], batch<T>(c), c->sort);
     prof_mark(c, 1, false);
     prof_mark(c, 2, true);
-    launch_radix_sort(c->stream, n, key_bits(c->nslots), c->sort, &c->sorted_keys, &c->sorted_vals);
+    launch_cell_table(c->stream, c->nslots, c->sort, c->cstart, c->cend);
+    launch_cell_scatter(c->stream, n, c->sort, c->cstart);
     prof_mark(c, 2, false);
     prof_mark(c, 3, true);
-    launch_clear_u32(c->stream, c->cstart, (size_t)c->nslots * 2);   // cstart and cend
-    launch_reorder<T>(c->stream, n, c->sorted_vals, c->sorted_keys, state<T>(c, c->cur), state<T>(c, 1 - c->cur),
-                      c->inv_perm, c->cstart, c->cend, (V2<T> *)c->dens, (V4<T> *)c->force);
+    launch_reorder<T>(c->stream, n, c->sort, c->cstart, c->cend, state<T>(c, c->cur), state<T>(c, 1 - c->cur),
+                      c->inv_perm, (V2<T> *)c->dens, (V4<T> *)c->force);
     c->cur = 1 - c->cur;
     prof_mark(c, 3, false);
 }
@@ -678,11 +669,13 @@ void one_step(sph_ctx *c)
     launch_springs<T>(s, sa, c->inv_perm, st, (V4<T> *)c->fspring);
     prof_mark(c, 4, false);
     prof_mark(c, 5, true);
-    launch_density<T>(s, c->n, st, batch<T>(c), c->cstart, c->cend, (V2<T> *)c->dens, c->masks, c->err, c->stat_rec);
+    launch_density<T>(s, c->n, st, batch<T>(c), c->cstart, c->cend, (V2<T> *)c->dens, c->masks, c->err, c->stat_rec,
+                      c->sort.cells, c->sort.ncell);
     prof_mark(c, 5, false);
     prof_mark(c, 6, true);
     launch_forces<T>(s, c->n, st, batch<T>(c), c->cstart, c->cend, (const V2<T> *)c->dens, c->masks,
-                     (const V4<T> *)c->fspring, (V4<T> *)c->force, c->fbody, c->err, c->stat_rec);
+                     (const V4<T> *)c->fspring, (V4<T> *)c->force, c->fbody, c->err, c->stat_rec, c->sort.cells,
+                     c->sort.ncell);
     prof_mark(c, 6, false);
     prof_mark(c, 9, true);
     if (c->n_probes) {
@@ -862,6 +855,7 @@ sph_status upload(sph_ctx *c, const sph_scene *s)
     }
     launch_clear_u32(st, c->log_count, c->nk);
     launch_clear_u32(st, c->track_pos, 2 * (size_t)c->nk);
+    launch_clear_u32(st, c->sort.counts, c->nslots);     // the cell-table scan keeps them zero afterwards
     // first neighbour search, then boundary volumes from the initial configuration
     c->cur = 0;
     if (n) {
@@ -1392,6 +1386,15 @@ sph_status sph_reset_smoothing(sph_ctx *ctx, uint32_t object)
 
 namespace {
 
+// Cell slot of every position of the cell order, from the cell table.
+std::vector<uint32_t> keys_of_positions(uint32_t n, const std::vector<uint32_t> &cs, const std::vector<uint32_t> &ce)
+{
+    std::vector<uint32_t> keys(n, 0xffffffffu);
+    for (size_t k = 0; k < cs.size(); ++k)
+        for (uint32_t p = cs[k]; p < ce[k] && p < n; ++p) keys[p] = (uint32_t)k;
+    return keys;
+}
+
 template <typename T>
 sph_status read_field_t(sph_ctx *c, int field, void *dst, size_t bytes)
 {
@@ -1410,7 +1413,7 @@ sph_status read_field_t(sph_ctx *c, int field, void *dst, size_t bytes)
     HIPCHK(c, hipMemcpyAsync(aux.data(), c->aux[c->cur], (size_t)n * 4, hipMemcpyDeviceToHost, s));
     std::vector<V4<T>> v4;
     std::vector<V2<T>> v2;
-    std::vector<uint32_t> keys;
+    std::vector<uint32_t> keys, cs, ce;
     std::vector<double> fb;
     if (field == SPH_FIELD_X || field == SPH_FIELD_PSI) {
         v4.resize(n);
@@ -1433,11 +1436,14 @@ sph_status read_field_t(sph_ctx *c, int field, void *dst, size_t bytes)
         v2.resize(n);
         HIPCHK(c, hipMemcpyAsync(v2.data(), c->dens, (size_t)n * sizeof(V2<T>), hipMemcpyDeviceToHost, s));
     } else if (field == SPH_FIELD_KEY) {
-        keys.resize(n);
-        HIPCHK(c, hipMemcpyAsync(keys.data(), c->sorted_keys, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        cs.resize(c->nslots);
+        ce.resize(c->nslots);
+        HIPCHK(c, hipMemcpyAsync(cs.data(), c->cstart, cs.size() * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(ce.data(), c->cend, ce.size() * 4, hipMemcpyDeviceToHost, s));
     }
     sph_status st = check_err(c);
     if (st == SPH_ERR_DEVICE) return st;
+    if (field == SPH_FIELD_KEY) keys = keys_of_positions(n, cs, ce);
     double *d = (double *)dst;
     for (uint32_t p = 0; p < n; ++p) {
         const uint32_t i = ids[p];
@@ -1509,20 +1515,22 @@ sph_status debug_nbrs_t(sph_ctx *c, uint32_t nt, const uint32_t *targets, uint32
     // positions the step's neighbour passes saw: the reorder's source buffer
     // through the sort permutation (integration has moved the current one)
     std::vector<V4<T>> pos(n), old(n);
-    std::vector<uint32_t> perm(n);
+    std::vector<uint32_t> old_ids(n), inv(n);
     if (n) {
         HIPCHK(c, hipMemcpyAsync(old.data(), c->pos[1 - c->cur], (size_t)n * sizeof(V4<T>), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipMemcpyAsync(perm.data(), c->sorted_vals, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(old_ids.data(), c->id[1 - c->cur], (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(inv.data(), c->inv_perm, (size_t)n * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipMemcpyAsync(ids.data(), c->id[c->cur], (size_t)n * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipMemcpyAsync(aux.data(), c->aux[c->cur], (size_t)n * 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipMemcpyAsync(keys.data(), c->sorted_keys, (size_t)n * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipMemcpyAsync(cs.data(), c->cstart, cs.size() * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipMemcpyAsync(ce.data(), c->cend, ce.size() * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipMemcpyAsync(masks.data(), c->masks, masks.size() * 8, hipMemcpyDeviceToHost, s));
     }
     sph_status st = check_err(c);
     if (st == SPH_ERR_DEVICE) return st;
-    for (uint32_t p = 0; p < n; ++p) pos[p] = old[perm[p]];
+    keys = keys_of_positions(n, cs, ce);
+    // the reorder moved the particle at old index v to inv_perm[id]
+    for (uint32_t v = 0; v < n; ++v) pos[inv[old_ids[v]]] = old[v];
     std::vector<std::vector<uint32_t>> lists(n);
     std::vector<uint8_t> want(n, targets ? 0 : 1);
     if (targets)

@@ -123,10 +123,13 @@ struct State {
 };
 
 struct Sort {
-    uint32_t *keys_a, *keys_b, *vals_a, *vals_b;
-    uint32_t *hist;
-    uint32_t *dbase;   // 256 digit totals
-    uint32_t nblk;
+    uint32_t *keys;      // [n] cell slot of each particle, current order
+    uint32_t *rank;      // [n] arrival rank among the particles of its slot
+    uint32_t *arrived;   // [n] current index of the particle at each position of the cell slices
+    uint32_t *counts;    // [nslots] particles per slot; zero between steps
+    uint2 *tiles;        // [scan tiles] (particles, occupied slots) totals of the slot scan
+    uint32_t *cells;     // [min(nslots, n)] occupied slots in slot order
+    uint32_t *ncell;     // [1] number of occupied slots
 };
 
 
@@ -274,28 +277,30 @@ __device__ __forceinline__ uint32_t scene_of_slot(const Batch<T> &b, uint32_t k)
 
 // --- launchers (k_grid.hip) ---
 template <typename T>
-void launch_keys(hipStream_t s, uint32_t n, const V4<T> *pos, const Batch<T> &b, uint32_t *keys);
-void launch_radix_sort(hipStream_t s, uint32_t n, int key_bits, Sort &st, uint32_t **sorted_keys,
-                       uint32_t **sorted_vals);
+void launch_keys(hipStream_t s, uint32_t n, const V4<T> *pos, const Batch<T> &b, Sort &st);
+uint32_t cell_scan_tiles(uint32_t nslots);
+void launch_cell_table(hipStream_t s, uint32_t nslots, Sort &st, uint32_t *cstart, uint32_t *cend);
+void launch_cell_scatter(hipStream_t s, uint32_t n, Sort &st, const uint32_t *cstart);
 void launch_clear_u32(hipStream_t s, uint32_t *p, size_t count);
 template <typename T>
-void launch_reorder(hipStream_t s, uint32_t n, const uint32_t *perm, const uint32_t *keys,
-                    State<T> in, State<T> out, uint32_t *inv_perm, uint32_t *cstart, uint32_t *cend,
-                    V2<T> *dens, V4<T> *force);
+void launch_reorder(hipStream_t s, uint32_t n, const Sort &st, const uint32_t *cstart, const uint32_t *cend,
+                    State<T> in, State<T> out, uint32_t *inv_perm, V2<T> *dens, V4<T> *force);
 template <typename T>
 void launch_psi_obj(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, const uint32_t *cstart,
                     const uint32_t *cend, const int32_t *obj_of_id);
 
 // --- launchers (k_sums.hip) ---
+// The two neighbour passes run one workgroup per occupied cell (cells, the
+// list the cell table wrote, and its length *ncell).
 template <typename T>
 void launch_density(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b,
                     const uint32_t *cstart, const uint32_t *cend, V2<T> *dens, uint64_t *masks,
-                    uint32_t *err, unsigned long long *stats);
+                    uint32_t *err, unsigned long long *stats, const uint32_t *cells, const uint32_t *ncell);
 template <typename T>
 void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b,
                    const uint32_t *cstart, const uint32_t *cend, const V2<T> *dens,
                    const uint64_t *masks, const V4<T> *fspring, V4<T> *force, double *fbody,
-                   uint32_t *err, unsigned long long *stats);
+                   uint32_t *err, unsigned long long *stats, const uint32_t *cells, const uint32_t *ncell);
 // Sum of the per-slot counter records [nslots][kStatWords] into out[kStats].
 void launch_stats_sum(hipStream_t s, uint32_t nslots, const unsigned long long *rec, unsigned long long *out);
 
