@@ -6,7 +6,8 @@
  * wrench between SPH updates from the grabbed body's state, its recent wrenches
  * and the fluid density around it (density field of Sec. 3.4)).
  *
- * Network: x (n_in <= 128 raw features, standardised, zero-padded to 128)
+ * Network: x (n_in <= 256 raw features, standardised, zero-padded to K_0 =
+ *   128 columns, or 256 when n_in > 128)
  *   -> L hidden layers of H units (GELU, erf form) -> n_out <= 16 outputs
  *   (standardised targets; de-standardised on output).  With residual_from
  *   = k > 0 the output is y = x[k-1 .. k-2+n_out] + destandardised network
@@ -19,7 +20,7 @@
  *
  * Parameter layout (FP32, flat, mlp_param_count() floats), layer l = 0..L:
  *   W_l [N_l][K_l] row-major (row = output unit), then b_l [N_l];
- *   K_0 = 128, K_l = H (l > 0); N_l = H (l < L), N_L = 16.
+ *   K_0 = 128 (n_in <= 128) or 256, K_l = H (l > 0); N_l = H (l < L), N_L = 16.
  * Rows n_out..15 of W_L and entries n_out..15 of b_L are forced to zero.
  *
  * Device arrays (X, Y, out) are caller-owned device memory; host arrays are
@@ -50,7 +51,7 @@ typedef enum {
 
 typedef struct {
     uint32_t abi_version;   /* MLP_ABI_VERSION */
-    uint32_t n_in;          /* raw input features, 1..128 */
+    uint32_t n_in;          /* raw input features, 1..256 */
     uint32_t n_out;         /* outputs, 1..16 */
     uint32_t hidden;        /* H: 64, 128, 192 or 256 */
     uint32_t layers;        /* L hidden layers, 1..4 */

@@ -12,7 +12,8 @@ What it computes (plain numpy, binary64):
     the loss refer to y - x[res_col ..];
   * the network z_l = a_{l-1} W_l^T + b_l, a_l = GELU(z_l) for the hidden
     layers (GELU in its exact form 0.5 z (1 + erf(z / sqrt 2))), a linear
-    output layer; inputs zero-padded to 128 columns, outputs padded to 16;
+    output layer; inputs zero-padded to 128 columns (256 for more than 128
+    inputs), outputs padded to 16;
   * the loss L = 1/(m n_out) sum (out' - y')^2 over the first n_out outputs and
     its gradient by the chain rule (backpropagation written out per layer);
   * Adam (Kingma and Ba 2015, Algorithm 1: moment estimates with bias
@@ -34,8 +35,13 @@ import math
 
 import numpy as np
 
-K_IN = 128      # padded input width
+K_IN = 128      # padded input width for up to 128 inputs (256 above)
 N_OUT_PAD = 16  # padded output width
+
+
+def k_in(n_in=K_IN):
+    """Padded input width of a network with n_in inputs."""
+    return K_IN if n_in <= K_IN else 2 * K_IN
 
 
 def bf16(a):
@@ -60,23 +66,23 @@ def gelu_grad(z):
     return 0.5 * (1.0 + _erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
 
 
-def shapes(hidden, layers):
+def shapes(hidden, layers, n_in=K_IN):
     """(N_l, K_l) of every layer, output layer last."""
-    out = [(hidden, K_IN)]
+    out = [(hidden, k_in(n_in))]
     out += [(hidden, hidden)] * (layers - 1)
     out.append((N_OUT_PAD, hidden))
     return out
 
 
-def param_count(hidden, layers):
-    return sum(n * k + n for n, k in shapes(hidden, layers))
+def param_count(hidden, layers, n_in=K_IN):
+    return sum(n * k + n for n, k in shapes(hidden, layers, n_in))
 
 
-def unpack(params, hidden, layers):
+def unpack(params, hidden, layers, n_in=K_IN):
     """Flat FP32/FP64 vector -> list of (W [N][K], b [N]) as float64 views."""
     p = np.asarray(params, np.float64)
     out, o = [], 0
-    for n, k in shapes(hidden, layers):
+    for n, k in shapes(hidden, layers, n_in):
         W = p[o:o + n * k].reshape(n, k)
         o += n * k
         b = p[o:o + n]
@@ -146,10 +152,10 @@ def forward(params, X, norm, hidden, layers, n_out, quant=True, res_col=None):
     mx, sx, my, sy = (np.asarray(v, np.float64) for v in norm)
     X = np.asarray(X, np.float64)
     m, n_in = X.shape
-    xs = np.zeros((m, K_IN))
+    xs = np.zeros((m, k_in(n_in)))
     xs[:, :n_in] = (X - mx) / sx
     a = _q(xs, quant)
-    wb = unpack(params, hidden, layers)
+    wb = unpack(params, hidden, layers, n_in)
     acts, zs = [a], []
     for l, (W, b) in enumerate(wb):
         z = a @ _q(W, quant).T + b
@@ -170,7 +176,7 @@ def loss_and_grad(params, X, Y, norm, hidden, layers, n_out, quant=True, res_col
     ys = (Y - _res(X, n_out, res_col) - my) / sy
     d = c["out_s"] - ys
     loss = float(np.sum(d * d) / (m * n_out))
-    wb = unpack(params, hidden, layers)
+    wb = unpack(params, hidden, layers, np.shape(X)[1])
     dz = np.zeros((m, N_OUT_PAD))
     dz[:, :n_out] = 2.0 * d / (m * n_out)
     dz = _q(dz, quant)

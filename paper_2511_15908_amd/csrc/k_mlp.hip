@@ -185,12 +185,12 @@ void launch_splitk_reduce(hipStream_t s, const float *partials, uint32_t splits,
     hipLaunchKernelGGL(k_splitk_reduce, dim3((count + 255) / 256), dim3(256), 0, s, partials, splits, count, out);
 }
 
-__global__ void k_standardize(const float *__restrict__ X, uint32_t m, uint32_t n_in, const float *__restrict__ mu,
-                              const float *__restrict__ sd, uint16_t *__restrict__ Xb)
+__global__ void k_standardize(const float *__restrict__ X, uint32_t m, uint32_t n_in, uint32_t k0,
+                              const float *__restrict__ mu, const float *__restrict__ sd, uint16_t *__restrict__ Xb)
 {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    if (i >= m * kIn) return;
-    const uint32_t r = i / kIn, c = i % kIn;
+    if (i >= m * k0) return;
+    const uint32_t r = i / k0, c = i % k0;
     float v = 0.f;
     if (c < n_in) v = (X[(size_t)r * n_in + c] - mu[c]) / sd[c];
     Xb[i] = to_bf16(v);
@@ -200,7 +200,8 @@ void launch_standardize(hipStream_t s, const float *X, uint32_t m, uint32_t n_in
                         uint16_t *Xb)
 {
     if (!m) return;
-    hipLaunchKernelGGL(k_standardize, dim3((m * kIn + 255) / 256), dim3(256), 0, s, X, m, n_in, mu, sd, Xb);
+    const uint32_t k0 = k0_of(n_in);
+    hipLaunchKernelGGL(k_standardize, dim3((m * k0 + 255) / 256), dim3(256), 0, s, X, m, n_in, k0, mu, sd, Xb);
 }
 
 // Loss gradient and per-block partial loss sums (rows of 16 outputs).
@@ -483,7 +484,7 @@ __global__ __launch_bounds__(256) void k_predict_one(PredictArgs a)
             return;
         }
     }
-    if (t < kIn) {
+    if (t < a.k0) {
         float v = 0.f;
         if (t < a.n_in) v = (a.x[t] - a.mu_x[t]) / a.sd_x[t];
         act[t] = from_bf16(to_bf16(v));
@@ -491,7 +492,7 @@ __global__ __launch_bounds__(256) void k_predict_one(PredictArgs a)
     __syncthreads();
     size_t off = 0;
     for (uint32_t l = 0; l <= a.layers; ++l) {
-        const uint32_t K = l == 0 ? kIn : a.hidden;
+        const uint32_t K = l == 0 ? a.k0 : a.hidden;
         const uint32_t N = l == a.layers ? kOutPad : a.hidden;
         float z = 0.f;
         if (t < N) {

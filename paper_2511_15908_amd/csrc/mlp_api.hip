@@ -79,8 +79,8 @@ mlp_status validate(const mlp_config *c, std::string &why)
             why = "reserved fields must be zero";
             return MLP_ERR_ARG;
         }
-    if (c->n_in < 1 || c->n_in > kIn || c->n_out < 1 || c->n_out > kOutPad) {
-        why = "n_in must be 1..128 and n_out 1..16";
+    if (c->n_in < 1 || c->n_in > kInMax || c->n_out < 1 || c->n_out > kOutPad) {
+        why = "n_in must be 1..256 and n_out 1..16";
         return MLP_ERR_ARG;
     }
     if (c->hidden < 64 || c->hidden > 256 || c->hidden % 64) {
@@ -117,7 +117,7 @@ void layout(mlp_ctx *c)
     c->Kl.clear();
     size_t o = 0;
     for (uint32_t l = 0; l <= c->L; ++l) {
-        const uint32_t K = l == 0 ? kIn : c->H, N = l == c->L ? kOutPad : c->H;
+        const uint32_t K = l == 0 ? k0_of(c->cfg.n_in) : c->H, N = l == c->L ? kOutPad : c->H;
         c->off.push_back(o);
         c->Nl.push_back(N);
         c->Kl.push_back(K);
@@ -138,11 +138,11 @@ size_t carve(mlp_ctx *c, char *base)
     c->m2 = cv.take<float>(P);
     c->grad = cv.take<float>(P);
     c->wb = cv.take<uint16_t>(P);
-    c->mu_x = cv.take<float>(kIn);
-    c->sd_x = cv.take<float>(kIn);
+    c->mu_x = cv.take<float>(kInMax);
+    c->sd_x = cv.take<float>(kInMax);
     c->mu_y = cv.take<float>(kOutPad);
     c->sd_y = cv.take<float>(kOutPad);
-    c->xb = cv.take<uint16_t>(B * kIn);
+    c->xb = cv.take<uint16_t>(B * k0_of(c->cfg.n_in));
     c->Z.assign(c->L, nullptr);
     c->Hact.assign(c->L, nullptr);
     for (uint32_t l = 0; l < c->L; ++l) {
@@ -161,12 +161,12 @@ size_t carve(mlp_ctx *c, char *base)
     c->partials = cv.take<float>(std::max((size_t)c->max_splits * maxwk, bias_part));
     c->loss_part = cv.take<double>(loss_blocks(c->B));
     c->loss = cv.take<double>(1);
-    c->px = cv.take<float>(kIn);
+    c->px = cv.take<float>(kInMax);
     c->py = cv.take<float>(kOutPad);
-    c->xlo = cv.take<float>(kIn);
-    c->xhi = cv.take<float>(kIn);
-    c->ga = cv.take<float>(kIn);
-    c->gb = cv.take<float>(kIn);
+    c->xlo = cv.take<float>(kInMax);
+    c->xhi = cv.take<float>(kInMax);
+    c->ga = cv.take<float>(kInMax);
+    c->gb = cv.take<float>(kInMax);
     c->gflags = cv.take<uint8_t>(B);
     c->gcount = cv.take<unsigned long long>(1);
     return cv.off;
@@ -199,7 +199,7 @@ void forward(mlp_ctx *c, const float *X, uint32_t m)
     hipStream_t s = c->stream;
     launch_standardize(s, X, m, c->cfg.n_in, c->mu_x, c->sd_x, c->xb);
     const uint16_t *a = c->xb;
-    uint32_t lda = kIn;
+    uint32_t lda = k0_of(c->cfg.n_in);
     for (uint32_t l = 0; l <= c->L; ++l) {
         GemmArgs g{};
         g.A = a;
@@ -375,8 +375,8 @@ mlp_status mlp_init(const mlp_config *cfg, void *d_workspace, size_t ws_bytes, v
     launch_fill_f32(s, c->m1, 0.f, (uint32_t)c->P);
     launch_fill_f32(s, c->m2, 0.f, (uint32_t)c->P);
     launch_fill_f32(s, c->grad, 0.f, (uint32_t)c->P);
-    launch_fill_f32(s, c->mu_x, 0.f, kIn);
-    launch_fill_f32(s, c->sd_x, 1.f, kIn);
+    launch_fill_f32(s, c->mu_x, 0.f, kInMax);
+    launch_fill_f32(s, c->sd_x, 1.f, kInMax);
     launch_fill_f32(s, c->mu_y, 0.f, kOutPad);
     launch_fill_f32(s, c->sd_y, 1.f, kOutPad);
     launch_fill_f32(s, reinterpret_cast<float *>(c->gcount), 0.f, 2);
@@ -434,11 +434,11 @@ mlp_status mlp_fit_normalizer(mlp_ctx *c, const float *X, const float *Y, uint32
     launch_fit_normalizer(c->stream, X, m, c->cfg.n_in, Residual{nullptr, 0, 0}, c->mu_x, c->sd_x, c->xlo, c->xhi);
     launch_fit_normalizer(c->stream, Y, m, c->cfg.n_out, residual(c, X), c->mu_y, c->sd_y, nullptr, nullptr);
     MLPCHK(c, hipGetLastError());
-    std::vector<float> a(kIn), b(kIn), d(kOutPad), e(kOutPad), lo(c->cfg.n_in), hi(c->cfg.n_in);
+    std::vector<float> a(kInMax), b(kInMax), d(kOutPad), e(kOutPad), lo(c->cfg.n_in), hi(c->cfg.n_in);
     MLPCHK(c, hipMemcpyAsync(lo.data(), c->xlo, c->cfg.n_in * 4, hipMemcpyDeviceToHost, c->stream));
     MLPCHK(c, hipMemcpyAsync(hi.data(), c->xhi, c->cfg.n_in * 4, hipMemcpyDeviceToHost, c->stream));
-    MLPCHK(c, hipMemcpyAsync(a.data(), c->mu_x, kIn * 4, hipMemcpyDeviceToHost, c->stream));
-    MLPCHK(c, hipMemcpyAsync(b.data(), c->sd_x, kIn * 4, hipMemcpyDeviceToHost, c->stream));
+    MLPCHK(c, hipMemcpyAsync(a.data(), c->mu_x, kInMax * 4, hipMemcpyDeviceToHost, c->stream));
+    MLPCHK(c, hipMemcpyAsync(b.data(), c->sd_x, kInMax * 4, hipMemcpyDeviceToHost, c->stream));
     MLPCHK(c, hipMemcpyAsync(d.data(), c->mu_y, kOutPad * 4, hipMemcpyDeviceToHost, c->stream));
     MLPCHK(c, hipMemcpyAsync(e.data(), c->sd_y, kOutPad * 4, hipMemcpyDeviceToHost, c->stream));
     MLPCHK(c, hipStreamSynchronize(c->stream));
@@ -618,6 +618,7 @@ static PredictArgs predict_args(mlp_ctx *c, const float *x, float *y)
     a.mu_y = c->mu_y;
     a.sd_y = c->sd_y;
     a.n_in = c->cfg.n_in;
+    a.k0 = k0_of(c->cfg.n_in);
     a.n_out = c->cfg.n_out;
     a.hidden = c->H;
     a.layers = c->L;

@@ -6,7 +6,9 @@
 
 namespace mlpk {
 
-constexpr uint32_t kIn = 128;     // padded input width
+constexpr uint32_t kInMax = 256;  // most raw inputs
+// padded input width: 128 columns for up to 128 inputs, else 256
+__host__ __device__ constexpr uint32_t k0_of(uint32_t n_in) { return n_in <= 128u ? 128u : 256u; }
 constexpr uint32_t kOutPad = 16;  // padded output width
 constexpr uint32_t kTile = 64;    // GEMM output tile (rows and columns)
 constexpr uint32_t kTileK = 32;   // GEMM contraction step (one MFMA 16x16x32)
@@ -77,7 +79,7 @@ struct PredictArgs {
     const uint16_t *wb;  // BF16 parameters (parameter layout)
     const float *w;      // FP32 parameters (biases are read from here)
     const float *mu_x, *sd_x, *mu_y, *sd_y;
-    uint32_t n_in, n_out, hidden, layers;
+    uint32_t n_in, k0, n_out, hidden, layers;   // k0: padded input width
     int32_t res_col0;    // first residual input column, or -1
     Guard guard;         // out of the training range: y = residual base
 };

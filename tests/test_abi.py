@@ -201,7 +201,10 @@ def test_mlp_validation_and_workspace(P):
     assert L.mlp_workspace_size(C.byref(_mlp_cfg()), C.byref(out)) == 0
     # parameters: 128x256+256 + 2 (256x256+256) + 16x256+16; activations of 4096 rows
     assert out.value > 4 * 4 * 168720 + 4096 * 256 * 6 * 3
-    for bad in [dict(n_in=0), dict(n_in=129), dict(n_out=17), dict(hidden=100), dict(hidden=512),
+    # more than 128 inputs pad to 256 columns: a larger first layer
+    small = out.value
+    assert L.mlp_workspace_size(C.byref(_mlp_cfg(n_in=200)), C.byref(out)) == 0 and out.value > small
+    for bad in [dict(n_in=0), dict(n_in=257), dict(n_out=17), dict(hidden=100), dict(hidden=512),
                 dict(layers=0), dict(layers=5), dict(max_batch=0), dict(max_batch=70000), dict(beta1=1.0),
                 dict(eps=0.0), dict(abi_version=2), dict(reserved=1)]:
         assert L.mlp_workspace_size(C.byref(_mlp_cfg(**bad)), C.byref(out)) == 1, bad

@@ -73,10 +73,10 @@ def test_gemm_empty_contraction(torch):
     assert float(Cg.abs().max()) == 0.0
 
 
-def _net(torch, seed=9, max_batch=4096, hidden=H, layers=LAYERS):
+def _net(torch, seed=9, max_batch=4096, hidden=H, layers=LAYERS, n_in=N_IN):
     from paper_2511_15908_amd import mlp, surrogate
-    net = mlp.Mlp(N_IN, N_OUT, hidden=hidden, layers=layers, max_batch=max_batch)
-    p = surrogate.init_params(seed, hidden, layers, N_IN, N_OUT)
+    net = mlp.Mlp(n_in, N_OUT, hidden=hidden, layers=layers, max_batch=max_batch)
+    p = surrogate.init_params(seed, hidden, layers, n_in, N_OUT)
     net.set_params(p)
     return net, p
 
@@ -126,6 +126,42 @@ def test_gradients_match_oracle(torch):
             assert rel < 2e-3 and cos > 0.99999
     # the loss is the oracle's; gradient pass leaves parameters unchanged
     assert np.array_equal(net.get_params(), p)
+
+
+def test_wide_inputs_match_oracle(torch):
+    """More than 128 inputs: the first layer pads to 256 columns; forward
+    (batched and the one-sample chain) and gradients against the oracle."""
+    n_in = 198
+    X, Y = _data(12, 900, n_in=n_in)
+    net, p = _net(torch, seed=13, n_in=n_in)
+    assert p.size == M.param_count(H, LAYERS, n_in) == net.n_params
+    dX, dY = torch.tensor(X, device="cuda"), torch.tensor(Y, device="cuda")
+    net.fit_normalizer(dX, dY)
+    norm = [np.asarray(v, np.float64) for v in net.get_normalizer()]
+    out_g = net.forward(dX).cpu().numpy().astype(np.float64)
+    out_o, _ = M.forward(p.astype(np.float64), X, norm, H, LAYERS, N_OUT, quant=True)
+    scale = np.abs(out_o).max()
+    err = np.abs(out_g - out_o).max() / scale
+    print(f"wide forward: max |diff| / max |out| = {err:.2e}")
+    assert err < 5e-3
+    for r in (0, 450, 899):
+        y1 = net.predict_one(X[r]).astype(np.float64)
+        assert np.abs(y1 - out_g[r]).max() / scale < 1e-3
+    g_gpu, loss_gpu = net.gradients(dX, dY)
+    loss_o, g_o = M.loss_and_grad(p.astype(np.float64), X, Y, norm, H, LAYERS, N_OUT, quant=True)
+    assert loss_gpu == pytest.approx(loss_o, rel=2e-3)
+    o = 0
+    for li, (n, k) in enumerate(M.shapes(H, LAYERS, n_in)):
+        for name, size in (("W", n * k), ("b", n)):
+            a = g_gpu[o:o + size].astype(np.float64)
+            b = g_o[o:o + size]
+            o += size
+            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            print(f"wide layer {li} {name}: rel L2 {rel:.2e}")
+            assert rel < 2e-3
+    # padded input columns keep zero weights and zero gradients
+    W0 = g_gpu[:H * 256].reshape(H, 256)
+    assert not W0[:, n_in:].any()
 
 
 def test_adam_matches_oracle(torch):
