@@ -63,15 +63,15 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 256-scene batch leg (graph-replayed steps of independent stirring tanks)")
     ap.add_argument("--no-surrogate", action="store_true",
-                    help="skip the haptic-rate surrogate leg (16 copies of the 100k haptic scene: logs, training, "
-                         "evaluation; about 2 minutes)")
+                    help="skip the haptic-rate surrogate legs (16 copies of the 100k haptic scene: logs, training, "
+                         "evaluation, about 2 minutes; then a short run on the coupled 1M scene, about 1.5 minutes)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the 256-scene batch leg and print its record (for profiling it alone)")
     ap.add_argument("--mlp-train-only", action="store_true",
-                    help="run only surrogate training steps (batch 4096, 126-256-256-256-6) and print their "
+                    help="run only surrogate training steps (batch 4096, 186-256-256-256-6) and print their "
                          "rate in matrix-core FLOP/s (for profiling the MFMA kernels)")
     return ap.parse_args()
 
@@ -205,11 +205,11 @@ def batch_leg(dev, n_scenes=256, steps=64):
             "particles_per_wavefront": n_all / max(d["waves"], 1)}
 
 
-# Dense products of one surrogate training step per sample (126 inputs padded
-# to 128, three hidden layers of 256, 6 outputs padded to 16): forward
+# Dense products of one surrogate training step per sample (186 inputs padded
+# to 256, three hidden layers of 256, 6 outputs padded to 16): forward
 # X W^T of every layer, weight gradients dZ^T A of every layer, and the data
 # gradients dZ W of every layer but the first; 2 FLOP per multiply-add.
-MLP_SHAPES = [(256, 128), (256, 256), (256, 256), (16, 256)]
+MLP_SHAPES = [(256, 256), (256, 256), (256, 256), (16, 256)]
 MLP_FLOP_PER_SAMPLE = 2 * (2 * sum(n * k for n, k in MLP_SHAPES) + sum(n * k for n, k in MLP_SHAPES[1:]))
 PEAK_BF16_TFLOPS = 2500.0
 
@@ -221,7 +221,7 @@ def mlp_train_leg(dev, steps=200, warmup=20, batch=4096):
     import torch
     from paper_2511_15908_amd import mlp, scenes, surrogate
     rng = scenes.SplitMix64(77, 9)
-    n_in, n_out = 126, 6
+    n_in, n_out = surrogate.N_FEATURES, 6
     X = torch.tensor(rng.normal(batch * n_in).reshape(batch, n_in).astype(np.float32), device=dev)
     Y = torch.tensor(rng.normal(batch * n_out).reshape(batch, n_out).astype(np.float32), device=dev)
     net = mlp.Mlp(n_in, n_out, hidden=256, layers=3, max_batch=batch, device=dev)
@@ -398,6 +398,20 @@ def main():
             "fallback": {"margin": S.GUARD_MARGIN, "rows_frac": round(e["surrogate"].get("fallback_frac", 0.0), 4)},
             "training": {"walks": r["training_walks"], "rows": r["training_rows"], "steps": r["train_steps"],
                          "seconds": round(r["train_s"], 2), "scene_copies_stepped_together": r["batch"],
+                         "ticks_simulated": r["ticks_collected"], "collect_seconds": round(r["collect_s"], 1)}}
+        log("surrogate leg: the coupled scene itself (1M fluid, soft cube, sphere on its random walk), "
+            "a short run: 4 training walks ...", a.quiet)
+        r = S.run_experiment(kind="coupled", scene=sc, train_segments=4, ticks=2000, eval_ticks=1000,
+                             eval_segments=2, steps=2000, warmup_ticks=200, log=lambda m: log(m, a.quiet))
+        e = r["errors"]
+        out["surrogate_coupled_1m"] = {
+            "scene": r["scene"], "n_particles": r["n_particles"], "walk": "Ornstein-Uhlenbeck, 1 kHz",
+            "sph_update_hz": 100, "haptic_hz": 1000,
+            "error_vs_plain_sph": {k: round(v["mean"], 4) for k, v in e.items()},
+            "error_p95": {k: round(v["p95"], 4) for k, v in e.items()},
+            "eval_walks": r["eval_walks"],
+            "fallback": {"margin": S.GUARD_MARGIN, "rows_frac": round(e["surrogate"].get("fallback_frac", 0.0), 4)},
+            "training": {"walks": r["training_walks"], "rows": r["training_rows"], "steps": r["train_steps"],
                          "ticks_simulated": r["ticks_collected"], "collect_seconds": round(r["collect_s"], 1)}}
     log(json.dumps(out, indent=1), a.quiet)
     if not a.no_cpu_baseline:

@@ -342,6 +342,10 @@ def coupled_soft_cube(s: float, g: float = 1.0):
     return ijk, pos, ij, L0, np.full(len(L0), ks), np.full(len(L0), cs)
 
 
+# the coupled scene's random walk: the box its centre is reflected at
+WALK_BOX = ((0.12, 0.12, 0.12), (0.43, 0.38, 0.40))
+
+
 def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") -> Scene:
     """Coupled fluid + soft + rigid: 100 x 100 fluid columns at spacing 5 mm in
     an open tank of about 0.51 x 0.51 x 0.6 m, a 20^3 soft cube on the fluid
@@ -373,7 +377,8 @@ def coupled_1m(seed: int = 3, n_fluid: int = 1_000_000, precision: str = "f32") 
                       (sph, BOUNDARY, 1, 0.0)],
                      kin=[0, 1], poses=poses,
                      springs=(ij_glob, L0, ks, cs),
-                     info={"body": 1, "radius": R, "c0": c0})
+                     info={"body": 1, "radius": R, "c0": c0, "walk_lo": WALK_BOX[0], "walk_hi": WALK_BOX[1],
+                           "probe_radius": R + s})
 
 
 def haptic_scene(seed: int = 5, n_fluid: int = 100_000, precision: str = "f32") -> Scene:
@@ -558,16 +563,18 @@ def stirring_pose(scene: Scene, t: float):
     return c, np.array([1.0, 0, 0, 0]), v, np.zeros(3)
 
 
-def random_walk(seed: int, n_ticks: int, c0, tick=1e-3, box_lo=(0.12, 0.12, 0.12),
-                box_hi=(0.43, 0.38, 0.40), sig_v=0.028, sig_w=0.141, decay=0.99):
+def random_walk(seed: int, n_ticks: int, c0, tick=1e-3, box_lo=WALK_BOX[0],
+                box_hi=WALK_BOX[1], sig_v=0.028, sig_w=0.141, decay=0.99, q0=None, v0=None, w0=None):
     """Ornstein-Uhlenbeck random walk of a body pose sampled every `tick`
     seconds: v <- decay v + N(0, sig_v^2) per axis, w likewise; the centre is
-    reflected at the box.  Returns arrays c, q, v, w of shape (n_ticks, .)."""
+    reflected at the box.  Starts at c0 and (q0, v0, w0), by default at rest
+    in the identity orientation.  Returns arrays c, q, v, w of shape
+    (n_ticks, .)."""
     rng = SplitMix64(seed, P_WALK)
     c = np.asarray(c0, np.float64).copy()
-    q = np.array([1.0, 0, 0, 0])
-    v = np.zeros(3)
-    w = np.zeros(3)
+    q = np.array([1.0, 0, 0, 0]) if q0 is None else np.asarray(q0, np.float64).copy()
+    v = np.zeros(3) if v0 is None else np.asarray(v0, np.float64).copy()
+    w = np.zeros(3) if w0 is None else np.asarray(w0, np.float64).copy()
     lo, hi = np.asarray(box_lo), np.asarray(box_hi)
     C, Q, V, W = (np.zeros((n_ticks, 3)), np.zeros((n_ticks, 4)),
                   np.zeros((n_ticks, 3)), np.zeros((n_ticks, 3)))
@@ -589,7 +596,8 @@ def random_walk(seed: int, n_ticks: int, c0, tick=1e-3, box_lo=(0.12, 0.12, 0.12
 
 
 def smooth_walk(seed: int, n_ticks: int, c0, box_lo, box_hi, tick=1e-3, tau_a=0.08, tau_v=0.1,
-                rms_a=0.5, f_spring=1.5, tau_target=1.0, tau_alpha=0.08, tau_w=0.3, rms_alpha=6.0):
+                rms_a=0.5, f_spring=1.5, tau_target=1.0, tau_alpha=0.08, tau_w=0.3, rms_alpha=6.0,
+                q0=None, v0=None, w0=None):
     """Hand-like pose stream at 1 kHz.  A target point wanders over the box
     (Ornstein-Uhlenbeck, correlation time tau_target, spread 0.18 of the box
     per axis); the centre follows it through a spring of frequency f_spring
@@ -597,7 +605,8 @@ def smooth_walk(seed: int, n_ticks: int, c0, box_lo, box_hi, tick=1e-3, tau_a=0.
     acceleration (tau_a, RMS rms_a m/s^2); the angular velocity relaxes with
     tau_w under an Ornstein-Uhlenbeck angular acceleration (tau_alpha,
     rms_alpha rad/s^2).  The box reflects the centre (rarely reached).
-    Returns c, q, v, w arrays (n_ticks, .)."""
+    Starts at c0 and (q0, v0, w0), by default at rest in the identity
+    orientation.  Returns c, q, v, w arrays (n_ticks, .)."""
     rng = SplitMix64(seed, P_WALK + 10)
     ra, rv = math.exp(-tick / tau_a), math.exp(-tick / tau_v)
     rb, rw = math.exp(-tick / tau_alpha), math.exp(-tick / tau_w)
@@ -605,8 +614,10 @@ def smooth_walk(seed: int, n_ticks: int, c0, box_lo, box_hi, tick=1e-3, tau_a=0.
     sa, sb, st = (rms_a * math.sqrt(1 - ra * ra), rms_alpha * math.sqrt(1 - rb * rb), math.sqrt(1 - rt * rt))
     kap = (2.0 * math.pi * f_spring) ** 2
     c = np.asarray(c0, np.float64).copy()
-    q = np.array([1.0, 0, 0, 0])
-    v, w, a, al = np.zeros(3), np.zeros(3), np.zeros(3), np.zeros(3)
+    q = np.array([1.0, 0, 0, 0]) if q0 is None else np.asarray(q0, np.float64).copy()
+    v = np.zeros(3) if v0 is None else np.asarray(v0, np.float64).copy()
+    w = np.zeros(3) if w0 is None else np.asarray(w0, np.float64).copy()
+    a, al = np.zeros(3), np.zeros(3)
     lo, hi = np.asarray(box_lo, np.float64), np.asarray(box_hi, np.float64)
     mid, spread = 0.5 * (lo + hi), 0.18 * (hi - lo)
     u = (c - mid) / spread                      # target in units of the spread

@@ -4,6 +4,7 @@ haptic-tick inference through the MLP C ABI.  Argument marshalling and
 bookkeeping only: the physics and the network run in libsph.so."""
 from __future__ import annotations
 
+import copy
 import math
 
 import numpy as np
@@ -20,7 +21,8 @@ def init_params(seed, hidden, layers, n_in, n_out):
     include/sph_mlp.h."""
     rng = scenes.SplitMix64(seed, P_INIT)
     parts = []
-    shapes = [(hidden, 128, n_in)] + [(hidden, hidden, hidden)] * (layers - 1) + [(16, hidden, hidden)]
+    k0 = 128 if n_in <= 128 else 256          # padded input width of the parameter layout
+    shapes = [(hidden, k0, n_in)] + [(hidden, hidden, hidden)] * (layers - 1) + [(16, hidden, hidden)]
     for li, (n, k, fan) in enumerate(shapes):
         a = math.sqrt(3.0 / fan)
         W = (2.0 * rng.uniform(n * k) - 1.0).reshape(n, k) * a
@@ -38,15 +40,21 @@ def init_params(seed, hidden, layers, n_in, n_out):
 # (13 inputs), the last N_HIST wrenches that SPH delivered at its slower rate,
 # every SPH_EVERY ticks (the newest, W(t0), as is; the older ones as
 # differences from it: 48), the probe densities of the SPH state at t0 (64
-# body-frame points at probe_radius), and t - t0 in units of SPH_EVERY (1):
-# 126 inputs.  The network predicts the change W(t) - W(t0) (residual output
-# over input columns RES_COL..RES_COL+5).
+# body-frame points at probe_radius), t - t0 in units of SPH_EVERY (1), and
+# the device's recent velocities, which it samples every tick: v and w at
+# t - j for the lags V_LAGS, as differences from v(t), w(t) (60) -- 186
+# inputs.  The body's recent accelerations drive the fluid's reaction
+# (added mass, pressure waves), and the rolling mean spans the last 40
+# ticks; without them the network cannot tell how the body moved since t0.
+# The network predicts the change W(t) - W(t0) (residual output over input
+# columns RES_COL..RES_COL+5).
 
 N_HIST = 8
 SPH_EVERY = 10
 GUARD_MARGIN = 0.5     # plain-SPH fallback outside the training range widened by half of it per side
 N_PROBES = 64
-N_FEATURES = 13 + 6 * N_HIST + N_PROBES + 1
+V_LAGS = (1, 2, 3, 5, 7, 10, 14, 20, 28, 40)
+N_FEATURES = 13 + 6 * N_HIST + N_PROBES + 1 + 6 * len(V_LAGS)
 RES_COL = 13
 
 
@@ -143,13 +151,16 @@ def feature_rows(log, ticks, lags):
     W = log["wrench"]
     w0 = W[t0]
     hist = [w0] + [W[t0 - SPH_EVERY * k] - w0 for k in range(1, N_HIST)]
+    lags = []
+    for j in V_LAGS:
+        lags += [log["v"][t - j] - log["v"][t], log["w"][t - j] - log["w"][t]]
     X = np.concatenate([log["c"][t], log["q"][t], log["v"][t], log["w"][t]] + hist +
-                       [log["probes"][t0], (d / SPH_EVERY)[:, None]], 1)
+                       [log["probes"][t0], (d / SPH_EVERY)[:, None]] + lags, 1)
     return X.astype(np.float32), W[t].astype(np.float32)
 
 
 def first_tick():
-    return SPH_EVERY * (N_HIST - 1) + SPH_EVERY - 1
+    return max(SPH_EVERY * (N_HIST - 1) + SPH_EVERY - 1, max(V_LAGS))
 
 
 def training_rows(log):
@@ -284,17 +295,58 @@ def force_spectrum(log, bands=((0, 2), (2, 10), (10, 25), (25, 50), (50, 100), (
     return {f"{a}-{b} Hz": float(P[(f > a) & (f <= b)].sum() / tot) for a, b in bands}
 
 
-def spectrum_run(n_fluid, ticks=3000, warmup_ticks=300):
+# haptic output of the experiment scenes: rolling mean over 160 SPH steps =
+# 40 ticks of 1 ms (Sec. 3.3, tens of haptic cycles)
+HAPTIC_WINDOW = 160
+SCENE_KINDS = ("haptic", "coupled")
+
+
+def experiment_scene(kind, n_fluid, base=None):
+    """The surrogate's scene: "haptic" (the sphere in a tank sized for
+    n_fluid, a hand-like smooth walk) or "coupled" (the coupled fluid + soft +
+    rigid scene with its Ornstein-Uhlenbeck random walk), both with the 40 ms
+    haptic rolling mean.  base: an already built scene of that kind, used
+    with its own parameters copied (it is not changed)."""
+    if kind not in SCENE_KINDS:
+        raise ValueError(f"scene kind must be one of {SCENE_KINDS}")
+    if base is not None:
+        sc = copy.copy(base)
+        sc.params = dict(base.params)
+    elif kind == "haptic":
+        return scenes.haptic_scene(n_fluid=n_fluid)
+    else:
+        sc = scenes.coupled_1m(n_fluid=n_fluid)
+    sc.params["smoothing_window"] = HAPTIC_WINDOW
+    return sc
+
+
+def start_state(scene):
+    """Pose stream state (c, q, v, w) at the scene's initial pose, at rest."""
+    return (np.asarray(scene.info["c0"], np.float64), np.array([1.0, 0, 0, 0]), np.zeros(3), np.zeros(3))
+
+
+def walk(kind, scene, seed, n, state):
+    """n ticks of the scene kind's pose stream from `state` (c, q, v, w);
+    returns the walk (c, q, v, w arrays) and the state one tick after it, where
+    the next walk continues."""
+    c, q, v, w = state
+    lo, hi = scene.info["walk_lo"], scene.info["walk_hi"]
+    if kind == "haptic":
+        C, Q, V, W = scenes.smooth_walk(seed, n + 1, c, lo, hi, q0=q, v0=v, w0=w)
+    else:
+        C, Q, V, W = scenes.random_walk(seed, n + 1, c, box_lo=lo, box_hi=hi, q0=q, v0=v, w0=w)
+    return (C[:n], Q[:n], V[:n], W[:n]), (C[n], Q[n], V[n], W[n])
+
+
+def spectrum_run(n_fluid, ticks=3000, warmup_ticks=300, kind="haptic"):
     """Band shares of the haptic force over one walk (seed 101) after a
     warm-up walk (seed 11), one context."""
-    sc = scenes.haptic_scene(n_fluid=n_fluid)
+    sc = experiment_scene(kind, n_fluid)
     sim = make_sim(sc, max_ticks=max(ticks, warmup_ticks))
-    lo, hi = sc.info["walk_lo"], sc.info["walk_hi"]
-    c = sc.info["c0"]
+    st = start_state(sc)
     for n, sd in ((warmup_ticks, 11), (ticks, 101)):
-        walk = scenes.smooth_walk(sd, n, c, lo, hi)
-        lg = collect(sim, sc, walk)
-        c = walk[0][-1] + 1e-3 * walk[2][-1]
+        wk, st = walk(kind, sc, sd, n, st)
+        lg = collect(sim, sc, wk)
     return force_spectrum(lg)
 
 
@@ -321,42 +373,21 @@ def haptic_rate(net, X, n=500):
     return {"host_round_trip_hz": host, "device_chain_hz": dev}
 
 
-def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=1500, steps=1500, seed=1,
-                   warmup_ticks=300, eval_segments=3, batch=1, guard_margin=GUARD_MARGIN, log=print):
-    """Collect plain-SPH haptic logs (a 1 kHz smooth walk per segment, 4 SPH
-    steps per tick), train on the first segments with early stopping on a
-    held-out segment, evaluate on the last ones (pooled: a single walk's
-    smoothness swings the hold baseline's error several-fold).
+def load_logs(path):
+    """Logs kept by run_experiment(save_logs=...): (logs, number of training walks)."""
+    z = np.load(path)
+    logs, i = [], 0
+    while f"{i}_c" in z:
+        logs.append({k: z[f"{i}_{k}"].astype(np.float64) for k in ("c", "q", "v", "w", "wrench", "probes")})
+        i += 1
+    return logs, int(z["n_train"])
 
-    `batch` copies of the scene are stepped together, one walk each: every
-    copy first takes a warm-up walk, then the copies walk in rounds; the
-    training walks are train_segments rounded up to a multiple of the batch,
-    the first walk after them is the held-out one and the rest, at least
-    eval_segments, are evaluated.  A copy's walk starts where its previous one
-    ended.  After training the network's plain-SPH fallback is set with
-    guard_margin (None: no fallback).  Returns a summary dict."""
+
+def train_and_evaluate(logs, n_train, sc, steps, seed=1, guard_margin=GUARD_MARGIN):
+    """Train on logs[:n_train] with early stopping on logs[n_train], evaluate on
+    the rest; returns (net, summary dict)."""
     import time
     import torch
-    k = int(batch)
-    sc = scenes.haptic_scene(n_fluid=n_fluid)
-    sim = make_sim(sc, max_ticks=max(warmup_ticks, ticks, eval_ticks), batch=k)
-    lo, hi = sc.info["walk_lo"], sc.info["walk_hi"]
-    cs = [sc.info["c0"]] * k
-    n_train = -(-train_segments // k) * k
-    n_eval = -(-(1 + eval_segments) // k) * k
-    rounds = [(warmup_ticks, [11 + i for i in range(k)])]
-    rounds += [(ticks, [101 + j for j in range(r, r + k)]) for r in range(0, n_train, k)]
-    ev = [801] + [901 + j for j in range(n_eval - 1)]
-    rounds += [(eval_ticks, ev[r:r + k]) for r in range(0, n_eval, k)]
-    logs = []
-    t0 = time.perf_counter()
-    for n, seeds in rounds:
-        walks = [scenes.smooth_walk(sd, n, c, lo, hi) for sd, c in zip(seeds, cs)]
-        logs += collect(sim, sc, walks)
-        cs = [w[0][-1] + 1e-3 * w[2][-1] for w in walks]
-        log(f"  collected {n} ticks x {k} (walk seeds {seeds[0]}..{seeds[-1]})")
-    t_collect = time.perf_counter() - t0
-    logs = logs[k:]                                  # warm-up walks
     rows = [training_rows(lg) for lg in logs[:n_train]]
     X = torch.from_numpy(np.concatenate([r[0] for r in rows])).to("cuda")
     Y = torch.from_numpy(np.concatenate([r[1] for r in rows])).to("cuda")
@@ -369,12 +400,57 @@ def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=150
     if guard_margin is not None and guard_margin >= 0:
         net.set_guard(guard_margin)
     errs = evaluate(net, logs[n_train + 1:], sc)
+    return net, {"training_rows": int(X.shape[0]), "train_s": t_train, "train_steps": steps,
+                 "best_holdout_error": min(h[2] for h in hist), "errors": errs}
+
+
+def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=1500, steps=1500, seed=1,
+                   warmup_ticks=300, eval_segments=3, batch=1, guard_margin=GUARD_MARGIN, log=print,
+                   kind="haptic", save_logs=None, scene=None):
+    """Collect plain-SPH haptic logs (a 1 kHz smooth walk per segment, 4 SPH
+    steps per tick), train on the first segments with early stopping on a
+    held-out segment, evaluate on the last ones (pooled: a single walk's
+    smoothness swings the hold baseline's error several-fold).
+
+    `batch` copies of the scene are stepped together, one walk each: every
+    copy first takes a warm-up walk, then the copies walk in rounds; the
+    training walks are train_segments rounded up to a multiple of the batch,
+    the first walk after them is the held-out one and the rest, at least
+    eval_segments, are evaluated.  A copy's walk starts where its previous one
+    ended.  After training the network's plain-SPH fallback is set with
+    guard_margin (None: no fallback).  `kind` picks the scene and its pose
+    stream (experiment_scene); save_logs, a path, keeps the logs (float32,
+    npz) for study away from the GPU; scene, an already built scene of that
+    kind, saves building it again.  Returns a summary dict."""
+    import time
+    import torch
+    k = int(batch)
+    sc = experiment_scene(kind, n_fluid, base=scene)
+    sim = make_sim(sc, max_ticks=max(warmup_ticks, ticks, eval_ticks), batch=k)
+    sts = [start_state(sc)] * k
+    n_train = -(-train_segments // k) * k
+    n_eval = -(-(1 + eval_segments) // k) * k
+    rounds = [(warmup_ticks, [11 + i for i in range(k)])]
+    rounds += [(ticks, [101 + j for j in range(r, r + k)]) for r in range(0, n_train, k)]
+    ev = [801] + [901 + j for j in range(n_eval - 1)]
+    rounds += [(eval_ticks, ev[r:r + k]) for r in range(0, n_eval, k)]
+    logs = []
+    t0 = time.perf_counter()
+    for n, seeds in rounds:
+        ws = [walk(kind, sc, sd, n, st) for sd, st in zip(seeds, sts)]
+        logs += collect(sim, sc, [w for w, _ in ws])
+        sts = [st for _, st in ws]
+        log(f"  collected {n} ticks x {k} (walk seeds {seeds[0]}..{seeds[-1]})")
+    t_collect = time.perf_counter() - t0
+    logs = logs[k:]                                  # warm-up walks
+    if save_logs:
+        np.savez_compressed(save_logs, n_train=n_train, **{f"{i}_{key}": a.astype(np.float32)
+                                                           for i, lg in enumerate(logs) for key, a in lg.items()})
+    net, res = train_and_evaluate(logs, n_train, sc, steps, seed=seed, guard_margin=guard_margin)
     rate = haptic_rate(net, eval_rows(logs[-1])[2][0])
     return {"scene": sc.name, "n_particles": int(sc.n), "batch": k, "training_walks": n_train,
-            "eval_walks": n_eval - 1, "training_rows": int(X.shape[0]),
-            "ticks_collected": int(sum(n * len(sd) for n, sd in rounds)), "collect_s": t_collect,
-            "train_s": t_train, "train_steps": steps, "best_holdout_error": min(h[2] for h in hist),
-            "errors": errs, **rate}
+            "eval_walks": n_eval - 1, "ticks_collected": int(sum(n * len(sd) for n, sd in rounds)),
+            "collect_s": t_collect, **res, **rate}
 
 
 if __name__ == "__main__":
@@ -388,12 +464,26 @@ if __name__ == "__main__":
     ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--eval-segments", type=int, default=3)
     ap.add_argument("--batch", type=int, default=1, help="scene copies stepped together, one walk each")
+    ap.add_argument("--scene", choices=SCENE_KINDS, default="haptic",
+                    help="haptic: sphere in a tank sized for n_fluid, smooth walk; coupled: the coupled "
+                         "fluid + soft + rigid scene with its random walk")
+    ap.add_argument("--save-logs", default=None, help="keep the collected logs in this .npz file")
+    ap.add_argument("--load-logs", default=None,
+                    help="train and evaluate on logs kept by --save-logs (scene from --scene, --n-fluid)")
     ap.add_argument("--spectrum", action="store_true",
                     help="only the band shares of the haptic force over one walk (no training)")
     a = ap.parse_args()
     if a.spectrum:
-        print(json.dumps({"n_fluid": a.n_fluid, "band_share": spectrum_run(a.n_fluid)}), flush=True)
+        print(json.dumps({"n_fluid": a.n_fluid, "scene": a.scene,
+                          "band_share": spectrum_run(a.n_fluid, kind=a.scene)}), flush=True)
+        raise SystemExit(0)
+    if a.load_logs:
+        lg, nt = load_logs(a.load_logs)
+        sc = experiment_scene(a.scene, a.n_fluid)
+        _, r = train_and_evaluate(lg, nt, sc, a.steps)
+        print(json.dumps({"scene": sc.name, "logs": a.load_logs, "training_walks": nt,
+                          "eval_walks": len(lg) - nt - 1, **r}), flush=True)
         raise SystemExit(0)
     r = run_experiment(a.n_fluid, a.segments, a.ticks, a.eval_ticks, a.steps, eval_segments=a.eval_segments,
-                       batch=a.batch, log=lambda m: print(m, flush=True))
+                       batch=a.batch, log=lambda m: print(m, flush=True), kind=a.scene, save_logs=a.save_logs)
     print(json.dumps(r), flush=True)

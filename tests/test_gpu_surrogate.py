@@ -1,12 +1,12 @@
 """The learned wrench surrogate end to end on the GPU: plain-SPH haptic logs
 of the 100k-particle haptic scene (a 1 kHz hand-like walk of the grabbed
 sphere, 4 SPH steps per tick, 40 ms haptic rolling mean), training by the
-library's own forward/backward/Adam kernels, and the gain over the haptic
-loop without the network (zero-order hold of the 100 Hz SPH wrench, and the
-hold followed by a rolling mean) on fifteen walks it never saw, judged
-against plain SPH at every tick, with the haptic loop's plain-SPH fallback
-outside the training range.  The logs come from sixteen copies of the scene
-stepped together, one walk each."""
+library's own forward/backward/Adam kernels, and the error against plain SPH
+at every tick between 100 Hz SPH updates, on fifteen walks it never saw,
+beside the haptic loop without the network (zero-order hold of the SPH
+wrench, and the hold followed by a rolling mean) and with the haptic loop's
+plain-SPH fallback outside the training range.  The logs come from sixteen
+copies of the scene stepped together, one walk each."""
 import numpy as np
 import pytest
 
@@ -43,28 +43,26 @@ def test_batched_collection_equals_one_context_per_walk():
     assert not np.array_equal(got[0]["wrench"], got[1]["wrench"])
 
 
-def test_surrogate_beats_hold_between_sph_updates():
+def test_surrogate_within_5_percent_between_sph_updates():
     import torch
     assert torch.cuda.is_available(), "GPU tests need a visible GPU"
     from paper_2511_15908_amd import surrogate as S
-    r = S.run_experiment(train_segments=16, ticks=1500, eval_ticks=1000, eval_segments=15, steps=1500, batch=16,
+    r = S.run_experiment(batch=16, train_segments=32, ticks=3000, eval_ticks=1500, eval_segments=15, steps=3000,
                          log=lambda m: print(m, flush=True))
-    assert r["training_walks"] == 16 and r["eval_walks"] == 15
+    assert r["training_walks"] == 32 and r["eval_walks"] == 15
     e = r["errors"]
     print({k: round(v["mean"], 4) for k, v in e.items()}, "p95",
           {k: round(v["p95"], 4) for k, v in e.items()},
-          f"rates {r['host_round_trip_hz']:.0f} Hz host, {r['device_chain_hz']:.0f} Hz device")
-    # pooled over fifteen walks: the hold's error swings several-fold with a
-    # walk's smoothness, the surrogate's on a walk that leaves the states the
-    # training walks covered; it must beat both baselines on the mean and the
-    # hold clearly on the tail
+          f"rates {r['host_round_trip_hz']:.0f} Hz host, {r['device_chain_hz']:.0f} Hz device",
+          "fallback rows", e["surrogate"]["fallback_frac"])
+    # the target of Sec. 3.3's haptic loop: within 5 % of plain SPH at 1 kHz
+    assert e["surrogate"]["mean"] <= 0.05
+    # pooled over fifteen walks, well below both baselines on the mean and the tail
     base = min(e["zero_order_hold"]["mean"], e["hold_rolling_mean"]["mean"])
-    assert e["surrogate"]["mean"] < base
+    assert e["surrogate"]["mean"] < 0.85 * base
     assert e["surrogate"]["p95"] < 0.85 * e["zero_order_hold"]["p95"]
-    # the plain-SPH fallback takes the walks that leave the training range
-    # and costs little elsewhere: the loop beats the network alone, and the
-    # network still serves most ticks
-    print("network only", round(e["network_only"]["mean"], 4), "fallback rows", e["surrogate"]["fallback_frac"])
-    assert e["surrogate"]["mean"] < e["network_only"]["mean"]
-    assert e["surrogate"]["fallback_frac"] < 0.25
+    # the plain-SPH fallback serves the rows outside the training range and
+    # costs little elsewhere; the network serves most ticks
+    assert e["surrogate"]["mean"] <= 1.02 * e["network_only"]["mean"]
+    assert e["surrogate"]["fallback_frac"] < 0.05
     assert r["host_round_trip_hz"] > 1000.0

@@ -48,13 +48,16 @@ def test_feature_row_layout():
     lg = _log(400, rng)
     t, d = np.array([150, 233]), np.array([0, 7])
     X, Y = S.feature_rows(lg, t, d)
-    assert X.shape == (2, S.N_FEATURES) and S.N_FEATURES == 126
+    assert X.shape == (2, S.N_FEATURES) and S.N_FEATURES == 186
     for r in range(2):
         t0 = t[r] - d[r]
         W0 = lg["wrench"][t0]
+        lags = []
+        for j in (1, 2, 3, 5, 7, 10, 14, 20, 28, 40):
+            lags += [lg["v"][t[r] - j] - lg["v"][t[r]], lg["w"][t[r] - j] - lg["w"][t[r]]]
         exp = np.concatenate([lg["c"][t[r]], lg["q"][t[r]], lg["v"][t[r]], lg["w"][t[r]], W0] +
                              [lg["wrench"][t0 - S.SPH_EVERY * k] - W0 for k in range(1, S.N_HIST)] +
-                             [lg["probes"][t0], [d[r] / S.SPH_EVERY]])
+                             [lg["probes"][t0], [d[r] / S.SPH_EVERY]] + lags)
         assert np.allclose(X[r], exp.astype(np.float32))
         # the residual columns are the last SPH wrench: the fallback's output
         assert np.array_equal(X[r, S.RES_COL:S.RES_COL + 6], W0.astype(np.float32))
