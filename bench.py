@@ -44,12 +44,13 @@ LANE_OPS_FORCE_PAIR = 45
 FLOP_DENSITY_PAIR = 17
 FLOP_FORCE_PAIR = 49
 # Compulsory HBM bytes per particle of the memory-bound phases (FP32 SoA,
-# unfused): keys 12 + 4; two 8-bit radix passes 2 x (8 + 8) + histograms;
-# reorder perm 4 + 32 + 32 + inverse 4 + cell bounds 6; integrate 40 + 24.
-# The whole step, neighbour sums included (their compulsory traffic: 24 and
-# 48), is 264 bytes per particle.
-HBM_BYTES_PER_PARTICLE = {"keys": 16, "sort": 34, "reorder": 78, "integrate": 64}
-HBM_BYTES_STEP_PER_PARTICLE = 264
+# unfused): keys 12 + key 4 + arrival rank 4; counting sort: scatter 8 + 4
+# (the slot scan adds 16 B per slot, under 1 B per particle at 1M);
+# reorder arrived 4 + key 4 + 32 + 32 + inverse 4 + cell bounds 6;
+# integrate 40 + 24.  The whole step, neighbour sums included (their
+# compulsory traffic: 24 and 48), is 250 bytes per particle.
+HBM_BYTES_PER_PARTICLE = {"keys": 20, "sort": 12, "reorder": 82, "integrate": 64}
+HBM_BYTES_STEP_PER_PARTICLE = 250
 
 
 def parse():

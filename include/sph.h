@@ -88,7 +88,7 @@ typedef struct {
     uint32_t abi_version;      /* must be SPH_ABI_VERSION */
     int32_t precision;         /* sph_precision of particle arithmetic; the wrench is always FP64 */
     uint32_t flags;            /* SPH_FLAG_* */
-    uint32_t smoothing_window; /* K >= 1 samples in the rolling average (Sec. 3.3, "tens" of cycles) */
+    uint32_t smoothing_window; /* K >= 1 samples in the rolling average (Sec. 3.3: some tens of cycles) */
     double h;                  /* smoothing length; kernel support is 2h (Eq. kernel) [m] */
     double rho0;               /* rest density (Eq. pressure) [kg/m^3] */
     double k_pressure;         /* pressure constant k (Eq. pressure) [m^2/s^2] */

@@ -3,11 +3,11 @@
 //    parent transform (Sec. 3.2); the pose comes from the haptic device
 //    (Sec. 3.3, Fig. 1);
 //  - body wrench: the particles' point forces summed into the parent's force
-//    and torque (Sec. 3.2, Alg. 2 "resolve new rigid forces"), reduced in
+//    and torque (Sec. 3.2, Alg. 2: the rigid-force step), reduced in
 //    binary64 with a fixed wavefront-shuffle tree (deterministic), pushed into
 //    the rolling-average ring of Sec. 3.3;
 //  - soft bodies: mass-spring forces through a spring lookup table (Sec. 3.2,
-//    Alg. 2 "apply soft body forces from springs");
+//    Alg. 2: the spring-force step);
 //  - semi-implicit Euler (Eq. euler) for fluid and soft particles.
 #include "sph_internal.h"
 

@@ -60,12 +60,17 @@ struct Nbhd {
 // dispatched round-robin over the 8 XCDs: within each full group of 512
 // cells every XCD gets a run of 64 consecutive cells, so that neighbouring
 // cells share its L2; the tail group keeps list order.
+#ifndef SPH_XCD_RUN
+#define SPH_XCD_RUN 64
+#endif
+constexpr uint32_t kXcdRun = SPH_XCD_RUN;            // consecutive cells per XCD (power of two)
 __device__ __forceinline__ uint32_t list_pos(uint32_t i, uint32_t ncell)
 {
-    const uint32_t full = ncell & ~511u;
+    constexpr uint32_t G = 8u * kXcdRun;
+    const uint32_t full = ncell - ncell % G;
     if (i >= full) return i;
-    const uint32_t grp = i >> 9, r = i & 511u;
-    return (grp << 9) + (r & 7u) * 64u + (r >> 3);
+    const uint32_t grp = i / G, r = i % G;
+    return grp * G + (r & 7u) * kXcdRun + (r >> 3);
 }
 
 // --- cross-lane moves by DPP (gfx9): row_shr:n reads lane i - n of the same

@@ -383,11 +383,52 @@ def load_logs(path):
     return logs, int(z["n_train"])
 
 
-def train_and_evaluate(logs, n_train, sc, steps, seed=1, guard_margin=GUARD_MARGIN):
+def write_logs(path, logs, n_train):
+    np.savez_compressed(path, n_train=n_train, **{f"{i}_{key}": a.astype(np.float32)
+                                                 for i, lg in enumerate(logs) for key, a in lg.items()})
+
+
+def merge_logs(out, paths):
+    """Pool the logs of several runs (made with different walk_seed0): every
+    run's training walks train, the first run's held-out walk stays the
+    held-out walk, and every other walk (the other runs' held-out walks
+    included) is evaluated."""
+    train, hold, ev = [], None, []
+    for p in paths:
+        lg, nt = load_logs(p)
+        train += lg[:nt]
+        if hold is None:
+            hold, ev = lg[nt], ev + lg[nt + 1:]
+        else:
+            ev += lg[nt:]
+    write_logs(out, train + [hold] + ev, len(train))
+    return len(train), len(ev)
+
+
+def second_stage(log, n=HAPTIC_WINDOW // 4):
+    """A copy of the log whose haptic wrench passes a second rolling mean over
+    the last n ticks (partial at the walk's start): the two boxcars make a
+    triangular window twice as long, which damps the band the 100 Hz updates
+    cannot follow far more than one boxcar does."""
+    W = log["wrench"]
+    c = np.concatenate([np.zeros((1, W.shape[1])), np.cumsum(W, 0)])
+    t = np.arange(W.shape[0])
+    lo = np.maximum(t + 1 - n, 0)
+    out = dict(log)
+    out["wrench"] = (c[t + 1] - c[lo]) / (t + 1 - lo)[:, None]
+    return out
+
+
+def train_and_evaluate(logs, n_train, sc, steps, seed=1, guard_margin=GUARD_MARGIN, stages=1):
     """Train on logs[:n_train] with early stopping on logs[n_train], evaluate on
-    the rest; returns (net, summary dict)."""
+    the rest (with stages = 2 the haptic wrench of every log passes a second
+    rolling mean first); returns (net, summary dict)."""
     import time
     import torch
+    if stages == 2:
+        logs = [second_stage(lg) for lg in logs]
+    elif stages != 1:
+        raise ValueError("stages must be 1 or 2")
     rows = [training_rows(lg) for lg in logs[:n_train]]
     X = torch.from_numpy(np.concatenate([r[0] for r in rows])).to("cuda")
     Y = torch.from_numpy(np.concatenate([r[1] for r in rows])).to("cuda")
@@ -406,7 +447,7 @@ def train_and_evaluate(logs, n_train, sc, steps, seed=1, guard_margin=GUARD_MARG
 
 def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=1500, steps=1500, seed=1,
                    warmup_ticks=300, eval_segments=3, batch=1, guard_margin=GUARD_MARGIN, log=print,
-                   kind="haptic", save_logs=None, scene=None):
+                   kind="haptic", save_logs=None, scene=None, walk_seed0=0):
     """Collect plain-SPH haptic logs (a 1 kHz smooth walk per segment, 4 SPH
     steps per tick), train on the first segments with early stopping on a
     held-out segment, evaluate on the last ones (pooled: a single walk's
@@ -421,7 +462,8 @@ def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=150
     guard_margin (None: no fallback).  `kind` picks the scene and its pose
     stream (experiment_scene); save_logs, a path, keeps the logs (float32,
     npz) for study away from the GPU; scene, an already built scene of that
-    kind, saves building it again.  Returns a summary dict."""
+    kind, saves building it again; walk_seed0 shifts every walk seed (runs
+    whose logs are pooled).  Returns a summary dict."""
     import time
     import torch
     k = int(batch)
@@ -430,9 +472,10 @@ def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=150
     sts = [start_state(sc)] * k
     n_train = -(-train_segments // k) * k
     n_eval = -(-(1 + eval_segments) // k) * k
-    rounds = [(warmup_ticks, [11 + i for i in range(k)])]
-    rounds += [(ticks, [101 + j for j in range(r, r + k)]) for r in range(0, n_train, k)]
-    ev = [801] + [901 + j for j in range(n_eval - 1)]
+    w0 = int(walk_seed0)
+    rounds = [(warmup_ticks, [w0 + 11 + i for i in range(k)])]
+    rounds += [(ticks, [w0 + 101 + j for j in range(r, r + k)]) for r in range(0, n_train, k)]
+    ev = [w0 + 801] + [w0 + 901 + j for j in range(n_eval - 1)]
     rounds += [(eval_ticks, ev[r:r + k]) for r in range(0, n_eval, k)]
     logs = []
     t0 = time.perf_counter()
@@ -444,8 +487,7 @@ def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=150
     t_collect = time.perf_counter() - t0
     logs = logs[k:]                                  # warm-up walks
     if save_logs:
-        np.savez_compressed(save_logs, n_train=n_train, **{f"{i}_{key}": a.astype(np.float32)
-                                                           for i, lg in enumerate(logs) for key, a in lg.items()})
+        write_logs(save_logs, logs, n_train)
     net, res = train_and_evaluate(logs, n_train, sc, steps, seed=seed, guard_margin=guard_margin)
     rate = haptic_rate(net, eval_rows(logs[-1])[2][0])
     return {"scene": sc.name, "n_particles": int(sc.n), "batch": k, "training_walks": n_train,
@@ -468,6 +510,11 @@ if __name__ == "__main__":
                     help="haptic: sphere in a tank sized for n_fluid, smooth walk; coupled: the coupled "
                          "fluid + soft + rigid scene with its random walk")
     ap.add_argument("--save-logs", default=None, help="keep the collected logs in this .npz file")
+    ap.add_argument("--walk-seed0", type=int, default=0, help="shift of every walk seed (runs pooled later)")
+    ap.add_argument("--haptic-stages", type=int, default=1, choices=(1, 2),
+                    help="2: the haptic wrench passes a second rolling mean over 40 ticks (with --load-logs)")
+    ap.add_argument("--merge-logs", nargs="+", default=None, metavar="PATH",
+                    help="OUT IN1 IN2 ...: pool the logs of several runs into OUT (no GPU work)")
     ap.add_argument("--load-logs", default=None,
                     help="train and evaluate on logs kept by --save-logs (scene from --scene, --n-fluid)")
     ap.add_argument("--spectrum", action="store_true",
@@ -477,13 +524,19 @@ if __name__ == "__main__":
         print(json.dumps({"n_fluid": a.n_fluid, "scene": a.scene,
                           "band_share": spectrum_run(a.n_fluid, kind=a.scene)}), flush=True)
         raise SystemExit(0)
+    if a.merge_logs:
+        nt, ne = merge_logs(a.merge_logs[0], a.merge_logs[1:])
+        print(json.dumps({"merged": a.merge_logs[0], "training_walks": nt, "eval_walks": ne}), flush=True)
+        raise SystemExit(0)
     if a.load_logs:
         lg, nt = load_logs(a.load_logs)
         sc = experiment_scene(a.scene, a.n_fluid)
-        _, r = train_and_evaluate(lg, nt, sc, a.steps)
-        print(json.dumps({"scene": sc.name, "logs": a.load_logs, "training_walks": nt,
+        _, r = train_and_evaluate(lg, nt, sc, a.steps, stages=a.haptic_stages)
+        print(json.dumps({"scene": sc.name, "logs": a.load_logs, "haptic_stages": a.haptic_stages,
+                          "training_walks": nt,
                           "eval_walks": len(lg) - nt - 1, **r}), flush=True)
         raise SystemExit(0)
     r = run_experiment(a.n_fluid, a.segments, a.ticks, a.eval_ticks, a.steps, eval_segments=a.eval_segments,
-                       batch=a.batch, log=lambda m: print(m, flush=True), kind=a.scene, save_logs=a.save_logs)
+                       batch=a.batch, log=lambda m: print(m, flush=True), kind=a.scene, save_logs=a.save_logs,
+                       walk_seed0=a.walk_seed0)
     print(json.dumps(r), flush=True)

@@ -104,3 +104,14 @@ def test_force_spectrum_bands():
         share = S.force_spectrum({"wrench": W})
         assert share[band] > 0.999, (f, share)
         assert abs(sum(share.values()) - 1.0) < 1e-9
+
+
+def test_second_stage_is_a_rolling_mean_of_the_haptic_wrench():
+    rng = np.random.default_rng(6)
+    lg = _log(300, rng)
+    out = S.second_stage(lg, n=40)
+    W = lg["wrench"]
+    for t in (0, 5, 39, 40, 299):
+        assert np.allclose(out["wrench"][t], W[max(0, t - 39):t + 1].mean(0), rtol=1e-12, atol=1e-12)
+    assert out["c"] is lg["c"] and np.array_equal(lg["wrench"], W)     # the input log is not changed
+
