@@ -1,5 +1,6 @@
 """Edge cases of the HIP path through the C ABI: empty and tiny scenes,
-closed-form free fall, cells far above 64 particles, particles outside the
+closed-form free fall, cells far above 64 particles (and above the
+reorder's LDS staging), a sparse grid of 2^24 key slots, particles outside the
 grid, neighbourhood capacity overflow, the instability flag, the
 alternative-reading flags, a non-default stream, argument errors."""
 import numpy as np
@@ -95,6 +96,30 @@ def test_overfull_cell(gpu, orc, prec):
     sc = _scene(x, v, precision=prec)
     tol = (1e-5, 1e-4) if prec == "f32" else (1e-13, 1e-12)
     _compare_one_step(gpu, orc, sc, prec, *tol)
+
+
+def test_crowded_cell_beyond_reorder_staging(gpu, orc):
+    """2,500 particles in one grid cell: the reorder ranks them against their
+    cell slice in global memory (the slice does not fit its LDS staging) and
+    the neighbourhood still fits the candidate capacity; FP64, one step."""
+    from paper_2511_15908_amd import scenes
+    rng = scenes.SplitMix64(8, 9)
+    x = (rng.uniform(7500).reshape(2500, 3) - 0.5) * 0.035 - 0.02    # inside the cell [-0.04, 0.0002)^3
+    sc = _scene(x, precision="f64", mass=1e-5)
+    _compare_one_step(gpu, orc, sc, "f64", 1e-13, 1e-12)
+
+
+def test_huge_sparse_grid(gpu, orc):
+    """A domain of 220 cells per axis (2^24 key slots, 16,384 scan tiles: the
+    slot scan takes its three-kernel path) holding a few hundred particles,
+    some of them alone in far cells."""
+    from paper_2511_15908_amd import scenes
+    rng = scenes.SplitMix64(9, 9)
+    near = (rng.uniform(900).reshape(300, 3) - 0.5) * 0.2
+    far = np.array([[4.0, -4.0, 3.9], [4.01, -4.0, 3.9], [-4.3, 4.2, -4.35], [2.0, 2.0, -3.0]])
+    sc = _scene(np.concatenate([near, far]), lo=(-4.4,) * 3, hi=(4.4,) * 3)
+    sim = _compare_one_step(gpu, orc, sc, "f32", 1e-5, 1e-4)
+    assert sim.info()["cell_slots"] == 1 << 24
 
 
 def test_particles_outside_grid(gpu, orc):
