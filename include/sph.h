@@ -3,8 +3,9 @@
  *
  * One simulation step follows the paper's simulation loop (arXiv 2511.15908,
  * Alg. 2 and Sec. 3.2): rigid-body particles are re-placed from their parent
- * transform, a uniform-grid spatial hash orders the particles (here a Morton
- * cell-key radix sort with reorder and cell-start tables), soft-body spring
+ * transform, a uniform-grid spatial hash orders the particles (here a
+ * counting sort by Morton cell slot with reorder and cell start/end tables),
+ * soft-body spring
  * forces are applied, then the SPH density/pressure pass and the force pass of
  * Alg. 1 run over the neighbours, the point forces on each grabbed body are
  * reduced into a force and torque (Sec. 3.2, Sec. 3.3), and fluid and soft
