@@ -403,8 +403,10 @@ def main():
         log("surrogate leg: the coupled scene itself (1M fluid, soft cube, sphere on its random walk), "
             "a short run: 4 training walks ...", a.quiet)
         r = S.run_experiment(kind="coupled", scene=sc, train_segments=4, ticks=2000, eval_ticks=1000,
-                             eval_segments=2, steps=2000, warmup_ticks=200, log=lambda m: log(m, a.quiet))
+                             eval_segments=2, steps=2000, warmup_ticks=200, log=lambda m: log(m, a.quiet),
+                             two_stages=True)
         e = r["errors"]
+        e2 = r["two_stages"]["errors"]
         out["surrogate_coupled_1m"] = {
             "scene": r["scene"], "n_particles": r["n_particles"], "walk": "Ornstein-Uhlenbeck, 1 kHz",
             "sph_update_hz": 100, "haptic_hz": 1000,
@@ -412,6 +414,9 @@ def main():
             "error_p95": {k: round(v["p95"], 4) for k, v in e.items()},
             "eval_walks": r["eval_walks"],
             "fallback": {"margin": S.GUARD_MARGIN, "rows_frac": round(e["surrogate"].get("fallback_frac", 0.0), 4)},
+            # the same logs with a second 40-tick rolling mean in the haptic loop
+            "two_rolling_means": {"error_vs_plain_sph": {k: round(v["mean"], 4) for k, v in e2.items()},
+                                  "error_p95": {k: round(v["p95"], 4) for k, v in e2.items()}},
             "training": {"walks": r["training_walks"], "rows": r["training_rows"], "steps": r["train_steps"],
                          "ticks_simulated": r["ticks_collected"], "collect_seconds": round(r["collect_s"], 1)}}
     log(json.dumps(out, indent=1), a.quiet)

@@ -447,7 +447,7 @@ def train_and_evaluate(logs, n_train, sc, steps, seed=1, guard_margin=GUARD_MARG
 
 def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=1500, steps=1500, seed=1,
                    warmup_ticks=300, eval_segments=3, batch=1, guard_margin=GUARD_MARGIN, log=print,
-                   kind="haptic", save_logs=None, scene=None, walk_seed0=0):
+                   kind="haptic", save_logs=None, scene=None, walk_seed0=0, two_stages=False):
     """Collect plain-SPH haptic logs (a 1 kHz smooth walk per segment, 4 SPH
     steps per tick), train on the first segments with early stopping on a
     held-out segment, evaluate on the last ones (pooled: a single walk's
@@ -463,7 +463,9 @@ def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=150
     stream (experiment_scene); save_logs, a path, keeps the logs (float32,
     npz) for study away from the GPU; scene, an already built scene of that
     kind, saves building it again; walk_seed0 shifts every walk seed (runs
-    whose logs are pooled).  Returns a summary dict."""
+    whose logs are pooled); two_stages also trains and evaluates a second
+    network on the same logs with the haptic wrench passed through a second
+    rolling mean (summary under "two_stages").  Returns a summary dict."""
     import time
     import torch
     k = int(batch)
@@ -490,9 +492,13 @@ def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=150
         write_logs(save_logs, logs, n_train)
     net, res = train_and_evaluate(logs, n_train, sc, steps, seed=seed, guard_margin=guard_margin)
     rate = haptic_rate(net, eval_rows(logs[-1])[2][0])
-    return {"scene": sc.name, "n_particles": int(sc.n), "batch": k, "training_walks": n_train,
-            "eval_walks": n_eval - 1, "ticks_collected": int(sum(n * len(sd) for n, sd in rounds)),
-            "collect_s": t_collect, **res, **rate}
+    out = {"scene": sc.name, "n_particles": int(sc.n), "batch": k, "training_walks": n_train,
+           "eval_walks": n_eval - 1, "ticks_collected": int(sum(n * len(sd) for n, sd in rounds)),
+           "collect_s": t_collect, **res, **rate}
+    if two_stages:
+        out["two_stages"] = train_and_evaluate(logs, n_train, sc, steps, seed=seed, guard_margin=guard_margin,
+                                               stages=2)[1]
+    return out
 
 
 if __name__ == "__main__":
