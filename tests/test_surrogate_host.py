@@ -115,3 +115,36 @@ def test_second_stage_is_a_rolling_mean_of_the_haptic_wrench():
         assert np.allclose(out["wrench"][t], W[max(0, t - 39):t + 1].mean(0), rtol=1e-12, atol=1e-12)
     assert out["c"] is lg["c"] and np.array_equal(lg["wrench"], W)     # the input log is not changed
 
+
+def test_walks_continue_where_the_previous_one_ended():
+    """A segment's pose stream starts from the state one tick after the
+    previous segment (position, orientation and velocities carried over)."""
+    import types
+    sc = types.SimpleNamespace(info={"c0": np.array([0.3, 0.25, 0.25]), "walk_lo": (0.12, 0.12, 0.12),
+                                     "walk_hi": (0.43, 0.38, 0.40)})
+    for kind in ("haptic", "coupled"):
+        st0 = S.start_state(sc)
+        (C, Q, V, W), st1 = S.walk(kind, sc, 7, 50, st0)
+        assert C.shape == (50, 3) and np.array_equal(C[0], st0[0]) and np.array_equal(Q[0], st0[1])
+        (C2, Q2, V2, W2), _ = S.walk(kind, sc, 8, 20, st1)
+        for a, b in zip((C2[0], Q2[0], V2[0], W2[0]), st1):
+            assert np.array_equal(a, b)
+        # one tick after the last sample of the first walk: a small step, not a jump
+        assert np.linalg.norm(C2[0] - C[-1]) < 1e-3 * 5.0 and abs(abs(Q2[0] @ Q[-1]) - 1.0) < 1e-4
+
+
+def test_merge_logs_pools_training_walks(tmp_path):
+    rng = np.random.default_rng(9)
+    a = [_log(120, rng) for _ in range(5)]     # 3 training, 1 held out, 1 evaluated
+    b = [_log(120, rng) for _ in range(4)]     # 2 training, then 2 evaluated
+    S.write_logs(tmp_path / "a.npz", a, 3)
+    S.write_logs(tmp_path / "b.npz", b, 2)
+    nt, ne = S.merge_logs(tmp_path / "m.npz", [tmp_path / "a.npz", tmp_path / "b.npz"])
+    assert (nt, ne) == (5, 3)
+    logs, n_train = S.load_logs(tmp_path / "m.npz")
+    assert n_train == 5 and len(logs) == 9
+    order = a[:3] + b[:2] + [a[3]] + [a[4]] + b[2:]
+    for got, want in zip(logs, order):
+        for k in want:
+            assert np.array_equal(got[k], want[k].astype(np.float32).astype(np.float64))
+
