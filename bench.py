@@ -400,6 +400,9 @@ def main():
             "training": {"walks": r["training_walks"], "rows": r["training_rows"], "steps": r["train_steps"],
                          "seconds": round(r["train_s"], 2), "scene_copies_stepped_together": r["batch"],
                          "ticks_simulated": r["ticks_collected"], "collect_seconds": round(r["collect_s"], 1)}}
+        log("haptic chain at 1 kHz while plain SPH runs on the same GPU (100k haptic scene) ...", a.quiet)
+        out["surrogate"]["haptic_under_sph_load"] = S.haptic_under_load("haptic", 100_000, seconds=2.0,
+                                                                        log=lambda m: log(m, a.quiet))
         log("surrogate leg: the coupled scene itself (1M fluid, soft cube, sphere on its random walk), "
             "a short run: 4 training walks ...", a.quiet)
         r = S.run_experiment(kind="coupled", scene=sc, train_segments=4, ticks=2000, eval_ticks=1000,
@@ -418,7 +421,9 @@ def main():
             "two_rolling_means": {"error_vs_plain_sph": {k: round(v["mean"], 4) for k, v in e2.items()},
                                   "error_p95": {k: round(v["p95"], 4) for k, v in e2.items()}},
             "training": {"walks": r["training_walks"], "rows": r["training_rows"], "steps": r["train_steps"],
-                         "ticks_simulated": r["ticks_collected"], "collect_seconds": round(r["collect_s"], 1)}}
+                         "ticks_simulated": r["ticks_collected"], "collect_seconds": round(r["collect_s"], 1)},
+            "haptic_under_sph_load": S.haptic_under_load("coupled", a.n_fluid, seconds=2.0, scene=sc,
+                                                         log=lambda m: log(m, a.quiet))}
     log(json.dumps(out, indent=1), a.quiet)
     if not a.no_cpu_baseline:
         log("timing the CPU oracle (same scene, all threads and one thread; FP64 dam break) ...", a.quiet)

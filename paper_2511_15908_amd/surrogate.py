@@ -445,6 +445,100 @@ def train_and_evaluate(logs, n_train, sc, steps, seed=1, guard_margin=GUARD_MARG
                  "best_holdout_error": min(h[2] for h in hist), "errors": errs}
 
 
+def haptic_under_load(kind="haptic", n_fluid=100_000, seconds=2.0, scene=None, seed=1, log=print):
+    """The 1 kHz haptic chain and plain SPH on one GPU at the same time, on two
+    streams of default priority: a host thread keeps SPH steps of the scene
+    queued on one stream (4 per tick, at most ~40 steps ahead) while the
+    haptic loop, paced by the wall clock at 1 ms, runs the one-workgroup
+    network chain on the other (features in, wrench out, its own stream
+    synchronised) with the plain-SPH fallback off, so every tick runs the
+    whole network.  Reports the chain's latency alone and under load, the
+    ticks whose latency exceeded the 1 ms period, and the SPH step rate alone
+    and under the haptic load."""
+    import threading
+    import time
+    import torch
+    from ._binding import Sim
+    sc = experiment_scene(kind, n_fluid, base=scene)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    sim = Sim(sc, stream=sa)
+    with torch.cuda.stream(sb):
+        net = make_net(seed=seed, max_batch=256)
+        rng = scenes.SplitMix64(seed, P_BATCH + 1)
+        X = torch.from_numpy(rng.normal(256 * N_FEATURES).reshape(256, N_FEATURES).astype(np.float32)).cuda()
+        Y = torch.from_numpy(rng.normal(256 * 6).reshape(256, 6).astype(np.float32)).cuda()
+        net.fit_normalizer(X, Y)
+        net.set_guard(-1.0)
+    xs = X.cpu().numpy()
+
+    def chain_latency(n):
+        lat = np.empty(n)
+        for k in range(n):
+            t0 = time.perf_counter()
+            net.predict_one(xs[k % xs.shape[0]])
+            lat[k] = time.perf_counter() - t0
+        return lat
+
+    chain_latency(50)
+    idle = chain_latency(500)
+    # SPH alone
+    sim.step(40)
+    sa.synchronize()
+    t0 = time.perf_counter()
+    sim.step(200)
+    sa.synchronize()
+    sph_alone = 200 / (time.perf_counter() - t0)
+    # both at once
+    stop = threading.Event()
+    done = [0]
+
+    def sph_worker():
+        evs = []
+        while not stop.is_set():
+            sim.step(4)
+            e = torch.cuda.Event()
+            e.record(sa)
+            evs.append(e)
+            done[0] += 4
+            if len(evs) > 10:                 # keep about 40 steps queued
+                evs.pop(0).synchronize()
+        sa.synchronize()
+
+    th = threading.Thread(target=sph_worker)
+    th.start()
+    time.sleep(0.2)                           # let the SPH queue fill
+    n_ticks = int(seconds * 1000)
+    lat = np.empty(n_ticks)
+    late = 0
+    steps0, t_start = done[0], time.perf_counter()
+    for k in range(n_ticks):
+        due = t_start + 1e-3 * k
+        rest = due - time.perf_counter()
+        if rest > 3e-4:
+            time.sleep(rest - 3e-4)               # sleeping lets the SPH thread run
+        while time.perf_counter() < due:
+            pass
+        t0 = time.perf_counter()
+        net.predict_one(xs[k % xs.shape[0]])
+        lat[k] = time.perf_counter() - t0
+        late += int(t0 + lat[k] > due + 1e-3)
+    wall = time.perf_counter() - t_start
+    steps = done[0] - steps0
+    stop.set()
+    th.join()
+    us = lambda a, q: round(float(np.percentile(a, q)) * 1e6, 1)   # noqa: E731
+    r = {"scene": sc.name, "n_particles": int(sc.n), "ticks": n_ticks,
+         "chain_latency_us_alone": {"p50": us(idle, 50), "p99": us(idle, 99), "max": round(float(idle.max()) * 1e6, 1)},
+         "chain_latency_us_under_sph": {"p50": us(lat, 50), "p99": us(lat, 99),
+                                        "max": round(float(lat.max()) * 1e6, 1)},
+         "ticks_past_their_1ms_period": late, "haptic_hz_achieved": round(n_ticks / wall, 1),
+         "sph_steps_per_s_alone": round(sph_alone, 1), "sph_steps_per_s_with_haptic": round(steps / wall, 1)}
+    log(f"  haptic chain under SPH load: {r}")
+    sim.close()
+    net.close()
+    return r
+
+
 def run_experiment(n_fluid=100_000, train_segments=4, ticks=3000, eval_ticks=1500, steps=1500, seed=1,
                    warmup_ticks=300, eval_segments=3, batch=1, guard_margin=GUARD_MARGIN, log=print,
                    kind="haptic", save_logs=None, scene=None, walk_seed0=0, two_stages=False):
@@ -519,6 +613,8 @@ if __name__ == "__main__":
     ap.add_argument("--walk-seed0", type=int, default=0, help="shift of every walk seed (runs pooled later)")
     ap.add_argument("--haptic-stages", type=int, default=1, choices=(1, 2),
                     help="2: the haptic wrench passes a second rolling mean over 40 ticks (with --load-logs)")
+    ap.add_argument("--under-load", action="store_true",
+                    help="only time the 1 kHz haptic chain while plain SPH runs on the same GPU")
     ap.add_argument("--merge-logs", nargs="+", default=None, metavar="PATH",
                     help="OUT IN1 IN2 ...: pool the logs of several runs into OUT (no GPU work)")
     ap.add_argument("--load-logs", default=None,
@@ -529,6 +625,9 @@ if __name__ == "__main__":
     if a.spectrum:
         print(json.dumps({"n_fluid": a.n_fluid, "scene": a.scene,
                           "band_share": spectrum_run(a.n_fluid, kind=a.scene)}), flush=True)
+        raise SystemExit(0)
+    if a.under_load:
+        print(json.dumps(haptic_under_load(a.scene, a.n_fluid, log=lambda m: print(m, flush=True))), flush=True)
         raise SystemExit(0)
     if a.merge_logs:
         nt, ne = merge_logs(a.merge_logs[0], a.merge_logs[1:])
