@@ -51,6 +51,9 @@ FLOP_FORCE_PAIR = 49
 # compulsory traffic: 24 and 48), is 250 bytes per particle.
 HBM_BYTES_PER_PARTICLE = {"keys": 20, "sort": 12, "reorder": 82, "integrate": 64}
 HBM_BYTES_STEP_PER_PARTICLE = 250
+# Kernel times come from HIP events on every PROFILE_EVERY-th timed step
+# (the event records cost a few microseconds each, two per phase).
+PROFILE_EVERY = 4
 
 
 def parse():
@@ -297,7 +300,7 @@ def main():
     sim.synchronize()
     torch.cuda.synchronize()
     s0 = sim.stats()
-    sim.profile_begin(a.steps)
+    sim.profile_begin(a.steps, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run(a.warmup, a.steps)
@@ -321,6 +324,7 @@ def main():
     roof = {"bound": "alu", "kernel": f"k_{dom}", "achieved": round(achieved, 3),
             "peak": round(PEAK_LANE_TOPS, 2), "unit": "Tlane-op/s", "frac": round(achieved / PEAK_LANE_TOPS, 4),
             "traffic": profiled_traffic(f"k_{dom}", int(info["n"])), "avg_launch_ms": round(ms[dom], 4),
+            "launches_timed": phases[dom][1], "timed_every_nth_step": PROFILE_EVERY,
             "algorithmic_lane_ops_per_launch": int(lane_ops[dom]),
             "other_kernel": {k: {"avg_launch_ms": round(ms[k], 4),
                                  "frac": round(lane_ops[k] / (ms[k] * 1e-3) / 1e12 / PEAK_LANE_TOPS, 4)}

@@ -345,10 +345,16 @@ sph_status sph_synchronize(sph_ctx *ctx);
 /*
  * Per-phase GPU timing with HIP events recorded on the step's stream.
  * sph_profile_begin(ctx, max_steps) arms it for the next max_steps steps;
- * sph_profile_read synchronises and writes, for each phase id 0..n_phases-1
- * (see sph_profile_phase_name), the summed milliseconds and launch count.
+ * sph_profile_begin_sampled(ctx, max_steps, every) records only on every
+ * every-th of them (the first, the every+1-th, ...), so that the event
+ * records (a few microseconds each, two per phase) weigh less on the steps
+ * timed around them; every = 0 is SPH_ERR_ARG.  Steps with events run
+ * eagerly, not as graph replays.  sph_profile_read synchronises and writes,
+ * for each phase id 0..n_phases-1 (see sph_profile_phase_name), the summed
+ * milliseconds and launch count over the steps that recorded events.
  */
 sph_status sph_profile_begin(sph_ctx *ctx, uint32_t max_steps);
+sph_status sph_profile_begin_sampled(sph_ctx *ctx, uint32_t max_steps, uint32_t every);
 sph_status sph_profile_read(sph_ctx *ctx, double *ms, uint32_t *launches, uint32_t n_phases);
 const char *sph_profile_phase_name(uint32_t phase);
 

@@ -34,7 +34,8 @@ N_PHASES = 10
 EXPORTED = ["sph_workspace_size", "sph_init", "sph_init_static", "sph_set_body_pose", "sph_step", "sph_get_body_wrench",
             "sph_reset_smoothing", "sph_read_field", "sph_debug_neighbors", "sph_debug_neighbors_of",
             "sph_get_stats", "sph_get_info",
-            "sph_synchronize", "sph_profile_begin", "sph_profile_read", "sph_profile_phase_name",
+            "sph_synchronize", "sph_profile_begin", "sph_profile_begin_sampled", "sph_profile_read",
+            "sph_profile_phase_name",
             "sph_set_probes", "sph_read_probes", "sph_grab_body", "sph_release_body", "sph_get_body_state",
             "sph_batch_workspace_size", "sph_batch_init", "sph_read_log", "sph_read_probe_log", "sph_set_graph",
             "sph_set_body_track", "sph_destroy", "sph_status_string", "sph_last_error"]
@@ -103,6 +104,7 @@ def load_library(path=None):
     L.sph_get_stats.argtypes = [vp, C.POINTER(C.c_uint64)]
     L.sph_synchronize.argtypes = [vp]
     L.sph_profile_begin.argtypes = [vp, C.c_uint32]
+    L.sph_profile_begin_sampled.argtypes = [vp, C.c_uint32, C.c_uint32]
     L.sph_profile_read.argtypes = [vp, d3, C.POINTER(C.c_uint32), C.c_uint32]
     L.sph_profile_phase_name.argtypes = [C.c_uint32]
     L.sph_profile_phase_name.restype = C.c_char_p
@@ -403,8 +405,11 @@ class Sim:
     def synchronize(self):
         self._check(self.L.sph_synchronize(self.ctx), "sph_synchronize")
 
-    def profile_begin(self, max_steps):
-        self._check(self.L.sph_profile_begin(self.ctx, int(max_steps)), "sph_profile_begin")
+    def profile_begin(self, max_steps, every=1):
+        """Per-phase event timing on the next max_steps steps, recorded on
+        every `every`-th of them."""
+        self._check(self.L.sph_profile_begin_sampled(self.ctx, int(max_steps), int(every)),
+                    "sph_profile_begin_sampled")
 
     def profile_read(self) -> dict:
         ms = np.zeros(N_PHASES)

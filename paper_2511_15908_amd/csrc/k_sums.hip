@@ -395,6 +395,24 @@ __device__ __forceinline__ int take_hit(uint64_t (&mw)[kScWords], int base)
 struct Cand64 {
     double x, y, z, m;
 };
+// The term candidates in LDS as two arrays of 16-byte records, (x, y) and
+// (z, m): a wavefront's 16-byte reads at scattered slots then spread over
+// all LDS banks (32-byte records use every other group of four).
+struct CandTerms {
+    double2 xy[kScWords * kWave];
+    double2 zm[kScWords * kWave];
+    template <typename T>
+    __device__ __forceinline__ void put(uint32_t k, const V4<T> &c)
+    {
+        xy[k] = double2{(double)c.x, (double)c.y};
+        zm[k] = double2{(double)c.z, (double)fabs(c.w)};
+    }
+    __device__ __forceinline__ Cand64 get(uint32_t k) const
+    {
+        const double2 a = xy[k], b = zm[k];
+        return Cand64{a.x, a.y, b.x, b.y};
+    }
+};
 
 // A pass whose cell part holds at most 32 targets (fluid, soft or kinematic
 // particles) is served with L = 2 lanes per target, at most 16 with L = 4:
@@ -476,7 +494,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
 {
     __shared__ Nbhd nb;
     __shared__ V4<T> cand[kScWords * kWave];         // tests: T positions, inf past the end
-    __shared__ Cand64 cand64[kScWords * kWave];     // terms: FP64 positions and masses
+    __shared__ CandTerms cand64;                 // terms: FP64 positions and masses
     __shared__ double accl[kLeftD > 0 ? kLeftD : 1];
     __shared__ unsigned long long cstat[5];
     __shared__ uint8_t tmap[kWave];
@@ -568,7 +586,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                 if (keep) {
                     const uint32_t slot_c = size + lanes_below(km, lane);
                     cand[slot_c] = c;
-                    cand64[slot_c] = Cand64{(double)c.x, (double)c.y, (double)c.z, (double)fabs(c.w)};
+                    cand64.put(slot_c, c);
                 }
                 size += (uint32_t)__popcll(km);
             }
@@ -633,8 +651,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                     while (m) {
                         const int k = (int)__builtin_ctzll(m);
                         m &= m - 1ull;
-                        const Cand64 c = cand64[k];
-                        acc = fma(c.m, spline_shape64<sizeof(T) == 8>(c.x - mx, c.y - my, c.z - mz, ph.inv_h64), acc);
+                        const Cand64 c = cand64.get(k);
+                        acc = fma(c.m, spline_shape64<sizeof(T) == 8>(c.x - mx, c.y - my, c.z - mz, ph.inv_h64, ph.cinv_h64), acc);
                     }
                 } else {
                     int base = 0;
@@ -642,8 +660,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                         skip_empty_word(mw, base);
                         if (mw[0] == 0ull) break;
                         const int k = take_hit(mw, base);
-                        const Cand64 c = cand64[k];
-                        acc = fma(c.m, spline_shape64<sizeof(T) == 8>(c.x - mx, c.y - my, c.z - mz, ph.inv_h64), acc);
+                        const Cand64 c = cand64.get(k);
+                        acc = fma(c.m, spline_shape64<sizeof(T) == 8>(c.x - mx, c.y - my, c.z - mz, ph.inv_h64, ph.cinv_h64), acc);
                     }
                 }
             }
@@ -669,8 +687,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                             nleftpair_f += cnt;
                             nleftpair_d += dn_t ? cnt : 0u;
                             if (dn_t && hit) {
-                                const Cand64 c64 = cand64[q * kWave + lane];
-                                part = fma(c64.m, spline_shape64<sizeof(T) == 8>(c64.x - tx, c64.y - ty, c64.z - tz, ph.inv_h64),
+                                const Cand64 c64 = cand64.get(q * kWave + lane);
+                                part = fma(c64.m, spline_shape64<sizeof(T) == 8>(c64.x - tx, c64.y - ty, c64.z - tz, ph.inv_h64, ph.cinv_h64),
                                            part);
                             }
                         }

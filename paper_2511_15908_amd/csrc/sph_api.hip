@@ -104,6 +104,9 @@ struct sph_ctx {
     std::vector<sph_params> prms;         // per scene
     // profiling
     uint32_t prof_left = 0;
+    uint32_t prof_every = 1;              // events on every k-th armed step
+    uint32_t prof_idx = 0;                // armed steps run so far
+    bool prof_now = false;                // this step records events
     std::vector<hipEvent_t> prof_ev;      // pairs per (step, phase)
     std::vector<int> prof_phase;
     size_t prof_used = 0;
@@ -614,7 +617,7 @@ BodyArgs body_args(sph_ctx *c)
 
 void prof_mark(sph_ctx *c, int phase, bool begin)
 {
-    if (!c->prof_left) return;
+    if (!c->prof_now) return;
     if (c->prof_used >= c->prof_ev.size()) return;
     (void)hipEventRecord(c->prof_ev[c->prof_used], c->stream);
     if (begin) c->prof_phase[c->prof_used / 2] = phase;
@@ -659,6 +662,7 @@ void one_step(sph_ctx *c)
 {
     hipStream_t s = c->stream;
     const BodyArgs ba = body_args(c);
+    c->prof_now = c->prof_left && c->prof_idx % c->prof_every == 0u;
     prof_mark(c, 0, true);
     launch_place<T>(s, ba, c->inv_perm, state<T>(c, c->cur));
     prof_mark(c, 0, false);
@@ -690,7 +694,11 @@ void one_step(sph_ctx *c)
     prof_mark(c, 8, true);
     launch_integrate<T>(s, c->n, st, (const V4<T> *)c->force, phys<T>(c), c->err);
     prof_mark(c, 8, false);
-    if (c->prof_left) --c->prof_left;
+    if (c->prof_left) {
+        --c->prof_left;
+        ++c->prof_idx;
+    }
+    c->prof_now = false;
     ++c->steps;
 }
 
@@ -714,6 +722,7 @@ void fill_phys(Phys<T> &ph, const sph_params *p)
     ph.kp = p->k_pressure;
     ph.psi_scale = p->rho0;
     ph.inv_h64 = 1.0 / h;
+    ph.cinv_h64 = kCbrt4 / h;
     ph.alpha6_64 = alpha / 6.0;
     ph.flags = p->flags;
 }
@@ -1710,9 +1719,14 @@ sph_status sph_get_info(const sph_ctx *ctx, sph_info *info)
 
 sph_status sph_profile_begin(sph_ctx *ctx, uint32_t max_steps)
 {
-    if (!ctx) return SPH_ERR_ARG;
+    return sph_profile_begin_sampled(ctx, max_steps, 1u);
+}
+
+sph_status sph_profile_begin_sampled(sph_ctx *ctx, uint32_t max_steps, uint32_t every)
+{
+    if (!ctx || every < 1u) return SPH_ERR_ARG;
     if (ctx->dead) return SPH_ERR_STATE;
-    const size_t need = (size_t)max_steps * kPhases * 2;
+    const size_t need = (size_t)((max_steps + every - 1u) / every) * kPhases * 2;
     while (ctx->prof_ev.size() < need) {
         hipEvent_t e;
         HIPCHK(ctx, hipEventCreate(&e));
@@ -1721,6 +1735,8 @@ sph_status sph_profile_begin(sph_ctx *ctx, uint32_t max_steps)
     ctx->prof_phase.assign(need / 2 + 1, 0);
     ctx->prof_used = 0;
     ctx->prof_left = max_steps;
+    ctx->prof_every = every;
+    ctx->prof_idx = 0;
     for (uint32_t k = 0; k < kPhases; ++k) {
         ctx->prof_ms[k] = 0;
         ctx->prof_cnt[k] = 0;

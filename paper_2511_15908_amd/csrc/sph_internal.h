@@ -109,6 +109,7 @@ struct Phys {
     T vmax2;      // 0: no speed check
     double rho0, kp;
     double inv_h64, alpha6_64;   // FP64 kernel constants of the density sum
+    double cinv_h64;             // 4^(1/3) / h
     double psi_scale; // rho0 (for psi init)
     uint32_t flags;
 };
@@ -193,6 +194,8 @@ template <>
 __device__ __forceinline__ double grid_R2<double>(const Grid &g) { return g.R2_64; }
 
 
+constexpr double kCbrt4 = 1.5874010519681994;   // 4^(1/3), rounded to binary64
+
 // Shape of the cubic spline, (2-q)+^3 - 4 (1-q)+^3 with q = r/h, in FP64 from
 // FP64 coordinate differences (exact for FP32 positions).  The density sum
 // carries FP64 terms: p = k (rho - rho0) turns a relative density error e
@@ -203,7 +206,7 @@ __device__ __forceinline__ double grid_R2<double>(const Grid &g) { return g.R2_6
 // EXACT = true (FP64 runs): r = sqrt(r^2) in binary64, so the density is good
 // to a few ulps and the pressure the force pass sees to ~1e-12 relative.
 template <bool EXACT>
-__device__ __forceinline__ double spline_r2(double r2, double inv_h)
+__device__ __forceinline__ double spline_r2(double r2, double inv_h, double cinv_h)
 {
     double r;
     if constexpr (EXACT) {
@@ -213,16 +216,17 @@ __device__ __forceinline__ double spline_r2(double r2, double inv_h)
         r = r2 * y;
         r = fma(0.5 * y, fma(-r, r, r2), r);
     }
-    const double q = r * inv_h;
-    const double t2 = fmax(2.0 - q, 0.0);
-    const double t1 = fmax(1.0 - q, 0.0);
-    return fma(t2 * t2, t2, -4.0 * (t1 * (t1 * t1)));
+    // (2-q)^3 - (c (1-q))+^3 with c^3 = 4; 2 - q is not clamped: the pairs
+    // summed pass r^2 < (2h)^2 in T, so 2 - q is at worst a rounding below 0
+    const double t2 = fma(-r, inv_h, 2.0);
+    const double u = fmax(fma(-r, cinv_h, kCbrt4), 0.0);
+    return fma(t2 * t2, t2, -(u * (u * u)));
 }
 
 template <bool EXACT>
-__device__ __forceinline__ double spline_shape64(double dx, double dy, double dz, double inv_h)
+__device__ __forceinline__ double spline_shape64(double dx, double dy, double dz, double inv_h, double cinv_h)
 {
-    return spline_r2<EXACT>(fma(dz, dz, fma(dy, dy, dx * dx)), inv_h);
+    return spline_r2<EXACT>(fma(dz, dz, fma(dy, dy, dx * dx)), inv_h, cinv_h);
 }
 
 // Kernel value W(|c - me|) in FP64 (exact square root in FP64 runs).
@@ -230,7 +234,7 @@ template <typename T>
 __device__ __forceinline__ double kernel_w64(const V4<T> &c, const V4<T> &me, const Phys<T> &ph)
 {
     return ph.alpha6_64 * spline_shape64<sizeof(T) == 8>((double)c.x - (double)me.x, (double)c.y - (double)me.y,
-                                                         (double)c.z - (double)me.z, ph.inv_h64);
+                                                         (double)c.z - (double)me.z, ph.inv_h64, ph.cinv_h64);
 }
 
 // --- batches of independent scenes ---

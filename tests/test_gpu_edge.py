@@ -255,3 +255,24 @@ def test_static_boundary_fields_stay_zero(gpu):
     assert static.size
     assert np.all(sim.read("rho")[static] == 0)
     assert np.all(sim.read("f")[static] == 0)
+
+
+def test_profile_sampling(gpu):
+    """Event timing on every step, and on every k-th armed step: launch counts
+    per phase, positive times, the steps past the armed ones unrecorded, and
+    k = 0 refused."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=5)
+    sim = gpu.Sim(sc)
+    for every, want in [(1, 10), (3, 4), (4, 3), (20, 1)]:
+        sim.profile_begin(10, every=every)
+        sim.step(12)
+        ph = sim.profile_read()
+        for name in ["keys", "density", "forces", "integrate"]:
+            ms, launches = ph[name]
+            assert launches == want, (every, name, launches)
+            assert ms > 0.0
+    with pytest.raises(gpu.SphError):
+        sim.profile_begin(10, every=0)
+    sim.step(2)
+    sim.synchronize()
