@@ -303,20 +303,26 @@ __device__ __forceinline__ uint32_t gap_sign(const V4<T> &a, const V4<T> &b, T R
     else return (uint32_t)((uint64_t)__double_as_longlong((double)d) >> 32);
 }
 
-#ifndef SPH_TEST_UNROLL
-#define SPH_TEST_UNROLL 8
-#endif
-
 // Hit bits of this lane's particle against nv (<= 32) staged candidates;
 // nv is uniform, so empty slots of a super-chunk are never tested.  The
 // candidates go from the last to the first, each shifting its sign bit in
-// at the bottom (one funnel shift), so candidate b ends at bit b.
+// at the bottom (one funnel shift), so candidate b ends at bit b.  They are
+// read four at a time before any is tested, so that the four LDS reads are
+// in flight together.
+constexpr uint32_t kTestBatch = 4;
 template <typename T>
 __device__ __forceinline__ uint32_t hit_bits(const V4<T> &me, const V4<T> *cand, uint32_t nv, T R2)
 {
     uint32_t bits = 0;
-#pragma unroll SPH_TEST_UNROLL
-    for (uint32_t b = nv; b-- > 0u;) bits = __builtin_amdgcn_alignbit(bits, gap_sign<T>(me, cand[b], R2), 31u);
+    uint32_t b = nv;
+    for (; b >= kTestBatch; b -= kTestBatch) {
+        V4<T> c[kTestBatch];
+#pragma unroll
+        for (uint32_t u = 0; u < kTestBatch; ++u) c[u] = cand[b - 1u - u];
+#pragma unroll
+        for (uint32_t u = 0; u < kTestBatch; ++u) bits = __builtin_amdgcn_alignbit(bits, gap_sign<T>(me, c[u], R2), 31u);
+    }
+    while (b-- > 0u) bits = __builtin_amdgcn_alignbit(bits, gap_sign<T>(me, cand[b], R2), 31u);
     return bits;
 }
 
@@ -332,6 +338,7 @@ __device__ __forceinline__ uint64_t hit_word(const V4<T> &me, const V4<T> *cand,
 #ifndef SPH_SPLIT_UNROLL
 #define SPH_SPLIT_UNROLL 4
 #endif
+
 // Split passes (L lanes per target, below): the lane of group g tests only
 // the word's candidates g, g + L, g + 2 L, ... (n of them), which are the
 // ones it walks; bit i of the result is candidate g + L i.
