@@ -320,7 +320,8 @@ __device__ __forceinline__ uint32_t hit_bits(const V4<T> &me, const V4<T> *cand,
 #pragma unroll
         for (uint32_t u = 0; u < kTestBatch; ++u) c[u] = cand[b - 1u - u];
 #pragma unroll
-        for (uint32_t u = 0; u < kTestBatch; ++u) bits = __builtin_amdgcn_alignbit(bits, gap_sign<T>(me, c[u], R2), 31u);
+        for (uint32_t u = 0; u < kTestBatch; ++u)
+            bits = __builtin_amdgcn_alignbit(bits, gap_sign<T>(me, c[u], R2), 31u);
     }
     while (b-- > 0u) bits = __builtin_amdgcn_alignbit(bits, gap_sign<T>(me, cand[b], R2), 31u);
     return bits;
@@ -505,6 +506,7 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
     __shared__ double accl[kLeftD > 0 ? kLeftD : 1];
     __shared__ unsigned long long cstat[5];
     __shared__ uint8_t tmap[kWave];
+    constexpr bool kExact = sizeof(T) == 8;          // FP64 runs: binary64 square root in the terms
     const uint32_t lane = threadIdx.x;
     const uint32_t ncq = *n_occupied;
     if (blockIdx.x >= ncq) return;
@@ -659,7 +661,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                         const int k = (int)__builtin_ctzll(m);
                         m &= m - 1ull;
                         const Cand64 c = cand64.get(k);
-                        acc = fma(c.m, spline_shape64<sizeof(T) == 8>(c.x - mx, c.y - my, c.z - mz, ph.inv_h64, ph.cinv_h64), acc);
+                        acc = fma(c.m, spline_shape64<kExact>(c.x - mx, c.y - my, c.z - mz, ph.inv_h64, ph.cinv_h64),
+                                  acc);
                     }
                 } else {
                     int base = 0;
@@ -668,7 +671,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                         if (mw[0] == 0ull) break;
                         const int k = take_hit(mw, base);
                         const Cand64 c = cand64.get(k);
-                        acc = fma(c.m, spline_shape64<sizeof(T) == 8>(c.x - mx, c.y - my, c.z - mz, ph.inv_h64, ph.cinv_h64), acc);
+                        acc = fma(c.m, spline_shape64<kExact>(c.x - mx, c.y - my, c.z - mz, ph.inv_h64, ph.cinv_h64),
+                                  acc);
                     }
                 }
             }
@@ -695,7 +699,9 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                             nleftpair_d += dn_t ? cnt : 0u;
                             if (dn_t && hit) {
                                 const Cand64 c64 = cand64.get(q * kWave + lane);
-                                part = fma(c64.m, spline_shape64<sizeof(T) == 8>(c64.x - tx, c64.y - ty, c64.z - tz, ph.inv_h64, ph.cinv_h64),
+                                part = fma(c64.m,
+                                           spline_shape64<kExact>(c64.x - tx, c64.y - ty, c64.z - tz, ph.inv_h64,
+                                                                  ph.cinv_h64),
                                            part);
                             }
                         }
@@ -754,31 +760,47 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
 
 // Pair force on particle a from particle c (both terms of Alg. 1's force
 // pass), accumulated into f.  gradW_ac = g(r) x_ac with
-//   g = (dW/dr)/r = alpha/(2 h^2) (4 t1^2 - t2^2) / q,  t1 = (1-q)+, t2 = (2-q)+,
-// written as (2 t1 - t2)(2 t1 + t2) / q, which is finite and 0 at r = 0 (self
-// pair).  A boundary particle takes the pressure and density of its
-// fluid/soft partner (pressure mirroring), its mass is psi_b; two boundary
-// particles exert nothing.  Every factor is symmetric in (a, c) and the
-// vector factors are antisymmetric, so the force c computes on itself from a
-// is the exact IEEE negation.
+//   g = (dW/dr)/r = alpha/(2 h^2) (4 t1^2 - t2^2) / q,  t1 = (1-q)+, t2 = (2-q)+.
+// 4 t1^2 - t2^2 = (2 t1 - t2)(2 t1 + t2) = -min(q, 2-q) max(4-3q, 2-q) on
+// 0 <= q <= 2 (q < 1: -q (4-3q); q >= 1: -(2-q)^2), so -g is
+//   alpha/(2h) min(q, 2-q) max(4-3q, 2-q) / r,
+// finite and 0 at r = 0 (self pair).  A boundary particle takes the pressure
+// and density of its fluid/soft partner (pressure mirroring), its mass is
+// psi_b; two boundary particles exert nothing.  Every scalar factor is
+// symmetric in (a, c), so the pressure force c computes on itself from a is
+// the exact IEEE negation.  The viscosity term sv (v_a - v_c) is summed as
+// -sv v_c here plus v_a times the sum of sv (fw), added once per chunk: two
+// operations fewer per pair, with the pair antisymmetric up to rounding.
 // P_mir is the pressure a boundary partner takes from this particle: P_a,
 // or 0 with the single-boundary-term flag.  KIN = false: particle a is not a
 // boundary particle; PLAIN: neither boundary flag (2, 4) is set.  With the
 // unified reading (flag 8) a boundary particle keeps its own density and
 // pressure: its staged mirror factor cv.w is 0 and a boundary target does not
 // take its partner's values either (mirror = false).
+// The velocities mv and cv come multiplied by 4 nu (vel_scaled), the uniform
+// factor of the viscosity term.
+template <typename T>
+__device__ __forceinline__ V4<T> vel_scaled(V4<T> v, const Phys<T> &ph)
+{
+    // both sides of a pair scale alike, so v_a - v_c stays antisymmetric
+    const T k = ph.two_nu * (T)2;
+    v.x *= k;
+    v.y *= k;
+    v.z *= k;
+    return v;
+}
+
 template <typename T, bool KIN, bool PLAIN>
 __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T rho_a, T P_a, T P_mir, bool isBa,
                                            bool mirror, T ma, const V4<T> &c, const V4<T> &cv, const V2<T> &cd,
-                                           const Phys<T> &ph, T &fx, T &fy, T &fz)
+                                           const Phys<T> &ph, T &fx, T &fy, T &fz, T &fw)
 {
     const T dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
     const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     const T rs = frsqrt(max(r2, (T)1e-30));      // 1/r
     const T q = (r2 * rs) * ph.inv_h;
-    const T t1 = max((T)1 - q, (T)0);
-    const T t2 = max((T)2 - q, (T)0);
-    const T g = ((ph.gch * fma((T)2, t1, -t2)) * fma((T)2, t1, t2)) * rs;
+    const T t2 = (T)2 - q;
+    const T gn = (min(q, t2) * max(fma((T)-3, q, (T)4), t2)) * (ph.gch * rs);   // -g
     // cv.w is 1 for a mirrored boundary candidate (0 otherwise), whose staged
     // density and pressure term are 0: the mirrored values enter by one FMA
     // each; boundary candidates carry -psi_b in c.w
@@ -792,11 +814,12 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
         Pa = (isBa && mirror) ? Pb : P_a;
         ra = (isBa && mirror) ? cd.x : rho_a;
     }
-    const T mm = ma * mc;
-    T sp = -(mm * (Pa + Pc)) * g;
-    // 2 nu m_a m_c [2/(rho_a+rho_c)] g r^2/(r^2+eps), one reciprocal (the
-    // factor 2 of 2 r^2 rides on the uniform 2 nu: scaling by 2 is exact)
-    T sv = (((ph.two_nu * (T)2) * mm) * g) * (r2 * frcp((ra + rc) * (r2 + ph.eps)));
+    const T mg = (ma * mc) * gn;                   // -m_a m_c g
+    // pressure: -m_a m_c (P_a/rho_a^2 + P_c/rho_c^2) g
+    T sp = (Pa + Pc) * mg;
+    // viscosity: 2 nu m_a m_c [2/(rho_a+rho_c)] g r^2/(r^2+eps), one
+    // reciprocal, with the 4 nu on the velocities
+    T sv = -((mg * r2) * frcp((ra + rc) * (r2 + ph.eps)));
     if (KIN) {
         const bool bb = isBa && isBc;
         sp = bb ? (T)0 : sp;
@@ -806,9 +829,10 @@ __device__ __forceinline__ void pair_force(const V4<T> &me, const V4<T> &mv, T r
         const bool novisc = (ph.flags & 4u) && (isBa || isBc);
         sv = novisc ? (T)0 : sv;
     }
-    fx = fma(sp, dx, fma(sv, mv.x - cv.x, fx));
-    fy = fma(sp, dy, fma(sv, mv.y - cv.y, fy));
-    fz = fma(sp, dz, fma(sv, mv.z - cv.z, fz));
+    fx = fma(sp, dx, fma(-sv, cv.x, fx));
+    fy = fma(sp, dy, fma(-sv, cv.y, fy));
+    fz = fma(sp, dz, fma(-sv, cv.z, fz));
+    fw += sv;
 }
 
 // Pair forces of one lane's hits among the staged candidates (walking its
@@ -819,7 +843,7 @@ template <typename T, bool KIN, bool PLAIN, bool ONE>
 __device__ __forceinline__ void walk_forces(uint64_t (&mw)[kScWords], const V4<T> &me, const V4<T> &mv,
                                             const V2<T> &md, T P_mir, bool kin, bool mirror, T ma, const V4<T> *cp,
                                             const V4<T> *cvel, const V2<T> *cden, const Phys<T> &ph, T &cx, T &cy,
-                                            T &cz)
+                                            T &cz, T &cw)
 {
     if (ONE) {
         uint64_t m = mw[0];
@@ -827,7 +851,7 @@ __device__ __forceinline__ void walk_forces(uint64_t (&mw)[kScWords], const V4<T
             const int k = (int)__builtin_ctzll(m);
             m &= m - 1ull;
             pair_force<T, KIN, PLAIN>(me, mv, md.x, md.y, P_mir, kin, mirror, ma, cp[k], cvel[k], cden[k], ph, cx, cy,
-                                      cz);
+                                      cz, cw);
         }
         return;
     }
@@ -836,7 +860,8 @@ __device__ __forceinline__ void walk_forces(uint64_t (&mw)[kScWords], const V4<T
         skip_empty_word(mw, base);
         if (mw[0] == 0ull) break;
         const int k = take_hit(mw, base);
-        pair_force<T, KIN, PLAIN>(me, mv, md.x, md.y, P_mir, kin, mirror, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz);
+        pair_force<T, KIN, PLAIN>(me, mv, md.x, md.y, P_mir, kin, mirror, ma, cp[k], cvel[k], cden[k], ph, cx, cy, cz,
+                                  cw);
     }
 }
 
@@ -915,7 +940,7 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
         const SplitPass sp = split_pass(act && (aux_type(aux) != TY_BOUNDARY || aux_kin(aux)), with_left, lane,
                                         t0, e0, s0, st.aux, tmap, p, act, pc, aux);
         const V4<T> me = st.pos[pc];
-        const V4<T> mv = st.vel[pc];
+        const V4<T> mv = vel_scaled(st.vel[pc], ph);
         const V2<T> md = dens[pc];
         const bool fs = act && aux_type(aux) != TY_BOUNDARY;
         const bool kin = act && aux_kin(aux);
@@ -964,7 +989,7 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                 if (keep) {
                     const uint32_t o = size + lanes_below(km, lane);
                     cp[o] = c;
-                    V4<T> cv = st.vel[j];
+                    V4<T> cv = vel_scaled(st.vel[j], ph);
                     cv.w = (mirror && c.w < (T)0) ? (T)1 : (T)0;    // mirror factor for the pair loop
                     cvel[o] = cv;
                     cden[o] = dens[j];
@@ -991,24 +1016,28 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                     witer += wave_reduce(mine, 0u, OpMax{});
                 }
                 // a super-chunk holds ~1/S of the neighbours: sum it in T, then in FP64
-                T cx = (T)0, cy = (T)0, cz = (T)0;
+                T cx = (T)0, cy = (T)0, cz = (T)0, cw = (T)0;
                 const T P_mir = (ph.flags & 2u) ? (T)0 : md.y;
                 const bool one = size <= (uint32_t)kWave;
                 if (wave_kin || (ph.flags & 6u)) {
                     if (one)
                         walk_forces<T, true, false, true>(mw, me, mv, md, P_mir, kin, mirror, ma, cp, cvel, cden, ph,
-                                                          cx, cy, cz);
+                                                          cx, cy, cz, cw);
                     else
                         walk_forces<T, true, false, false>(mw, me, mv, md, P_mir, kin, mirror, ma, cp, cvel, cden, ph,
-                                                           cx, cy, cz);
+                                                           cx, cy, cz, cw);
                 } else {
                     if (one)
                         walk_forces<T, false, true, true>(mw, me, mv, md, P_mir, kin, mirror, ma, cp, cvel, cden, ph,
-                                                          cx, cy, cz);
+                                                          cx, cy, cz, cw);
                     else
                         walk_forces<T, false, true, false>(mw, me, mv, md, P_mir, kin, mirror, ma, cp, cvel, cden, ph,
-                                                           cx, cy, cz);
+                                                           cx, cy, cz, cw);
                 }
+                // the viscosity terms' target velocity, once per chunk
+                cx = fma(mv.x, cw, cx);
+                cy = fma(mv.y, cw, cy);
+                cz = fma(mv.z, cw, cz);
                 fx += (double)cx;
                 fy += (double)cy;
                 fz += (double)cz;
@@ -1021,9 +1050,9 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                     const bool kin_t = aux_kin(at);
                     if (aux_type(at) == TY_BOUNDARY && !kin_t) continue;   // uniform: static boundary
                     const V4<T> mt = st.pos[pt];
-                    const V4<T> mvt = st.vel[pt];
+                    const V4<T> mvt = vel_scaled(st.vel[pt], ph);
                     const V2<T> mdt = dens[pt];
-                    T cx = (T)0, cy = (T)0, cz = (T)0;
+                    T cx = (T)0, cy = (T)0, cz = (T)0, cw = (T)0;
 #pragma unroll
                     for (int q = 0; q < kScWords; ++q) {
                         if ((uint32_t)q < nwc) {
@@ -1032,9 +1061,12 @@ __global__ __launch_bounds__(64) SPH_FORCES_OCCUPANCY void k_forces(uint32_t n, 
                             if ((m >> lane) & 1ull)
                                 pair_force<T, true, false>(mt, mvt, mdt.x, mdt.y, (ph.flags & 2u) ? (T)0 : mdt.y,
                                                            kin_t, mirror, fabs(mt.w), cp[v], cvel[v], cden[v], ph,
-                                                           cx, cy, cz);
+                                                           cx, cy, cz, cw);
                         }
                     }
+                    cx = fma(mvt.x, cw, cx);
+                    cy = fma(mvt.y, cw, cy);
+                    cz = fma(mvt.z, cw, cz);
                     cx = wave_reduce(cx, (T)0, OpAdd{});
                     cy = wave_reduce(cy, (T)0, OpAdd{});
                     cz = wave_reduce(cz, (T)0, OpAdd{});
