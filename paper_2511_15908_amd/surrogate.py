@@ -6,6 +6,7 @@ from __future__ import annotations
 
 import copy
 import math
+import sys
 
 import numpy as np
 
@@ -504,11 +505,16 @@ def haptic_under_load(kind="haptic", n_fluid=100_000, seconds=2.0, scene=None, s
                 evs.pop(0).synchronize()
         sa.synchronize()
 
+    # the SPH thread hands the interpreter lock back within 0.2 ms (the
+    # default switch interval, 5 ms, would hold a tick back for that long)
+    switch = sys.getswitchinterval()
+    sys.setswitchinterval(2e-4)
     th = threading.Thread(target=sph_worker)
     th.start()
     time.sleep(0.2)                           # let the SPH queue fill
     n_ticks = int(seconds * 1000)
     lat = np.empty(n_ticks)
+    delay = np.empty(n_ticks)
     late = 0
     steps0, t_start = done[0], time.perf_counter()
     for k in range(n_ticks):
@@ -521,16 +527,19 @@ def haptic_under_load(kind="haptic", n_fluid=100_000, seconds=2.0, scene=None, s
         t0 = time.perf_counter()
         net.predict_one(xs[k % xs.shape[0]])
         lat[k] = time.perf_counter() - t0
+        delay[k] = t0 - due
         late += int(t0 + lat[k] > due + 1e-3)
     wall = time.perf_counter() - t_start
     steps = done[0] - steps0
     stop.set()
     th.join()
+    sys.setswitchinterval(switch)
     us = lambda a, q: round(float(np.percentile(a, q)) * 1e6, 1)   # noqa: E731
     r = {"scene": sc.name, "n_particles": int(sc.n), "ticks": n_ticks,
          "chain_latency_us_alone": {"p50": us(idle, 50), "p99": us(idle, 99), "max": round(float(idle.max()) * 1e6, 1)},
          "chain_latency_us_under_sph": {"p50": us(lat, 50), "p99": us(lat, 99),
                                         "max": round(float(lat.max()) * 1e6, 1)},
+         "tick_start_delay_us": {"p99": us(delay, 99), "max": round(float(delay.max()) * 1e6, 1)},
          "ticks_past_their_1ms_period": late, "haptic_hz_achieved": round(n_ticks / wall, 1),
          "sph_steps_per_s_alone": round(sph_alone, 1), "sph_steps_per_s_with_haptic": round(steps / wall, 1)}
     log(f"  haptic chain under SPH load: {r}")
