@@ -123,6 +123,26 @@ def test_small_scene_one_step(gpu, orc, prec, seed):
     _check_step(sc, o, g, r, prec, TOL[prec])
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("nu", [0.0, 0.02])
+def test_viscosity_extremes(gpu, orc, prec, nu):
+    """No viscosity (the velocities the force pass stages then scale to 0) and
+    a viscosity 20x the benchmark's with random velocities of up to 0.5 m/s on
+    every fluid and soft particle (the viscous sum then carries most of the
+    force and its per-chunk target-velocity term cancels the most)."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=13, precision=prec)
+    sc.params["nu"] = nu
+    rng = scenes.SplitMix64(13, 7)
+    moving = (sc.type != 2)[:, None]
+    sc.v = np.where(moving, (2.0 * rng.uniform(sc.v.size).reshape(sc.v.shape) - 1.0) * 0.5, sc.v)
+    c0 = sc.object_pose0[1, :3]
+    poses = {1: scenes.random_pose_velocity(13, c0)}
+    sim, o, init, outs = _run_both(gpu, orc, sc, prec, poses)
+    g, r = outs[0]
+    _check_step(sc, o, g, r, prec, TOL[prec])
+
+
 def _split_pass_share(sc, keys):
     """Share of the density pass's wavefront passes that have at most 32
     movable targets (fluid, soft, kinematic) and are served two lanes per
