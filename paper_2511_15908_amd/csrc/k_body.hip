@@ -73,49 +73,19 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Pass 1: each block reduces up to 256 body particles of one object.
-__global__ __launch_bounds__(256) void k_wrench_partial(BodyArgs b)
-{
-    __shared__ double red[4][6];
-    const uint32_t blk = blockIdx.x, t = threadIdx.x, lane = t & 63u, wv = t >> 6;
-    const uint32_t o = b.blk_obj[blk];
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    if (t < b.blk_count[blk]) {
-        const uint32_t s = b.blk_first[blk] + t;
-        double R[9];
-        quat_R(b.poses + 16u * o + 3, R);
-        const double r0 = b.r_loc[3 * s], r1 = b.r_loc[3 * s + 1], r2 = b.r_loc[3 * s + 2];
-        double rw[3];
-        for (int a = 0; a < 3; ++a) rw[a] = R[3 * a] * r0 + R[3 * a + 1] * r1 + R[3 * a + 2] * r2;
-        const double fx = b.fbody[3 * s], fy = b.fbody[3 * s + 1], fz = b.fbody[3 * s + 2];
-        v[0] = fx;
-        v[1] = fy;
-        v[2] = fz;
-        v[3] = rw[1] * fz - rw[2] * fy;
-        v[4] = rw[2] * fx - rw[0] * fz;
-        v[5] = rw[0] * fy - rw[1] * fx;
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
-    if (lane == 0)
-        for (int k = 0; k < 6; ++k) red[wv][k] = v[k];
-    __syncthreads();
-    if (t < 6) b.partials[6u * blk + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
-}
-
-// Pass 2: one wave per kinematic object sums its partials in a fixed order,
-// pushes the sample into the ring and advances the pose by one step.
-__global__ __launch_bounds__(64) void k_wrench_final(BodyArgs b)
+// The wrench of kinematic object o (Sec. 3.2: the rigid particles' point
+// forces summed into the parent body), one 256-thread block per object, in
+// the integration launch: each thread sums the object's body particles t,
+// t + 256, ... in order, the block adds its four wavefront sums in a fixed
+// order, and thread 0 pushes the sample into the ring, logs the step and
+// advances the pose (wrench_apply).  No block depends on another, so no
+// cross-block fence is needed and the result does not depend on the order
+// in which blocks run.
+// The step's sample of object o: ring, log, free-body dynamics, next pose.
+__device__ __forceinline__ void wrench_apply(const BodyArgs &b, uint32_t o, const double v[6])
 {
 #pragma clang fp contract(off)
-    const uint32_t o = blockIdx.x, lane = threadIdx.x;
-    const uint32_t b0 = b.obj_blk0[o], b1 = b.obj_blk0[o + 1];
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    for (uint32_t k = b0 + lane; k < b1; k += 64u)
-        for (int c = 0; c < 6; ++c) v[c] += b.partials[6u * k + c];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) v[c] = wave_sum(v[c]);
-    if (lane == 0) {
+    {
         const uint32_t cnt = b.ring_count[o];
         double *slot = b.ring + ((size_t)o * b.K + (cnt % b.K)) * 6u;
         for (int c = 0; c < 6; ++c) slot[c] = v[c];
@@ -187,12 +157,6 @@ __global__ __launch_bounds__(64) void k_wrench_final(BodyArgs b)
     }
 }
 
-void launch_wrench(hipStream_t s, const BodyArgs &b)
-{
-    if (!b.nk || !b.nblk) return;
-    hipLaunchKernelGGL(k_wrench_partial, dim3(b.nblk), dim3(256), 0, s, b);
-    hipLaunchKernelGGL(k_wrench_final, dim3(b.nk), dim3(64), 0, s, b);
-}
 
 struct PoseArg {
     double v[13];
@@ -318,66 +282,51 @@ template void launch_probe<float>(hipStream_t, const ProbeArgs &, State<float>, 
 template void launch_probe<double>(hipStream_t, const ProbeArgs &, State<double>, const Batch<double> &,
                                    const uint32_t *, const uint32_t *);
 
-// ------------------------------------------------------------------ springs
-
-// Half a wavefront (32 lanes) per spring row, one spring per lane (rows
-// longer than 32 loop), the row's sum by a fixed butterfly: the gathers of a
-// row are in flight together instead of one after another.
-template <typename T>
-__global__ __launch_bounds__(64) void k_springs(SpringArgs a, const uint32_t *__restrict__ inv_perm, State<T> st,
-                                                V4<T> *__restrict__ fspring)
-{
-    const uint32_t r = blockIdx.x * 2u + (threadIdx.x >> 5);
-    const uint32_t l = threadIdx.x & 31u;
-    const bool row = r < a.rows;
-    double f[3] = {0.0, 0.0, 0.0};
-    if (row) {
-        const uint32_t i = inv_perm[a.row_id[r]];
-        const V4<T> xi = st.pos[i], vi = st.vel[i];
-        for (uint32_t e = a.row_ptr[r] + l; e < a.row_ptr[r + 1]; e += 32u) {
-            const uint32_t j = inv_perm[a.partner[e]];
-            const V4<T> xj = st.pos[j], vj = st.vel[j];
-            const double d0 = (double)xi.x - (double)xj.x;
-            const double d1 = (double)xi.y - (double)xj.y;
-            const double d2 = (double)xi.z - (double)xj.z;
-            const double len = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const double il = 1.0 / len;
-            const double e0 = d0 * il, e1 = d1 * il, e2 = d2 * il;
-            const double vr = ((double)vi.x - (double)vj.x) * e0 + ((double)vi.y - (double)vj.y) * e1 +
-                              ((double)vi.z - (double)vj.z) * e2;
-            const double *pr = a.prm + 3u * e;
-            const double mag = pr[1] * (len - pr[0]) + pr[2] * vr;
-            f[0] -= mag * e0;
-            f[1] -= mag * e1;
-            f[2] -= mag * e2;
-        }
-    }
-#pragma unroll
-    for (int m = 16; m >= 1; m >>= 1) {
-        f[0] += __shfl_xor(f[0], m, 32);
-        f[1] += __shfl_xor(f[1], m, 32);
-        f[2] += __shfl_xor(f[2], m, 32);
-    }
-    if (row && l == 0) fspring[r] = V4<T>{(T)f[0], (T)f[1], (T)f[2], (T)0};
-}
-
-template <typename T>
-void launch_springs(hipStream_t s, const SpringArgs &a, const uint32_t *inv_perm, State<T> st, V4<T> *fspring)
-{
-    if (!a.rows) return;
-    hipLaunchKernelGGL(k_springs<T>, dim3((a.rows + 1) / 2), dim3(64), 0, s, a, inv_perm, st, fspring);
-}
-template void launch_springs<float>(hipStream_t, const SpringArgs &, const uint32_t *, State<float>, V4<float> *);
-template void launch_springs<double>(hipStream_t, const SpringArgs &, const uint32_t *, State<double>,
-                                     V4<double> *);
-
 // ------------------------------------------------------------------ integrate
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_integrate(uint32_t n, State<T> st, const V4<T> *__restrict__ force,
-                                                   Phys<T> ph, uint32_t *__restrict__ err)
+__device__ __forceinline__ void wrench_obj(const BodyArgs &b, uint32_t o)
 {
-    const uint32_t p = blockIdx.x * 256u + threadIdx.x;
+    __shared__ double red[4][6];
+    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+    double R[9];
+    quat_R(b.poses + 16u * o + 3, R);
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t s = b.obj_slot0[o] + t; s < b.obj_slot0[o + 1]; s += 256u) {
+        const double r0 = b.r_loc[3 * s], r1 = b.r_loc[3 * s + 1], r2 = b.r_loc[3 * s + 2];
+        double rw[3];
+        for (int a = 0; a < 3; ++a) rw[a] = R[3 * a] * r0 + R[3 * a + 1] * r1 + R[3 * a + 2] * r2;
+        const double fx = b.fbody[3 * s], fy = b.fbody[3 * s + 1], fz = b.fbody[3 * s + 2];
+        v[0] += fx;
+        v[1] += fy;
+        v[2] += fz;
+        v[3] += rw[1] * fz - rw[2] * fy;
+        v[4] += rw[2] * fx - rw[0] * fz;
+        v[5] += rw[0] * fy - rw[1] * fx;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k) red[wv][k] = v[k];
+    __syncthreads();
+    if (t != 0) return;
+    double w[6];
+    for (int k = 0; k < 6; ++k) w[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    wrench_apply(b, o, w);
+}
+
+
+// Blocks [0, nw) reduce the wrench of one kinematic object each (above, from
+// the same step's forces), the blocks after them integrate the particles.
+template <typename T>
+__global__ __launch_bounds__(256) void k_integrate(uint32_t n, uint32_t nw, State<T> st,
+                                                   const V4<T> *__restrict__ force, Phys<T> ph,
+                                                   uint32_t *__restrict__ err, BodyArgs b)
+{
+    if (blockIdx.x < nw) {
+        wrench_obj(b, blockIdx.x);
+        return;
+    }
+    const uint32_t p = (blockIdx.x - nw) * 256u + threadIdx.x;
     if (p >= n) return;
     if (aux_type(st.aux[p]) == TY_BOUNDARY) return;
     V4<T> x = st.pos[p];
@@ -399,14 +348,16 @@ __global__ __launch_bounds__(256) void k_integrate(uint32_t n, State<T> st, cons
 }
 
 template <typename T>
-void launch_integrate(hipStream_t s, uint32_t n, State<T> st, const V4<T> *force, const Phys<T> &ph, uint32_t *err)
+void launch_integrate(hipStream_t s, uint32_t n, State<T> st, const V4<T> *force, const Phys<T> &ph, uint32_t *err,
+                      const BodyArgs &b)
 {
     if (!n) return;
-    hipLaunchKernelGGL(k_integrate<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, st, force, ph, err);
+    const uint32_t nint = (n + 255) / 256;
+    hipLaunchKernelGGL(k_integrate<T>, dim3(b.nk + nint), dim3(256), 0, s, n, b.nk, st, force, ph, err, b);
 }
 template void launch_integrate<float>(hipStream_t, uint32_t, State<float>, const V4<float> *, const Phys<float> &,
-                                      uint32_t *);
+                                      uint32_t *, const BodyArgs &);
 template void launch_integrate<double>(hipStream_t, uint32_t, State<double>, const V4<double> *,
-                                       const Phys<double> &, uint32_t *);
+                                       const Phys<double> &, uint32_t *, const BodyArgs &);
 
 }  // namespace sphk

@@ -471,6 +471,51 @@ __device__ __forceinline__ SplitPass split_pass(bool target, bool with_left, uin
     return sp;
 }
 
+// ------------------------------------------------------------------ springs
+
+// Spring forces of soft rows r = 2 sb and 2 sb + 1 (mass-spring soft bodies,
+// Sec. 3.2), run by workgroups of the density launch past its cells: half a
+// wavefront (32 lanes) per row, one spring per lane (rows longer than 32
+// loop), the row's sum by a fixed butterfly, so the gathers of a row are in
+// flight together.  The force pass reads the result.
+template <typename T>
+__device__ __forceinline__ void spring_rows(const SpringArgs &a, const uint32_t *__restrict__ inv_perm, State<T> st,
+                                            V4<T> *__restrict__ fspring, uint32_t sb)
+{
+    const uint32_t r = sb * 2u + (threadIdx.x >> 5);
+    const uint32_t l = threadIdx.x & 31u;
+    const bool row = r < a.rows;
+    double f[3] = {0.0, 0.0, 0.0};
+    if (row) {
+        const uint32_t i = inv_perm[a.row_id[r]];
+        const V4<T> xi = st.pos[i], vi = st.vel[i];
+        for (uint32_t e = a.row_ptr[r] + l; e < a.row_ptr[r + 1]; e += 32u) {
+            const uint32_t j = inv_perm[a.partner[e]];
+            const V4<T> xj = st.pos[j], vj = st.vel[j];
+            const double d0 = (double)xi.x - (double)xj.x;
+            const double d1 = (double)xi.y - (double)xj.y;
+            const double d2 = (double)xi.z - (double)xj.z;
+            const double len = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double il = 1.0 / len;
+            const double e0 = d0 * il, e1 = d1 * il, e2 = d2 * il;
+            const double vr = ((double)vi.x - (double)vj.x) * e0 + ((double)vi.y - (double)vj.y) * e1 +
+                              ((double)vi.z - (double)vj.z) * e2;
+            const double *pr = a.prm + 3u * e;
+            const double mag = pr[1] * (len - pr[0]) + pr[2] * vr;
+            f[0] -= mag * e0;
+            f[1] -= mag * e1;
+            f[2] -= mag * e2;
+        }
+    }
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) {
+        f[0] += __shfl_xor(f[0], m, 32);
+        f[1] += __shfl_xor(f[1], m, 32);
+        f[2] += __shfl_xor(f[2], m, 32);
+    }
+    if (row && l == 0) fspring[r] = V4<T>{(T)f[0], (T)f[1], (T)f[2], (T)0};
+}
+
 // ------------------------------------------------------------------ density
 
 __device__ __forceinline__ double wave_sum_f64(double v) { return wave_reduce(v, 0.0, OpAdd{}); }
@@ -498,7 +543,8 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
                                                 uint64_t *__restrict__ masks, uint32_t *__restrict__ err,
                                                 unsigned long long *__restrict__ stats,
                                                 const uint32_t *__restrict__ cells,
-                                                const uint32_t *__restrict__ n_occupied)
+                                                const uint32_t *__restrict__ n_occupied, SpringArgs sa,
+                                                const uint32_t *__restrict__ inv_perm, V4<T> *__restrict__ fspring)
 {
     __shared__ Nbhd nb;
     __shared__ V4<T> cand[kScWords * kWave];         // tests: T positions, inf past the end
@@ -509,7 +555,12 @@ __global__ __launch_bounds__(64) SPH_DENSITY_OCCUPANCY void k_density(uint32_t n
     constexpr bool kExact = sizeof(T) == 8;          // FP64 runs: binary64 square root in the terms
     const uint32_t lane = threadIdx.x;
     const uint32_t ncq = *n_occupied;
-    if (blockIdx.x >= ncq) return;
+    if (blockIdx.x >= ncq) {
+        // the workgroups past the occupied cells: two spring rows each
+        const uint32_t sb = blockIdx.x - ncq;
+        if (sb < (sa.rows + 1u) / 2u) spring_rows<T>(sa, inv_perm, st, fspring, sb);
+        return;
+    }
     const uint32_t slot = cells[list_pos(blockIdx.x, ncq)];
     const uint32_t s0 = cstart[slot], e0 = cend[slot];
     if (s0 >= e0) return;
@@ -1128,11 +1179,14 @@ inline uint32_t cell_grid(uint32_t n, uint32_t nslots) { return std::max(1u, std
 template <typename T>
 void launch_density(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, const uint32_t *cstart,
                     const uint32_t *cend, V2<T> *dens, uint64_t *masks, uint32_t *err, unsigned long long *stats,
-                    const uint32_t *cells, const uint32_t *ncell)
+                    const uint32_t *cells, const uint32_t *ncell, const SpringArgs &sa, const uint32_t *inv_perm,
+                    V4<T> *fspring)
 {
     if (!n) return;
-    hipLaunchKernelGGL(k_density<T>, dim3(cell_grid(n, b.nslots)), dim3(64), 0, s, n, st, b, cstart, cend, dens,
-                       masks, err, stats, cells, ncell);
+    // the occupied cells first (at most cell_grid of them), then the spring rows
+    const uint32_t grid = cell_grid(n, b.nslots) + (sa.rows + 1u) / 2u;
+    hipLaunchKernelGGL(k_density<T>, dim3(grid), dim3(64), 0, s, n, st, b, cstart, cend, dens, masks, err, stats,
+                       cells, ncell, sa, inv_perm, fspring);
 }
 
 template <typename T>
@@ -1149,10 +1203,12 @@ void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, co
 
 template void launch_density<float>(hipStream_t, uint32_t, State<float>, const Batch<float> &, const uint32_t *,
                                     const uint32_t *, V2<float> *, uint64_t *, uint32_t *, unsigned long long *,
-                                    const uint32_t *, const uint32_t *);
+                                    const uint32_t *, const uint32_t *, const SpringArgs &, const uint32_t *,
+                                    V4<float> *);
 template void launch_density<double>(hipStream_t, uint32_t, State<double>, const Batch<double> &, const uint32_t *,
                                      const uint32_t *, V2<double> *, uint64_t *, uint32_t *, unsigned long long *,
-                                     const uint32_t *, const uint32_t *);
+                                     const uint32_t *, const uint32_t *, const SpringArgs &, const uint32_t *,
+                                     V4<double> *);
 template void launch_forces<float>(hipStream_t, uint32_t, State<float>, const Batch<float> &, const uint32_t *,
                                    const uint32_t *, const V2<float> *, const uint64_t *, const V4<float> *,
                                    V4<float> *, double *, uint32_t *, unsigned long long *, const uint32_t *,

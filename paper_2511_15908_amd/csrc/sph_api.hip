@@ -41,7 +41,7 @@ struct sph_ctx {
     sph_params prm{};
     int prec = 0;
     uint32_t n = 0, n_fluid = 0, n_soft = 0, n_bnd = 0;
-    uint32_t nb = 0, nk = 0, n_objects = 0, rows = 0, nsprings = 0, nblk_w = 0, K = 1;
+    uint32_t nb = 0, nk = 0, n_objects = 0, rows = 0, nsprings = 0, K = 1;
     std::vector<int32_t> kin_of_object;   // object -> kinematic index or -1
     std::vector<uint32_t> obj_scene;      // object -> scene of the batch
     std::vector<uint32_t> kin_objects;    // kinematic index -> object
@@ -79,8 +79,8 @@ struct sph_ctx {
     uint32_t *row_id = nullptr, *row_ptr = nullptr, *partner = nullptr;
     double *sprm = nullptr;
     uint32_t *slot_id = nullptr, *slot_obj = nullptr;
-    double *r_loc = nullptr, *poses = nullptr, *fbody = nullptr, *partials = nullptr, *props = nullptr;
-    uint32_t *blk_obj = nullptr, *blk_first = nullptr, *blk_count = nullptr, *obj_blk0 = nullptr;
+    double *r_loc = nullptr, *poses = nullptr, *fbody = nullptr, *props = nullptr;
+    uint32_t *obj_slot0 = nullptr;
     double *ring = nullptr;
     uint32_t *ring_count = nullptr;
     uint32_t *err = nullptr;
@@ -206,7 +206,7 @@ bool body_mass_props(const sph_scene *s, uint32_t o, double *m_out, double com[3
 }
 
 struct Plan {
-    uint32_t n, nb, nk, rows, nsp2, nblk_w, nslots, K, max_probes, nscenes, log_steps, track_steps;
+    uint32_t n, nb, nk, rows, nsp2, nslots, K, max_probes, nscenes, log_steps, track_steps;
     int prec;
 };
 
@@ -372,9 +372,7 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
             }
         }
     }
-    uint32_t nblk_w = 0;
     for (uint32_t o = 0; o < s->n_objects; ++o) {
-        if (s->object_kinematic[o]) nblk_w += (per_obj[o] + 255) / 256;
         if (s->object_kinematic[o] == 2) {
             double m = 0, com[3], I[9], Ii[9];
             if (!per_obj[o] || !body_mass_props(s, o, &m, com, I, Ii)) {
@@ -388,7 +386,6 @@ sph_status validate(const sph_params *p, const sph_scene *s, Plan &pl, std::stri
     pl.nk = nk;
     pl.rows = nsoft;
     pl.nsp2 = 2 * s->n_springs;
-    pl.nblk_w = nblk_w;
     pl.nslots = g.nslots;
     pl.K = p->smoothing_window;
     pl.prec = p->precision;
@@ -494,7 +491,6 @@ sph_status validate_batch(const sph_params *p, const sph_scene *sc, uint32_t ns,
         tot.nk += pk.nk;
         tot.rows += pk.rows;
         tot.nsp2 += pk.nsp2;
-        tot.nblk_w += pk.nblk_w;
         tot.max_probes = pk.max_probes;
     }
     if (n > (1u << 24) - 1u || slots > (1u << 30)) {
@@ -550,11 +546,7 @@ void carve(sph_ctx *c, const Plan &pl, char *base, size_t *total)
     c->slot_obj = cv.take<uint32_t>((size_t)pl.nb * 4);
     c->r_loc = cv.take<double>((size_t)pl.nb * 3 * 8);
     c->fbody = cv.take<double>((size_t)pl.nb * 3 * 8);
-    c->partials = cv.take<double>((size_t)pl.nblk_w * 6 * 8);
-    c->blk_obj = cv.take<uint32_t>((size_t)pl.nblk_w * 4);
-    c->blk_first = cv.take<uint32_t>((size_t)pl.nblk_w * 4);
-    c->blk_count = cv.take<uint32_t>((size_t)pl.nblk_w * 4);
-    c->obj_blk0 = cv.take<uint32_t>((size_t)(pl.nk + 1) * 4);
+    c->obj_slot0 = cv.take<uint32_t>((size_t)(pl.nk + 1) * 4);
     c->poses = cv.take<double>((size_t)pl.nk * 16 * 8);
     c->props = cv.take<double>((size_t)pl.nk * 24 * 8);
     c->ring = cv.take<double>((size_t)pl.nk * pl.K * 6 * 8);
@@ -593,12 +585,7 @@ BodyArgs body_args(sph_ctx *c)
     b.r_loc = c->r_loc;
     b.poses = c->poses;
     b.fbody = c->fbody;
-    b.partials = c->partials;
-    b.blk_obj = c->blk_obj;
-    b.blk_first = c->blk_first;
-    b.blk_count = c->blk_count;
-    b.obj_blk0 = c->obj_blk0;
-    b.nblk = c->nblk_w;
+    b.obj_slot0 = c->obj_slot0;
     b.nk = c->nk;
     b.ring = c->ring;
     b.ring_count = c->ring_count;
@@ -668,13 +655,11 @@ void one_step(sph_ctx *c)
     prof_mark(c, 0, false);
     neighbour_search<T>(c);
     const State<T> st = state<T>(c, c->cur);
-    prof_mark(c, 4, true);
-    SpringArgs sa{c->rows, c->row_id, c->row_ptr, c->partner, c->sprm};
-    launch_springs<T>(s, sa, c->inv_perm, st, (V4<T> *)c->fspring);
-    prof_mark(c, 4, false);
     prof_mark(c, 5, true);
+    // the density launch also computes the soft-body springs (phase "density")
+    const SpringArgs sa{c->rows, c->row_id, c->row_ptr, c->partner, c->sprm};
     launch_density<T>(s, c->n, st, batch<T>(c), c->cstart, c->cend, (V2<T> *)c->dens, c->masks, c->err, c->stat_rec,
-                      c->sort.cells, c->sort.ncell);
+                      c->sort.cells, c->sort.ncell, sa, c->inv_perm, (V4<T> *)c->fspring);
     prof_mark(c, 5, false);
     prof_mark(c, 6, true);
     launch_forces<T>(s, c->n, st, batch<T>(c), c->cstart, c->cend, (const V2<T> *)c->dens, c->masks,
@@ -688,11 +673,9 @@ void one_step(sph_ctx *c)
         launch_probe<T>(s, pa, st, batch<T>(c), c->cstart, c->cend);
     }
     prof_mark(c, 9, false);
-    prof_mark(c, 7, true);
-    launch_wrench(s, ba);
-    prof_mark(c, 7, false);
+    // integration and the body wrench share one launch (phase "integrate")
     prof_mark(c, 8, true);
-    launch_integrate<T>(s, c->n, st, (const V4<T> *)c->force, phys<T>(c), c->err);
+    launch_integrate<T>(s, c->n, st, (const V4<T> *)c->force, phys<T>(c), c->err, ba);
     prof_mark(c, 8, false);
     if (c->prof_left) {
         --c->prof_left;
@@ -764,7 +747,7 @@ sph_status upload(sph_ctx *c, const sph_scene *s)
         }
     }
     // kinematic bodies: slots ordered by kinematic index then particle id
-    std::vector<uint32_t> slot_id, slot_obj, blk_obj, blk_first, blk_count, obj_blk0;
+    std::vector<uint32_t> slot_id, slot_obj, obj_slot0;
     std::vector<double> r_loc, poses(16 * (size_t)c->nk, 0.0), props(24 * (size_t)c->nk, 0.0);
     std::vector<uint32_t> slot_of(n, 0);
     for (uint32_t k = 0; k < c->nk; ++k) {
@@ -787,8 +770,7 @@ sph_status upload(sph_ctx *c, const sph_scene *s)
         quat_to_R(q, R);
         for (int a = 0; a < 3; ++a) poses[16 * k + a] = pz[a];
         for (int a = 0; a < 4; ++a) poses[16 * k + 3 + a] = q[a];
-        obj_blk0.push_back((uint32_t)blk_obj.size());
-        const uint32_t first = (uint32_t)slot_id.size();
+        obj_slot0.push_back((uint32_t)slot_id.size());
         for (uint32_t i = 0; i < n; ++i) {
             if (s->type[i] != SPH_BOUNDARY || s->object[i] != (int32_t)o) continue;
             slot_of[i] = (uint32_t)slot_id.size();
@@ -797,14 +779,8 @@ sph_status upload(sph_ctx *c, const sph_scene *s)
             const double d[3] = {s->x[3 * i] - pz[0], s->x[3 * i + 1] - pz[1], s->x[3 * i + 2] - pz[2]};
             for (int a = 0; a < 3; ++a) r_loc.push_back(R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2]);
         }
-        const uint32_t cnt = (uint32_t)slot_id.size() - first;
-        for (uint32_t b0 = 0; b0 < cnt; b0 += 256) {
-            blk_obj.push_back(k);
-            blk_first.push_back(first + b0);
-            blk_count.push_back(std::min<uint32_t>(256, cnt - b0));
-        }
     }
-    obj_blk0.push_back((uint32_t)blk_obj.size());
+    obj_slot0.push_back((uint32_t)slot_id.size());
     for (uint32_t i = 0; i < n; ++i) {
         const uint8_t t = s->type[i];
         pos[i] = V4<T>{(T)s->x[3 * i], (T)s->x[3 * i + 1], (T)s->x[3 * i + 2],
@@ -838,10 +814,7 @@ sph_status upload(sph_ctx *c, const sph_scene *s)
     HIPCHK(c, H2D(c->slot_id, slot_id.data(), slot_id.size() * 4));
     HIPCHK(c, H2D(c->slot_obj, slot_obj.data(), slot_obj.size() * 4));
     HIPCHK(c, H2D(c->r_loc, r_loc.data(), r_loc.size() * 8));
-    HIPCHK(c, H2D(c->blk_obj, blk_obj.data(), blk_obj.size() * 4));
-    HIPCHK(c, H2D(c->blk_first, blk_first.data(), blk_first.size() * 4));
-    HIPCHK(c, H2D(c->blk_count, blk_count.data(), blk_count.size() * 4));
-    HIPCHK(c, H2D(c->obj_blk0, obj_blk0.data(), obj_blk0.size() * 4));
+    HIPCHK(c, H2D(c->obj_slot0, obj_slot0.data(), obj_slot0.size() * 4));
     HIPCHK(c, H2D(c->poses, poses.data(), poses.size() * 8));
     HIPCHK(c, H2D(c->props, props.data(), props.size() * 8));
     // zero what must start at zero (fill kernels, no memset nodes)
@@ -1012,7 +985,6 @@ sph_status sph_batch_init(const sph_params *params, const sph_scene *scenes, uin
     c->nk = pl.nk;
     c->rows = pl.rows;
     c->nsprings = scene->n_springs;
-    c->nblk_w = pl.nblk_w;
     c->K = pl.K;
     c->n_objects = scene->n_objects;
     c->max_probes = pl.max_probes;

@@ -296,10 +296,19 @@ void launch_psi_obj(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b, c
 // --- launchers (k_sums.hip) ---
 // The two neighbour passes run one workgroup per occupied cell (cells, the
 // list the cell table wrote, and its length *ncell).
+// Soft-body springs (CSR by soft particle), computed by the density launch.
+struct SpringArgs {
+    uint32_t rows;
+    const uint32_t *row_id;   // soft row -> particle id
+    const uint32_t *row_ptr;  // [rows+1]
+    const uint32_t *partner;  // [2 ns] partner particle id
+    const double *prm;        // [3 * 2 ns] L0, k, c per CSR entry
+};
 template <typename T>
 void launch_density(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b,
                     const uint32_t *cstart, const uint32_t *cend, V2<T> *dens, uint64_t *masks,
-                    uint32_t *err, unsigned long long *stats, const uint32_t *cells, const uint32_t *ncell);
+                    uint32_t *err, unsigned long long *stats, const uint32_t *cells, const uint32_t *ncell,
+                    const SpringArgs &sa, const uint32_t *inv_perm, V4<T> *fspring);
 template <typename T>
 void launch_forces(hipStream_t s, uint32_t n, State<T> st, const Batch<T> &b,
                    const uint32_t *cstart, const uint32_t *cend, const V2<T> *dens,
@@ -316,12 +325,8 @@ struct BodyArgs {
     const double *r_loc;       // [3 nb] body-frame offsets
     double *poses;             // [16 nk]: c[3], q[4], v[3], w[3], pad
     double *fbody;             // [3 nb]
-    double *partials;          // [6 nblk]
-    const uint32_t *blk_obj;   // [nblk] object of each reduction block
-    const uint32_t *blk_first; // [nblk] first slot of each reduction block
-    const uint32_t *blk_count; // [nblk]
-    const uint32_t *obj_blk0;  // [nk+1] first reduction block of each object
-    uint32_t nblk, nk;
+    const uint32_t *obj_slot0; // [nk+1] first body-particle slot of each kinematic object
+    uint32_t nk;
     double *ring;              // [nk][K][6]
     uint32_t *ring_count;      // [nk] samples pushed (monotone; reset by sph_reset_smoothing)
     uint32_t K;
@@ -338,7 +343,6 @@ struct BodyArgs {
 constexpr int kPropFree = 19;
 template <typename T>
 void launch_place(hipStream_t s, const BodyArgs &b, const uint32_t *inv_perm, State<T> st);
-void launch_wrench(hipStream_t s, const BodyArgs &b);
 void launch_set_pose(hipStream_t s, double *pose_slot, const double c[3], const double q[4],
                      const double v[3], const double w[3]);
 void launch_reset_ring(hipStream_t s, uint32_t *ring_count_slot);
@@ -360,18 +364,8 @@ template <typename T>
 void launch_probe(hipStream_t s, const ProbeArgs &a, State<T> st, const Batch<T> &b,
                   const uint32_t *cstart, const uint32_t *cend);
 
-struct SpringArgs {
-    uint32_t rows;
-    const uint32_t *row_id;   // soft row -> particle id
-    const uint32_t *row_ptr;  // [rows+1]
-    const uint32_t *partner;  // [2 ns] partner particle id
-    const double *prm;        // [3 * 2 ns] L0, k, c per CSR entry
-};
-template <typename T>
-void launch_springs(hipStream_t s, const SpringArgs &a, const uint32_t *inv_perm, State<T> st,
-                    V4<T> *fspring);
 template <typename T>
 void launch_integrate(hipStream_t s, uint32_t n, State<T> st, const V4<T> *force, const Phys<T> &ph,
-                      uint32_t *err);
+                      uint32_t *err, const BodyArgs &b);
 
 }  // namespace sphk
