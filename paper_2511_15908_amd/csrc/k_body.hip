@@ -291,6 +291,8 @@ __device__ __forceinline__ void wrench_obj(const BodyArgs &b, uint32_t o)
     double R[9];
     quat_R(b.poses + 16u * o + 3, R);
     double v[6] = {0, 0, 0, 0, 0, 0};
+    // unrolled: the loads of four particles are in flight together
+#pragma unroll 4
     for (uint32_t s = b.obj_slot0[o] + t; s < b.obj_slot0[o + 1]; s += 256u) {
         const double r0 = b.r_loc[3 * s], r1 = b.r_loc[3 * s + 1], r2 = b.r_loc[3 * s + 2];
         double rw[3];
