@@ -125,3 +125,29 @@ def test_buoyancy_sign(gpu, density, sign):
     c, q, v, w = sim.body_state(1)
     print(f"density {density}: v_z after 0.05 s = {v[2]:.4f} m/s")
     assert sign * v[2] > 0.02
+
+
+def test_kinematic_body_without_particles(gpu, orc):
+    """A kinematic object that owns no particles still gets its step: a zero
+    wrench sample and the pose advanced by its velocities (the oracle's pose
+    advance, step by step), next to a scene whose other bodies interact."""
+    from paper_2511_15908_amd import scenes
+    sc = scenes.small_scene(seed=21)
+    empty = int(sc.object_kinematic.shape[0])
+    sc.object_kinematic = np.append(sc.object_kinematic, np.uint8(1))
+    sc.object_pose0 = np.vstack([sc.object_pose0, [0.1, 0.2, 0.05, 1.0, 0.0, 0.0, 0.0]])
+    sim = gpu.Sim(sc)
+    c, q = np.array([0.1, 0.2, 0.05]), np.array([0.9, 0.1, -0.2, 0.3])
+    v, w = np.array([0.3, -0.1, 0.2]), np.array([1.5, -0.5, 2.0])
+    sim.set_body_pose(empty, c, q, v, w)
+    q = q / np.linalg.norm(q)
+    dt = sc.params["dt"]
+    for _ in range(10):
+        sim.step(1)
+        c, q = orc.pose_advance(c, q, v, w, dt)
+    F, T = sim.wrench(empty)
+    assert np.all(np.asarray(F) == 0.0) and np.all(np.asarray(T) == 0.0)
+    cg, qg, vg, wg = sim.body_state(empty)
+    assert np.allclose(cg, c, rtol=0, atol=1e-14)
+    assert np.allclose(qg, q, rtol=0, atol=1e-14)
+    assert np.array_equal(vg, v) and np.array_equal(wg, w)
