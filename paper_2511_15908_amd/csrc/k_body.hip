@@ -4,11 +4,11 @@
 //    (Sec. 3.3, Fig. 1);
 //  - body wrench: the particles' point forces summed into the parent's force
 //    and torque (Sec. 3.2, Alg. 2: the rigid-force step), reduced in
-//    binary64 with a fixed wavefront-shuffle tree (deterministic), pushed into
-//    the rolling-average ring of Sec. 3.3;
-//  - soft bodies: mass-spring forces through a spring lookup table (Sec. 3.2,
-//    Alg. 2: the spring-force step);
+//    binary64 by one block per body in a fixed order (deterministic), pushed
+//    into the rolling-average ring of Sec. 3.3; it runs in the integration
+//    launch;
 //  - semi-implicit Euler (Eq. euler) for fluid and soft particles.
+// (The soft bodies' spring forces run in the density launch, k_sums.hip.)
 #include "sph_internal.h"
 
 namespace sphk {
