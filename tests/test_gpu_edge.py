@@ -98,6 +98,23 @@ def test_overfull_cell(gpu, orc, prec):
     _compare_one_step(gpu, orc, sc, prec, *tol)
 
 
+@pytest.mark.parametrize("n", [64, 65, 72, 73, 128, 136, 137])
+def test_cell_pass_structure(gpu, orc, n):
+    """One grid cell of n particles, every fifth a static boundary particle:
+    whole passes of 64 (64, 128), a remainder of up to 8 served in transposed
+    mode inside the last pass (65, 72, 136), one past that (73, 137: a second,
+    split pass).  Neighbour sets bit-exact, density and forces against the
+    oracle."""
+    from paper_2511_15908_amd import scenes
+    rng = scenes.SplitMix64(31 + n, 9)
+    x = (rng.uniform(3 * n).reshape(n, 3) - 0.5) * 0.03 - 0.02     # inside the cell [-0.04, 0.0002)^3
+    v = (rng.uniform(3 * n).reshape(n, 3) - 0.5) * 0.2
+    types = np.where(np.arange(n) % 5 == 4, 2, 0).astype(np.uint8)
+    v[types == 2] = 0.0
+    sc = _scene(x, v, types=types, objects=np.where(types == 2, 0, -1))
+    _compare_one_step(gpu, orc, sc, "f32", 1e-5, 1e-4)
+
+
 def test_crowded_cell_beyond_reorder_staging(gpu, orc):
     """2,500 particles in one grid cell: the reorder ranks them against their
     cell slice in global memory (the slice does not fit its LDS staging) and
