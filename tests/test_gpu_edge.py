@@ -21,7 +21,7 @@ def gpu():
 
 
 def _scene(x, v=None, types=None, mass=1e-3, h=0.02, precision="f32", lo=(-0.2,) * 3, hi=(0.2,) * 3,
-           gravity=(0.0, 0.0, -9.81), objects=None):
+           gravity=(0.0, 0.0, -9.81), objects=None, kinematic=False):
     from paper_2511_15908_amd import scenes
     x = np.asarray(x, np.float64).reshape(-1, 3)
     n = x.shape[0]
@@ -31,7 +31,7 @@ def _scene(x, v=None, types=None, mass=1e-3, h=0.02, precision="f32", lo=(-0.2,)
     if objects is not None:
         obj = np.asarray(objects, np.int32)
         no = int(obj.max()) + 1 if n else 0
-        kin = [0] * no
+        kin = [1 if kinematic else 0] * no
         poses = [[0, 0, 0, 1, 0, 0, 0]] * no
     params = scenes._params(h, 1e-4, lo, hi, precision)
     params["gravity"] = gravity
@@ -113,6 +113,26 @@ def test_cell_pass_structure(gpu, orc, n):
     v[types == 2] = 0.0
     sc = _scene(x, v, types=types, objects=np.where(types == 2, 0, -1))
     _compare_one_step(gpu, orc, sc, "f32", 1e-5, 1e-4)
+
+
+@pytest.mark.parametrize("n", [72, 73, 136])
+def test_cell_pass_structure_kinematic(gpu, orc, n):
+    """As above with every fifth particle a kinematic body particle (a target
+    of the force pass, also among the leftovers): the body particles'
+    reactions and the body wrench against the oracle."""
+    from paper_2511_15908_amd import scenes
+    rng = scenes.SplitMix64(41 + n, 9)
+    x = (rng.uniform(3 * n).reshape(n, 3) - 0.5) * 0.03 - 0.02
+    types = np.where(np.arange(n) % 5 == 4, 2, 0).astype(np.uint8)
+    sc = _scene(x, types=types, objects=np.where(types == 2, 0, -1), kinematic=True)
+    sim = _compare_one_step(gpu, orc, sc, "f32", 1e-5, 1e-4)
+    o = orc.Oracle(sc, "f32")
+    r = o.step()
+    b = np.nonzero(types == 2)[0]
+    mref = float(np.median(sc.mass[types != 2]))
+    assert _cmp.rel_force(sim.read("f")[b], r["f"][b], mref * 9.81) <= 1e-4
+    F, T = sim.wrench(0)
+    assert _cmp.rel_vec(F, r["wrench"][0][0], mref * 9.81 * b.size) <= 1e-4
 
 
 def test_crowded_cell_beyond_reorder_staging(gpu, orc):
