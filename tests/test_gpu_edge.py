@@ -135,6 +135,25 @@ def test_cell_pass_structure_kinematic(gpu, orc, n):
     assert _cmp.rel_vec(F, r["wrench"][0][0], mref * 9.81 * b.size) <= 1e-4
 
 
+@pytest.mark.parametrize("n", [72, 73])
+def test_cell_pass_structure_unified(gpu, orc, n):
+    """The unified boundary reading (flag 8) in a cell whose boundary particles
+    are density targets too: the density pass then serves more targets per
+    pass than the force pass.  Boundary densities against the oracle."""
+    from paper_2511_15908_amd import scenes
+    rng = scenes.SplitMix64(51 + n, 9)
+    x = (rng.uniform(3 * n).reshape(n, 3) - 0.5) * 0.03 - 0.02
+    types = np.where(np.arange(n) % 3 == 2, 2, 0).astype(np.uint8)
+    sc = _scene(x, types=types, objects=np.where(types == 2, 0, -1))
+    sc.params["flags"] = 8
+    _compare_one_step(gpu, orc, sc, "f32", 1e-5, 1e-4)
+    sim = gpu.Sim(sc)
+    sim.step(1)
+    r = orc.Oracle(sc, "f32").step()
+    b = np.nonzero(types == 2)[0]
+    assert _cmp.rel_density(sim.read("rho")[b], r["rho"][b]) <= 1e-5
+
+
 def test_crowded_cell_beyond_reorder_staging(gpu, orc):
     """2,500 particles in one grid cell: the reorder ranks them against their
     cell slice in global memory (the slice does not fit its LDS staging) and
