@@ -22,6 +22,8 @@
 //  - Force pass: restages the same super-chunks (position, velocity,
 //    density) and walks the stored masks, so no pair is tested twice; FP32
 //    terms summed per super-chunk, then in FP64.
+// The density launch's workgroups past the occupied cells compute the
+// soft-body spring forces (two CSR rows each), which the force pass adds.
 // No atomics in the sums, so results are bitwise reproducible.
 #include <algorithm>
 
