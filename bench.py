@@ -117,8 +117,8 @@ def cpu_baseline(scene, log_fn=None):
     """The oracle as it stands, timed on the host cores: whole FP64 oracle
     steps (neighbour lists, density, forces, springs, wrench, integration).
     value: 3 steps of the benchmark scene on all cores; beside it one step on
-    one core, and the FP64 dam break in full (100 steps) on all cores and for
-    10 steps on one core."""
+    one core, the FP64 dam break in full (100 steps) on all cores and for
+    10 steps on one core, and 3 steps of the 250k stirring tank on all cores."""
     import oracle
     from paper_2511_15908_amd import scenes
     oracle.build(force=False)
@@ -137,6 +137,8 @@ def cpu_baseline(scene, log_fn=None):
     _omp(1)
     dam_one = _time_oracle(dam, 10)
     _omp(cores)
+    say("cpu baseline: stirring tank (250k fluid, FP32 state), 3 steps on all threads")
+    stir = _time_oracle(scenes.stirring_tank(), 3)
     return {"value": allc["particle_updates_per_s"], "unit": "particle-updates/s", "cores": cores,
             "kind": "oracle", "cpu_model": _cpu_model(),
             "sample": f"3 full FP64 oracle steps of the same {scene.n:,}-particle scene "
@@ -148,7 +150,10 @@ def cpu_baseline(scene, log_fn=None):
                                "all_threads": {"value": dam_all["particle_updates_per_s"], "steps": 100,
                                                "s_per_step": round(dam_all["s_per_step"], 4)},
                                "one_thread": {"value": dam_one["particle_updates_per_s"], "steps": 10,
-                                              "s_per_step": round(dam_one["s_per_step"], 4)}}}
+                                              "s_per_step": round(dam_one["s_per_step"], 4)}},
+            "stirring_250k": {"n_particles": stir["n_particles"],
+                              "all_threads": {"value": stir["particle_updates_per_s"], "steps": 3,
+                                              "s_per_step": round(stir["s_per_step"], 3)}}}
 
 
 def profiled_traffic(kernel, n_particles):
