@@ -98,8 +98,9 @@ def test_overfull_cell(gpu, orc, prec):
     _compare_one_step(gpu, orc, sc, prec, *tol)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("n", [64, 65, 72, 73, 128, 136, 137])
-def test_cell_pass_structure(gpu, orc, n):
+def test_cell_pass_structure(gpu, orc, n, prec):
     """One grid cell of n particles, every fifth a static boundary particle:
     whole passes of 64 (64, 128), a remainder of up to 8 served in transposed
     mode inside the last pass (65, 72, 136), one past that (73, 137: a second,
@@ -111,8 +112,9 @@ def test_cell_pass_structure(gpu, orc, n):
     v = (rng.uniform(3 * n).reshape(n, 3) - 0.5) * 0.2
     types = np.where(np.arange(n) % 5 == 4, 2, 0).astype(np.uint8)
     v[types == 2] = 0.0
-    sc = _scene(x, v, types=types, objects=np.where(types == 2, 0, -1))
-    _compare_one_step(gpu, orc, sc, "f32", 1e-5, 1e-4)
+    sc = _scene(x, v, types=types, objects=np.where(types == 2, 0, -1), precision=prec)
+    tol = (1e-5, 1e-4) if prec == "f32" else (1e-13, 1e-12)
+    _compare_one_step(gpu, orc, sc, prec, *tol)
 
 
 @pytest.mark.parametrize("n", [72, 73, 136])
