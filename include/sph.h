@@ -352,8 +352,9 @@ sph_status sph_synchronize(sph_ctx *ctx);
  * eagerly, not as graph replays.  sph_profile_read synchronises and writes,
  * for each phase id 0..n_phases-1 (see sph_profile_phase_name), the summed
  * milliseconds and launch count over the steps that recorded events.  The
- * springs run inside the density launch and the body wrench inside the
- * integration launch, so their phases ("springs", "wrench") read 0.
+ * body placement runs inside the key launch, the springs inside the density
+ * launch and the body wrench inside the integration launch, so their phases
+ * ("place", "springs", "wrench") read 0.
  */
 sph_status sph_profile_begin(sph_ctx *ctx, uint32_t max_steps);
 sph_status sph_profile_begin_sampled(sph_ctx *ctx, uint32_t max_steps, uint32_t every);

@@ -1,7 +1,7 @@
-// Rigid and soft bodies and the integrator of one SPH step (arXiv 2511.15908):
-//  - kinematic (grabbed) bodies: particles keep constant offsets from the
-//    parent transform (Sec. 3.2); the pose comes from the haptic device
-//    (Sec. 3.3, Fig. 1);
+// Rigid bodies and the integrator of one SPH step (arXiv 2511.15908):
+//  - kinematic (grabbed) bodies: the pose comes from the haptic device
+//    (Sec. 3.3, Fig. 1); their particles keep constant offsets from it
+//    (Sec. 3.2) and are placed by the key launch (place_body_particle);
 //  - body wrench: the particles' point forces summed into the parent's force
 //    and torque (Sec. 3.2, Alg. 2: the rigid-force step), reduced in
 //    binary64 by one block per body in a fixed order (deterministic), pushed
@@ -13,56 +13,6 @@
 
 namespace sphk {
 
-__device__ __forceinline__ void quat_R(const double *q, double R[9])
-{
-#pragma clang fp contract(off)
-    const double w = q[0], x = q[1], y = q[2], z = q[3];
-    R[0] = 1.0 - 2.0 * (y * y + z * z);
-    R[1] = 2.0 * (x * y - w * z);
-    R[2] = 2.0 * (x * z + w * y);
-    R[3] = 2.0 * (x * y + w * z);
-    R[4] = 1.0 - 2.0 * (x * x + z * z);
-    R[5] = 2.0 * (y * z - w * x);
-    R[6] = 2.0 * (x * z - w * y);
-    R[7] = 2.0 * (y * z + w * x);
-    R[8] = 1.0 - 2.0 * (x * x + y * y);
-}
-
-// ------------------------------------------------------------------ placement
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_place(BodyArgs b, const uint32_t *__restrict__ inv_perm, State<T> st)
-{
-#pragma clang fp contract(off)
-    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
-    if (s >= b.nb) return;
-    const double *pose = b.poses + 16u * b.slot_obj[s];
-    double R[9];
-    quat_R(pose + 3, R);
-    const double r0 = b.r_loc[3 * s], r1 = b.r_loc[3 * s + 1], r2 = b.r_loc[3 * s + 2];
-    double rw[3];
-    for (int a = 0; a < 3; ++a) rw[a] = R[3 * a] * r0 + R[3 * a + 1] * r1 + R[3 * a + 2] * r2;
-    const double *w = pose + 10;
-    const double vx = pose[7] + (w[1] * rw[2] - w[2] * rw[1]);
-    const double vy = pose[8] + (w[2] * rw[0] - w[0] * rw[2]);
-    const double vz = pose[9] + (w[0] * rw[1] - w[1] * rw[0]);
-    const uint32_t p = inv_perm[b.slot_id[s]];
-    V4<T> x = st.pos[p];
-    x.x = (T)(pose[0] + rw[0]);
-    x.y = (T)(pose[1] + rw[1]);
-    x.z = (T)(pose[2] + rw[2]);
-    st.pos[p] = x;
-    st.vel[p] = V4<T>{(T)vx, (T)vy, (T)vz, (T)0};
-}
-
-template <typename T>
-void launch_place(hipStream_t s, const BodyArgs &b, const uint32_t *inv_perm, State<T> st)
-{
-    if (!b.nb) return;
-    hipLaunchKernelGGL(k_place<T>, dim3((b.nb + 255) / 256), dim3(256), 0, s, b, inv_perm, st);
-}
-template void launch_place<float>(hipStream_t, const BodyArgs &, const uint32_t *, State<float>);
-template void launch_place<double>(hipStream_t, const BodyArgs &, const uint32_t *, State<double>);
 
 // ------------------------------------------------------------------ wrench
 

@@ -20,8 +20,10 @@ namespace sphk {
 // among the particles of its key.  Lanes of a wavefront hold consecutive
 // particles; each run of equal keys takes one atomic for its length, and
 // its lanes number themselves from the returned base.
+// Kinematic body particles are placed here first (the body's pose of this
+// step, Sec. 3.2), so that their keys use the placed positions.
 template <typename T>
-__global__ __launch_bounds__(256) void k_keys(uint32_t n, const V4<T> *__restrict__ pos, Batch<T> b,
+__global__ __launch_bounds__(256) void k_keys(uint32_t n, State<T> st, Batch<T> b, BodyArgs ba,
                                               uint32_t *__restrict__ keys, uint32_t *__restrict__ rank,
                                               uint32_t *__restrict__ counts)
 {
@@ -33,7 +35,14 @@ __global__ __launch_bounds__(256) void k_keys(uint32_t n, const V4<T> *__restric
         const Grid g = b.sc[scene_of_particle(b, i)].g;
         T lo[3], inv;
         grid_lo_inv<T>(g, lo, inv);
-        const V4<T> p = pos[i];
+        V4<T> p = st.pos[i];
+        const uint32_t aux = st.aux[i];
+        if (aux_type(aux) == TY_BOUNDARY && aux_kin(aux)) {
+            V4<T> v;
+            place_body_particle<T>(ba, aux_index(aux), p, v);
+            st.pos[i] = p;
+            st.vel[i] = v;
+        }
         const int cx = cell_coord<T>(p.x, lo[0], inv, g.dims[0]);
         const int cy = cell_coord<T>(p.y, lo[1], inv, g.dims[1]);
         const int cz = cell_coord<T>(p.z, lo[2], inv, g.dims[2]);
@@ -56,13 +65,16 @@ __global__ __launch_bounds__(256) void k_keys(uint32_t n, const V4<T> *__restric
 }
 
 template <typename T>
-void launch_keys(hipStream_t s, uint32_t n, const V4<T> *pos, const Batch<T> &b, Sort &st)
+void launch_keys(hipStream_t s, uint32_t n, State<T> state, const Batch<T> &b, const BodyArgs &ba, Sort &st)
 {
     if (!n) return;
-    hipLaunchKernelGGL(k_keys<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, b, st.keys, st.rank, st.counts);
+    hipLaunchKernelGGL(k_keys<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, state, b, ba, st.keys, st.rank,
+                       st.counts);
 }
-template void launch_keys<float>(hipStream_t, uint32_t, const V4<float> *, const Batch<float> &, Sort &);
-template void launch_keys<double>(hipStream_t, uint32_t, const V4<double> *, const Batch<double> &, Sort &);
+template void launch_keys<float>(hipStream_t, uint32_t, State<float>, const Batch<float> &, const BodyArgs &,
+                                 Sort &);
+template void launch_keys<double>(hipStream_t, uint32_t, State<double>, const Batch<double> &, const BodyArgs &,
+                                  Sort &);
 
 // ---------------------------------------------------------------- cell table
 // Exclusive scan of the per-slot counts: cstart[s] = particles in slots

@@ -624,7 +624,7 @@ void neighbour_search(sph_ctx *c)
 {
     const uint32_t n = c->n;
     prof_mark(c, 1, true);
-    launch_keys<T>(c->stream, n, (const V4<T> *)c->pos[c->cur], batch<T>(c), c->sort);
+    launch_keys<T>(c->stream, n, state<T>(c, c->cur), batch<T>(c), body_args(c), c->sort);
     prof_mark(c, 1, false);
     prof_mark(c, 2, true);
     launch_cell_table(c->stream, c->nslots, c->sort, c->cstart, c->cend);
@@ -650,9 +650,7 @@ void one_step(sph_ctx *c)
     hipStream_t s = c->stream;
     const BodyArgs ba = body_args(c);
     c->prof_now = c->prof_left && c->prof_idx % c->prof_every == 0u;
-    prof_mark(c, 0, true);
-    launch_place<T>(s, ba, c->inv_perm, state<T>(c, c->cur));
-    prof_mark(c, 0, false);
+    // the kinematic bodies' particles are placed by the key launch (phase "keys")
     neighbour_search<T>(c);
     const State<T> st = state<T>(c, c->cur);
     prof_mark(c, 5, true);

@@ -280,8 +280,9 @@ __device__ __forceinline__ uint32_t scene_of_slot(const Batch<T> &b, uint32_t k)
 }
 
 // --- launchers (k_grid.hip) ---
+struct BodyArgs;
 template <typename T>
-void launch_keys(hipStream_t s, uint32_t n, const V4<T> *pos, const Batch<T> &b, Sort &st);
+void launch_keys(hipStream_t s, uint32_t n, State<T> state, const Batch<T> &b, const BodyArgs &ba, Sort &st);
 uint32_t cell_scan_tiles(uint32_t nslots);
 void launch_cell_table(hipStream_t s, uint32_t nslots, Sort &st, uint32_t *cstart, uint32_t *cend);
 void launch_cell_scatter(hipStream_t s, uint32_t n, Sort &st, const uint32_t *cstart);
@@ -341,8 +342,46 @@ struct BodyArgs {
     uint32_t track_cap;
 };
 constexpr int kPropFree = 19;
+
+// Rotation matrix of a unit quaternion (w, x, y, z), row-major.
+__device__ __forceinline__ void quat_R(const double *q, double R[9])
+{
+#pragma clang fp contract(off)
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Placement of kinematic body particle slot s (Sec. 3.2: rigid particles
+// keep constant offsets from the parent transform): x = c + R r_loc,
+// v = v_c + w x (R r_loc), in binary64, rounded to the run precision; x.w
+// (-psi) is kept.
 template <typename T>
-void launch_place(hipStream_t s, const BodyArgs &b, const uint32_t *inv_perm, State<T> st);
+__device__ __forceinline__ void place_body_particle(const BodyArgs &b, uint32_t s, V4<T> &x, V4<T> &v)
+{
+#pragma clang fp contract(off)
+    const double *pose = b.poses + 16u * b.slot_obj[s];
+    double R[9];
+    quat_R(pose + 3, R);
+    const double r0 = b.r_loc[3 * s], r1 = b.r_loc[3 * s + 1], r2 = b.r_loc[3 * s + 2];
+    double rw[3];
+    for (int a = 0; a < 3; ++a) rw[a] = R[3 * a] * r0 + R[3 * a + 1] * r1 + R[3 * a + 2] * r2;
+    const double *w = pose + 10;
+    const double vx = pose[7] + (w[1] * rw[2] - w[2] * rw[1]);
+    const double vy = pose[8] + (w[2] * rw[0] - w[0] * rw[2]);
+    const double vz = pose[9] + (w[0] * rw[1] - w[1] * rw[0]);
+    x.x = (T)(pose[0] + rw[0]);
+    x.y = (T)(pose[1] + rw[1]);
+    x.z = (T)(pose[2] + rw[2]);
+    v = V4<T>{(T)vx, (T)vy, (T)vz, (T)0};
+}
 void launch_set_pose(hipStream_t s, double *pose_slot, const double c[3], const double q[4],
                      const double v[3], const double w[3]);
 void launch_reset_ring(hipStream_t s, uint32_t *ring_count_slot);
