@@ -44,13 +44,14 @@ LANE_OPS_FORCE_PAIR = 45
 FLOP_DENSITY_PAIR = 17
 FLOP_FORCE_PAIR = 49
 # Compulsory HBM bytes per particle of the memory-bound phases (FP32 SoA,
-# unfused): keys 12 + key 4 + arrival rank 4; counting sort: scatter 8 + 4
+# unfused): keys 12 + type word 4 (the key launch also places the kinematic
+# bodies' particles) + key 4 + arrival rank 4; counting sort: scatter 8 + 4
 # (the slot scan adds 16 B per slot, under 1 B per particle at 1M);
 # reorder arrived 4 + key 4 + 32 + 32 + inverse 4 + cell bounds 6;
 # integrate 40 + 24.  The whole step, neighbour sums included (their
-# compulsory traffic: 24 and 48), is 250 bytes per particle.
-HBM_BYTES_PER_PARTICLE = {"keys": 20, "sort": 12, "reorder": 82, "integrate": 64}
-HBM_BYTES_STEP_PER_PARTICLE = 250
+# compulsory traffic: 24 and 48), is 254 bytes per particle.
+HBM_BYTES_PER_PARTICLE = {"keys": 24, "sort": 12, "reorder": 82, "integrate": 64}
+HBM_BYTES_STEP_PER_PARTICLE = 254
 # Kernel times come from HIP events on every PROFILE_EVERY-th timed step
 # (the event records cost a few microseconds each, two per phase).
 PROFILE_EVERY = 4
